@@ -1,0 +1,318 @@
+"""FP64 CPU oracle for overlap-save coherent dedispersion, detection,
+decimation and folding of complex baseband voltages -- the pulsar mode
+("PCD") of PONDER, Naidu, Joshi, Manoharan & Krishnakumar,
+"PONDER - A real time software backend for pulsar and IPS observations at
+the Ooty Radio Telescope", arXiv:1503.01405.
+
+THIS IS TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.  Only the tests, the
+package smoke check and the CPU-baseline leg of the benchmark may import it.
+The GPU library neither imports nor links anything from here, and nothing
+here imports the GPU library.
+
+Everything is plain numpy/scipy in float64/complex128, written step by step
+in the order the paper describes the method (Sec. 3.7 and Fig. 6: spectrum,
+multiply by the inverse ISM response of Eq. (4), inverse transform, series,
+fold).  The paper leaves several points open; the readings taken here are:
+
+  C1  dispersion constant: 1/2.41e-4 s MHz^2 per unit DM (the constant of
+      Eq. (1)); the chirp phase is DM f^2 / (2.41e-10 f0^2 (f0+f)) turns
+      with f, f0 in MHz.  Eq. (4) as printed (8.3e3 pi) is short of the
+      1e6 that turns MHz into Hz.
+  C2  sign: numpy's forward transform is exp(-2 pi i k n / N); upper-side
+      baseband (baseband f is sky f0 + f).  The ISM response is
+      exp(+2 pi i turns) and dedispersion multiplies by its inverse
+      exp(-2 pi i turns).
+  C3  outputs are referred to arrival at f0.  Per block the first
+      n_front = ceil(delta_hi fs) samples and the last discard - n_front
+      samples are dropped, with s = ceil(delta_hi fs) + ceil(delta_lo fs)
+      and discard = next_pow2(max(s, 16)) if that is <= N/2, otherwise s
+      rounded up to a multiple of 16 (discard = 0 when s = 0).
+  C4  taper: unit (the paper does not say which taper it uses).
+  C5  bin k = N/2 is the frequency -bw/2 (numpy fftfreq).
+  C6  forward transform unnormalised, inverse with 1/N.
+  C7  detection is |y|^2 with no baseline or bandpass correction.
+  C8  the time series is the SUM of `decim` consecutive powers.
+  C9  fold phase: output m is input sample m + n_front; with
+      inv_pfs = 1 / (period_s * fs_hz),  x = (m + n_front) * inv_pfs,
+      bin = min(floor((x - floor(x)) * nbins), nbins - 1), all in float64.
+  C10 profile value = mean power per bin (sum / count, 0 for an empty bin).
+  C11 sub-integration s holds outputs m in [s*S, (s+1)*S).
+  C12 Eq. (1) read as N_min = 2 * smear / ts.
+  C16 only fully covered blocks produce outputs.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.fft as sfft
+
+# C1: the dispersion constant of Eq. (1), in s MHz^2 cm^3 / pc.
+DM_CONST_S = 1.0 / 2.41e-4
+# The same constant with f in MHz and the result in turns (1e6 cycles per s*MHz).
+DM_CONST_TURNS = 1.0 / 2.41e-10
+
+
+# --------------------------------------------------------------------------
+# Dispersion delays and the paper's design equations
+# --------------------------------------------------------------------------
+def dispersion_delay_s(f_mhz, f_ref_mhz, dm):
+    """Cold-plasma delay of frequency f relative to f_ref, in seconds.
+
+    Same form as Eq. (3) of Sec. 3.4 (4.15e6 (f_ref^-2 - f^-2) DM ms) with
+    the sign chosen so that lower frequencies arrive later (positive delay).
+    """
+    f = np.asarray(f_mhz, dtype=np.float64)
+    return DM_CONST_S * dm * (1.0 / (f * f) - 1.0 / (f_ref_mhz * f_ref_mhz))
+
+
+def residual_smear_ms(df_ch_mhz, f_ch_mhz, dm):
+    """Eq. (2), Sec. 3.4: dispersion smear inside one channel, in ms."""
+    return 8.3e6 * df_ch_mhz * dm / f_ch_mhz ** 3
+
+
+def fft_length_eq1(f_hi_mhz, df_mhz, dm, ts_s):
+    """Eq. (1), Sec. 3.2, read as N = 2 * smear / ts (reading C12).
+
+    The printed equation puts the 2 on each frequency term; the reading
+    multiplies the full band smear (f_h - df)^-2 - f_h^-2 by 2 DM /
+    (2.41e-4 ts).
+    """
+    smear = (1.0 / (f_hi_mhz - df_mhz) ** 2 - 1.0 / f_hi_mhz ** 2) * dm / 2.41e-4
+    return 2.0 * smear / ts_s
+
+
+# --------------------------------------------------------------------------
+# Plan geometry (reading C3)
+# --------------------------------------------------------------------------
+def plan_geometry(f0_mhz, bw_mhz, dm, nfft):
+    """Sample rate, smear and overlap-save discard/hop for one plan.
+
+    Sec. 3.7: the filter must be longer than the dispersion smear and the
+    cyclic edges of the FFT convolution must be dropped.  Returns a dict;
+    raises ValueError where no output would be produced.
+    """
+    if nfft <= 0 or nfft & (nfft - 1):
+        raise ValueError("nfft must be a power of two")
+    if not (bw_mhz > 0 and f0_mhz - bw_mhz / 2 > 0 and dm >= 0):
+        raise ValueError("need bw > 0, f0 - bw/2 > 0 and dm >= 0")
+    fs = bw_mhz * 1e6
+    f_lo = f0_mhz - bw_mhz / 2
+    f_hi = f0_mhz + bw_mhz / 2
+    delta_lo = DM_CONST_S * dm * (1.0 / (f_lo * f_lo) - 1.0 / (f0_mhz * f0_mhz))
+    delta_hi = DM_CONST_S * dm * (1.0 / (f0_mhz * f0_mhz) - 1.0 / (f_hi * f_hi))
+    n_front = int(math.ceil(delta_hi * fs))
+    n_back_min = int(math.ceil(delta_lo * fs))
+    s = n_front + n_back_min
+    if s == 0:
+        discard = 0
+    else:
+        p2 = 1 << max(4, (s - 1).bit_length())
+        discard = p2 if p2 <= nfft // 2 else ((s + 15) // 16) * 16
+    hop = nfft - discard
+    if hop <= 0:
+        raise ValueError("nfft too short for the dispersion smear")
+    return dict(fs=fs, delta_lo=delta_lo, delta_hi=delta_hi,
+                smear_samples=s, n_front=n_front, discard=discard, hop=hop,
+                nfft=nfft)
+
+
+def n_blocks(nsamp, nfft, hop):
+    """Number of overlap-save blocks fully covered by nsamp samples (C16)."""
+    if nsamp < nfft:
+        return 0
+    return (nsamp - nfft) // hop + 1
+
+
+# --------------------------------------------------------------------------
+# The chirp of Eq. (4)
+# --------------------------------------------------------------------------
+def baseband_freqs_mhz(nfft, bw_mhz):
+    """Baseband frequency of each FFT bin in MHz (reading C5)."""
+    return sfft.fftfreq(nfft, d=1.0 / bw_mhz)
+
+
+def chirp_turns(f_mhz, f0_mhz, dm):
+    """Phase of the ISM response H(f0 + f) of Eq. (4), in turns (reading C1)."""
+    f = np.asarray(f_mhz, dtype=np.float64)
+    return dm * f * f / (2.41e-10 * f0_mhz * f0_mhz * (f0_mhz + f))
+
+
+def ism_response(nfft, f0_mhz, bw_mhz, dm):
+    """H sampled on the FFT grid: exp(+2 pi i turns) (reading C2)."""
+    return np.exp(2j * np.pi * chirp_turns(baseband_freqs_mhz(nfft, bw_mhz), f0_mhz, dm))
+
+
+def dedispersion_chirp(nfft, f0_mhz, bw_mhz, dm):
+    """H^-1 on the FFT grid, exp(-2 pi i turns): the multiplier of Sec. 3.7."""
+    return np.exp(-2j * np.pi * chirp_turns(baseband_freqs_mhz(nfft, bw_mhz), f0_mhz, dm))
+
+
+# --------------------------------------------------------------------------
+# The method, step by step
+# --------------------------------------------------------------------------
+def unpack(iq):
+    """Interleaved int8 I/Q -> complex128 x = I + iQ, no offset, no scale."""
+    iq = np.asarray(iq)
+    x = np.empty(iq.size // 2, dtype=np.complex128)
+    x.real = iq[0::2]
+    x.imag = iq[1::2]
+    return x
+
+
+def dedisperse_block(x_block, chirp, n_front, hop, workers=None):
+    """One overlap-save block: fft, multiply by H^-1 (unit taper, C4),
+    inverse fft with 1/N (C6), keep y[n_front : n_front + hop] (C3)."""
+    X = sfft.fft(x_block, workers=workers)
+    y = sfft.ifft(X * chirp, workers=workers)
+    return y[n_front:n_front + hop]
+
+
+def dedisperse(x, f0_mhz, bw_mhz, dm, nfft, first_block=0, nblocks=None,
+               batch=8, workers=None):
+    """Dedispersed voltages of blocks [first_block, first_block + nblocks).
+
+    Block b covers input samples [b*hop, b*hop + nfft); its kept outputs are
+    outputs m = b*hop + j for j in [0, hop) (input sample m + n_front).
+    Returns (y, m0) with y complex128 and m0 the output index of y[0].
+    """
+    g = plan_geometry(f0_mhz, bw_mhz, dm, nfft)
+    hop, n_front = g["hop"], g["n_front"]
+    total = n_blocks(x.size, nfft, hop)
+    if nblocks is None:
+        nblocks = total - first_block
+    if first_block < 0 or first_block + nblocks > total:
+        raise ValueError("block range not covered by the input")
+    chirp = dedispersion_chirp(nfft, f0_mhz, bw_mhz, dm)
+    y = np.empty(nblocks * hop, dtype=np.complex128)
+    for b0 in range(0, nblocks, batch):
+        nb = min(batch, nblocks - b0)
+        X = np.stack([x[(first_block + b0 + i) * hop:(first_block + b0 + i) * hop + nfft]
+                      for i in range(nb)])
+        X = sfft.fft(X, axis=1, workers=workers)
+        X *= chirp
+        Y = sfft.ifft(X, axis=1, workers=workers)
+        y[b0 * hop:(b0 + nb) * hop] = Y[:, n_front:n_front + hop].reshape(-1)
+    return y, first_block * hop
+
+
+def detect(y):
+    """Square-law detection p = |y|^2 (reading C7)."""
+    return y.real * y.real + y.imag * y.imag
+
+
+def decimate(p, decim):
+    """Time series: sum of `decim` consecutive powers (reading C8, Sec. 4's
+    integration from the 62.5 ns base resolution to 1 us)."""
+    n = p.size // decim
+    return p[:n * decim].reshape(n, decim).sum(axis=1)
+
+
+def fold_bins(m, n_front, period_s, fs_hz, nbins):
+    """Profile bin of output m (reading C9), float64 throughout."""
+    inv_pfs = 1.0 / (period_s * fs_hz)
+    x = (np.asarray(m, dtype=np.int64) + n_front).astype(np.float64) * inv_pfs
+    frac = x - np.floor(x)
+    b = np.floor(frac * nbins).astype(np.int64)
+    return np.minimum(b, nbins - 1)
+
+
+def fold(p, m0, n_front, period_s, fs_hz, nbins, subint_nsamp):
+    """Sums and counts per (sub-integration, bin) of powers p of outputs
+    m0, m0+1, ...  (Sec. 3.4.1 and Sec. 3.7: the fold thread folds the
+    dedispersed series at the pulsar period and writes profiles
+    periodically; readings C9-C11).  Returns (sums, counts, first_subint).
+    """
+    m = m0 + np.arange(p.size, dtype=np.int64)
+    b = fold_bins(m, n_front, period_s, fs_hz, nbins)
+    if subint_nsamp > 0:
+        s = m // subint_nsamp
+    else:
+        s = np.zeros_like(m)
+    if p.size == 0:
+        return np.zeros((0, nbins)), np.zeros((0, nbins), dtype=np.int64), 0
+    s0 = int(s[0])
+    ns = int(s[-1]) - s0 + 1
+    idx = (s - s0) * nbins + b
+    sums = np.bincount(idx, weights=p, minlength=ns * nbins).reshape(ns, nbins)
+    cnts = np.bincount(idx, minlength=ns * nbins).reshape(ns, nbins).astype(np.int64)
+    return sums, cnts, s0
+
+
+def profiles_from(sums, cnts):
+    """Mean power per bin, 0 where a bin is empty (reading C10)."""
+    out = np.zeros_like(sums)
+    nz = cnts > 0
+    out[nz] = sums[nz] / cnts[nz]
+    return out
+
+
+def run(iq, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, subint_nsamp=0,
+        decim=16, batch=8, workers=None, keep_power=False):
+    """The whole path over one stream, every fully covered block.
+
+    Returns a dict with
+      geometry   the plan geometry
+      n_out      number of outputs (fully covered blocks x hop)
+      series     sum of `decim` consecutive powers, float64
+      sums, cnts per (sub-integration, bin), all sub-integrations touched
+      profiles   sums / cnts
+      complete   number of leading sub-integrations that are complete
+      power      the detected series at full resolution (if keep_power)
+    """
+    g = plan_geometry(f0_mhz, bw_mhz, dm, nfft)
+    x = unpack(iq)
+    hop, n_front = g["hop"], g["n_front"]
+    nb = n_blocks(x.size, nfft, hop)
+    n_out = nb * hop
+    series = np.empty(n_out // decim, dtype=np.float64)
+    ns_total = (max(n_out - 1, 0) // subint_nsamp + 1) if (subint_nsamp > 0 and n_out) else (1 if n_out else 0)
+    sums = np.zeros((ns_total, nbins))
+    cnts = np.zeros((ns_total, nbins), dtype=np.int64)
+    power = np.empty(n_out) if keep_power else None
+    for b0 in range(0, nb, batch):
+        k = min(batch, nb - b0)
+        y, m0 = dedisperse(x, f0_mhz, bw_mhz, dm, nfft, first_block=b0,
+                           nblocks=k, batch=batch, workers=workers)
+        p = detect(y)
+        series[m0 // decim:(m0 + p.size) // decim] = decimate(p, decim)
+        s, c, s0 = fold(p, m0, n_front, period_s, g["fs"], nbins, subint_nsamp)
+        sums[s0:s0 + s.shape[0]] += s
+        cnts[s0:s0 + c.shape[0]] += c
+        if keep_power:
+            power[m0:m0 + p.size] = p
+    complete = (n_out // subint_nsamp) if subint_nsamp > 0 else 0
+    return dict(geometry=g, n_out=n_out, series=series, sums=sums, cnts=cnts,
+                profiles=profiles_from(sums, cnts), complete=complete,
+                power=power)
+
+
+# --------------------------------------------------------------------------
+# Forward model used to build test streams (the inverse of the method)
+# --------------------------------------------------------------------------
+def disperse_pads(f0_mhz, bw_mhz, dm):
+    """Samples the dispersing filter needs before and after each output:
+    ceil(delta_lo fs) in front (low frequencies arrive later), ceil(delta_hi
+    fs) behind."""
+    g = plan_geometry(f0_mhz, bw_mhz, dm, 1 << 30)
+    return int(math.ceil(g["delta_lo"] * g["fs"])), int(math.ceil(g["delta_hi"] * g["fs"]))
+
+
+def disperse(z, f0_mhz, bw_mhz, dm, nfft):
+    """Apply the ISM response H (reading C2) to an undispersed stream by
+    overlap-save.  z covers pad_lo samples before and pad_hi samples after
+    the part kept; the result has z.size - pad_lo - pad_hi samples."""
+    pad_lo, pad_hi = disperse_pads(f0_mhz, bw_mhz, dm)
+    hop = nfft - pad_lo - pad_hi
+    if hop <= 0:
+        raise ValueError("nfft too short to disperse")
+    n_keep = z.size - pad_lo - pad_hi
+    H = ism_response(nfft, f0_mhz, bw_mhz, dm)
+    nb = -(-n_keep // hop)
+    zp = np.zeros(nb * hop + pad_lo + pad_hi + nfft, dtype=np.complex128)
+    zp[:z.size] = z
+    out = np.empty(nb * hop, dtype=np.complex128)
+    for b in range(nb):
+        y = sfft.ifft(sfft.fft(zp[b * hop:b * hop + nfft]) * H)
+        out[b * hop:(b + 1) * hop] = y[pad_lo:pad_lo + hop]
+    return out[:n_keep]

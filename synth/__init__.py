@@ -1,0 +1,133 @@
+"""Seeded synthetic baseband streams shaped like the Ooty Radio Telescope's
+pulsar data (single polarisation, 8-bit samples, 16 MHz complex baseband at
+326.5 MHz; Sec. 2, Sec. 3.1 and Sec. 4 of Naidu et al., arXiv:1503.01405).
+
+This module holds only the input recipe: Gaussian noise, a periodic pulse
+envelope and the 8-bit quantiser.  It contains none of the dedispersion
+arithmetic (no FFT, no chirp, no detection, no fold), so both the FP64 oracle
+and the GPU path can take their inputs from it without sharing any of the
+method's code.  Interstellar dispersion of a test stream is the oracle's
+forward model and lives there.
+
+Recipe (one stream):
+  * each complex sample is I + iQ with I, Q independent N(0, sigma^2),
+    sigma = 20, drawn from numpy's PCG64 ``default_rng(seed)`` as
+    ``standard_normal((n, 2))`` in chunks (the draw sequence does not depend
+    on the chunking);
+  * a pulse of Gaussian shape (full width at half maximum ``fwhm_s``) centred
+    at rotational phase ``phase0`` multiplies the noise amplitude by
+    sqrt(1 + peak * g(t)), so the expected power is (1 + peak * g) times the
+    noise power;
+  * quantisation rounds half to even and clips to the int8 range
+    [-128, 127]; I and Q are interleaved, I first.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SIGMA = 20.0          # per-component noise standard deviation (8-bit counts)
+F0_MHZ = 326.5        # ORT centre frequency
+BW_MHZ = 16.0         # complex bandwidth == complex sample rate in Msps
+PERIOD_S = 0.0891     # synthetic pulsar period
+FWHM_S = 1.0e-3       # pulse full width at half maximum
+PEAK = 3.0            # pulse peak power in units of the noise power
+PHASE0 = 0.5          # rotational phase of the pulse centre
+
+_CHUNK = 1 << 22
+
+
+def pulse_gain(sample_index, fs_hz, period_s=PERIOD_S, fwhm_s=FWHM_S,
+               peak=PEAK, phase0=PHASE0):
+    """Amplitude multiplier sqrt(1 + peak*g(t)) at t = sample_index / fs_hz.
+
+    g is a unit-height Gaussian in time of full width at half maximum
+    ``fwhm_s`` centred on rotational phase ``phase0`` of every period.
+    """
+    t = np.asarray(sample_index, dtype=np.float64) / fs_hz
+    ph = t / period_s - phase0
+    dt = (ph - np.rint(ph)) * period_s          # signed offset from the nearest pulse centre
+    g = np.exp(-4.0 * math.log(2.0) * (dt / fwhm_s) ** 2)
+    return np.sqrt(1.0 + peak * g)
+
+
+def pulse_power_shape(sample_index, fs_hz, period_s=PERIOD_S, fwhm_s=FWHM_S,
+                      peak=PEAK, phase0=PHASE0):
+    """Expected power envelope 1 + peak*g(t) (the square of ``pulse_gain``)."""
+    return pulse_gain(sample_index, fs_hz, period_s, fwhm_s, peak, phase0) ** 2
+
+
+def noise(seed: int, nsamp: int, sigma: float = SIGMA, chunk: int = _CHUNK):
+    """Complex128 Gaussian noise I + iQ, each component N(0, sigma^2)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty(nsamp, dtype=np.complex128)
+    for s in range(0, nsamp, chunk):
+        e = min(nsamp, s + chunk)
+        d = rng.standard_normal((e - s, 2))
+        out[s:e].real = d[:, 0] * sigma
+        out[s:e].imag = d[:, 1] * sigma
+    return out
+
+
+def pulsed_noise(seed: int, nsamp: int, first_index: int = 0,
+                 fs_hz: float = BW_MHZ * 1e6, period_s: float = PERIOD_S,
+                 fwhm_s: float = FWHM_S, peak: float = PEAK,
+                 phase0: float = PHASE0, sigma: float = SIGMA):
+    """Undispersed complex128 stream: noise times the pulse gain.
+
+    Sample i of the result sits at time (first_index + i) / fs_hz, so a
+    stream padded in front for a later dispersion step keeps its pulse phase
+    referenced to the first sample the user keeps.
+    """
+    z = noise(seed, nsamp, sigma)
+    idx = np.arange(first_index, first_index + nsamp, dtype=np.int64)
+    z *= pulse_gain(idx, fs_hz, period_s, fwhm_s, peak, phase0)
+    return z
+
+
+def quantize_int8(z):
+    """Interleaved int8 I/Q: round half to even, clip to [-128, 127]."""
+    z = np.asarray(z)
+    out = np.empty(2 * z.size, dtype=np.int8)
+    out[0::2] = np.clip(np.rint(z.real), -128, 127).astype(np.int8)
+    out[1::2] = np.clip(np.rint(z.imag), -128, 127).astype(np.int8)
+    return out
+
+
+def pulsed_stream_int8(seed: int, nsamp: int, fs_hz: float = BW_MHZ * 1e6,
+                       period_s: float = PERIOD_S, fwhm_s: float = FWHM_S,
+                       peak: float = PEAK, phase0: float = PHASE0,
+                       sigma: float = SIGMA, chunk: int = _CHUNK):
+    """Undispersed pulsed noise quantised to int8, built chunk by chunk.
+
+    Equal to ``quantize_int8(pulsed_noise(seed, nsamp, ...))`` but never
+    holds more than one chunk in float64, so a 60 s stream (1.92 GB of int8)
+    can be built on a host with modest memory.
+    """
+    rng = np.random.default_rng(seed)
+    out = np.empty(2 * nsamp, dtype=np.int8)
+    for s in range(0, nsamp, chunk):
+        e = min(nsamp, s + chunk)
+        d = rng.standard_normal((e - s, 2))
+        gain = pulse_gain(np.arange(s, e, dtype=np.int64), fs_hz, period_s,
+                          fwhm_s, peak, phase0)
+        d *= (sigma * gain)[:, None]
+        np.rint(d, out=d)
+        np.clip(d, -128, 127, out=d)
+        out[2 * s:2 * e] = d.astype(np.int8).reshape(-1)
+    return out
+
+
+def white_stream_int8(seed: int, nsamp: int, sigma: float = SIGMA,
+                      chunk: int = _CHUNK):
+    """Pure noise quantised to int8 (no pulse)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty(2 * nsamp, dtype=np.int8)
+    for s in range(0, nsamp, chunk):
+        e = min(nsamp, s + chunk)
+        d = rng.standard_normal((e - s, 2)) * sigma
+        np.rint(d, out=d)
+        np.clip(d, -128, 127, out=d)
+        out[2 * s:2 * e] = d.astype(np.int8).reshape(-1)
+    return out

@@ -1,0 +1,304 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each checks it against a value
+printed in the paper (tests/golden/paper_values.json), a closed form, an
+invariant, a brute-force O(N^2) evaluation or exact integer arithmetic.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+F0, BW = 326.5, 16.0
+
+
+# --------------------------------------------------------------- constants
+def test_dispersion_constant_matches_eq3_and_eq4(golden):
+    # Eq. (3): 4.15e6 ms == 4.15e3 s per unit DM per MHz^-2
+    assert abs(O.DM_CONST_S / (golden["eq3_coefficient_ms"]["value"] * 1e-3) - 1) < 1e-3
+    # Eq. (4): phase 8.3e3 * pi * DM f^2/(f0^2 (f+f0)); with the missing 1e6
+    # (MHz -> Hz) that is 2 pi DM_CONST_TURNS
+    assert abs(2 * O.DM_CONST_TURNS / (golden["eq4_coefficient"]["value"] * 1e6) - 1) < 1e-3
+    # Eq. (1) constant is the one used
+    assert O.DM_CONST_S == 1.0 / golden["eq1_constant"]["value"]
+
+
+def test_eq2_smear_across_band_matches_exact_delay(golden):
+    g = O.plan_geometry(F0, BW, 1.0, 1 << 18)
+    exact_ms = (g["delta_lo"] + g["delta_hi"]) * 1e3
+    eq2 = O.residual_smear_ms(BW, F0, 1.0)
+    assert abs(eq2 / exact_ms - 1) < 2e-3            # 3.815 vs 3.819 ms
+    assert abs(exact_ms - 3.8195) < 1e-3
+
+
+def test_1024_channel_smear_printed_in_paper(golden):
+    # Sec. 3.4: 1024 channels over 16 MHz leave ~3.8 us per unit DM
+    dfc = BW / 1024
+    exact_us = O.dispersion_delay_s(F0 - dfc / 2, F0 + dfc / 2, 1.0) * 1e6
+    eq2_us = O.residual_smear_ms(dfc, F0, 1.0) * 1e3
+    printed = golden["smear_1024ch_us_per_dm"]["value"]
+    assert abs(exact_us / printed - 1) < 0.03
+    assert abs(eq2_us / printed - 1) < 0.03
+
+
+def test_base_and_integrated_resolution(golden):
+    g = O.plan_geometry(F0, BW, 1.0, 1 << 18)
+    assert 1.0 / g["fs"] == pytest.approx(golden["base_resolution_s"]["value"], rel=1e-12)
+    assert 16 / g["fs"] == pytest.approx(golden["integrated_resolution_s"]["value"], rel=1e-12)
+
+
+def test_eq1_reading_is_documented(golden):
+    # Reading C12: N = 2 smear / ts; at DM 130 this gives 2^23.9, not the
+    # paper's 2^27 (documented discrepancy, not a requirement of the build).
+    n = O.fft_length_eq1(F0 + BW / 2, BW, 130.0, golden["base_resolution_s"]["value"])
+    assert 23.8 < math.log2(n) < 24.0
+
+
+# ------------------------------------------------------------------- chirp
+@pytest.mark.parametrize("dm", [0.0, 1.0, 50.0, 200.0])
+def test_chirp_unit_modulus(dm):
+    C = O.dedispersion_chirp(1 << 16, F0, BW, dm)
+    H = O.ism_response(1 << 16, F0, BW, dm)
+    assert np.max(np.abs(np.abs(C) - 1)) < 1e-15
+    assert np.max(np.abs(C * np.conj(C) - 1)) < 1e-15
+    assert np.max(np.abs(H * C - 1)) < 1e-14
+    assert C[0] == 1.0
+    if dm == 0.0:
+        assert np.all(C == 1.0)
+
+
+@pytest.mark.parametrize("dm", [1.0, 50.0, 200.0])
+def test_group_delay_is_cold_plasma_delay(dm):
+    """-d(turns)/df of the ISM response is the delay of Eq. (3)'s form."""
+    f = np.linspace(-BW / 2 * 0.999, BW / 2 * 0.999, 257)
+    h = 1e-4
+    slope = (O.chirp_turns(f + h, F0, dm) - O.chirp_turns(f - h, F0, dm)) / (2 * h)  # turns/MHz = us
+    # H = exp(+2 pi i turns), numpy convention: a delay tau multiplies the
+    # spectrum by exp(-2 pi i f tau) -> tau = -d(phase)/d(2 pi f)
+    tau_s = -slope * 1e-6
+    want = O.dispersion_delay_s(F0 + f, F0, dm)
+    # lower frequencies later (positive), upper earlier
+    assert np.all(want[f < 0] > 0) and np.all(want[f > 0] < 0)
+    np.testing.assert_allclose(tau_s, want, rtol=1e-7, atol=1e-12)
+
+
+def test_dispersed_impulse_arrives_at_subband_delays():
+    """A dispersed impulse: in each of 16 sub-bands the energy centroid lies
+    at the cold-plasma delay of that sub-band's centre."""
+    dm = 1.0
+    fs = BW * 1e6
+    pad_lo, pad_hi = O.disperse_pads(F0, BW, dm)
+    L = 1 << 17
+    t0 = 40000
+    z = np.zeros(pad_lo + L + pad_hi, dtype=np.complex128)
+    z[pad_lo + t0] = 1.0
+    out = O.disperse(z, F0, BW, dm, 1 << 18)
+    S = np.fft.fft(out)
+    fr = np.fft.fftfreq(out.size, 1.0 / BW)
+    edges = np.linspace(-BW / 2, BW / 2, 17)
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        mask = (fr >= lo) & (fr < hi)
+        sub = np.fft.ifft(np.where(mask, S, 0))
+        w = np.abs(sub) ** 2
+        t = np.arange(out.size)
+        centroid = (w * t).sum() / w.sum()
+        fc = 0.5 * (lo + hi)
+        want = t0 + O.dispersion_delay_s(F0 + fc, F0, dm) * fs
+        sub_smear = (O.dispersion_delay_s(F0 + lo, F0, dm) - O.dispersion_delay_s(F0 + hi, F0, dm)) * fs
+        assert abs(centroid - want) < 0.05 * sub_smear + 3, (lo, hi, centroid, want)
+
+
+# --------------------------------------------------------------------- FFT
+def _brute_dft(x, sign):
+    n = x.size
+    k = np.arange(n)
+    W = np.exp(sign * 2j * np.pi * np.outer(k, k) / n)
+    return W @ x
+
+
+@pytest.mark.parametrize("n", [8, 16, 64])
+def test_block_transform_is_brute_force_dft(n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    C = np.exp(2j * np.pi * rng.random(n))
+    got = O.dedisperse_block(x, C, 0, n)
+    want = _brute_dft(_brute_dft(x, -1) * C, +1) / n
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(x).max())
+
+
+def test_parseval_and_all_pass_energy():
+    rng = np.random.default_rng(3)
+    n = 1 << 14
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    X = np.fft.fft(x)
+    assert abs(np.sum(np.abs(X) ** 2) / n / np.sum(np.abs(x) ** 2) - 1) < 1e-12
+    C = O.dedispersion_chirp(n, F0, BW, 3.0)
+    y = O.dedisperse_block(x, C, 0, n)
+    assert abs(np.sum(np.abs(y) ** 2) / np.sum(np.abs(x) ** 2) - 1) < 1e-12
+
+
+def test_overlap_save_equals_brute_circular_convolution():
+    """Valid outputs of every block equal the O(N^2) circular convolution of
+    that block with h = IDFT(H^-1), and land at outputs m = b*hop + j."""
+    n, dm = 256, 0.001
+    g = O.plan_geometry(F0, BW, dm, n)
+    assert g["discard"] == 64 and g["hop"] == 192
+    rng = np.random.default_rng(7)
+    iq = rng.integers(-128, 128, size=2 * (n + 3 * g["hop"])).astype(np.int8)
+    x = iq[0::2].astype(np.float64) + 1j * iq[1::2]
+    C = O.dedispersion_chirp(n, F0, BW, dm)
+    h = _brute_dft(C, +1) / n
+    y, m0 = O.dedisperse(O.unpack(iq), F0, BW, dm, n)
+    assert m0 == 0 and y.size == 4 * g["hop"]
+    idx = np.arange(n)
+    for b in range(4):
+        xb = x[b * g["hop"]:b * g["hop"] + n]
+        conv = np.array([np.sum(xb * h[(i - idx) % n]) for i in range(n)])
+        want = conv[g["n_front"]:g["n_front"] + g["hop"]]
+        np.testing.assert_allclose(y[b * g["hop"]:(b + 1) * g["hop"]], want, rtol=0, atol=1e-9)
+
+
+# -------------------------------------------------------------------- fold
+def _brute_fold(p, m0, n_front, period_s, fs, nbins, S):
+    inv = 1.0 / (period_s * fs)
+    sums, cnts = {}, {}
+    for i, v in enumerate(p):
+        m = m0 + i
+        x = float(m + n_front) * inv
+        b = min(int(math.floor((x - math.floor(x)) * nbins)), nbins - 1)
+        s = m // S if S > 0 else 0
+        sums[(s, b)] = sums.get((s, b), 0.0) + float(v)
+        cnts[(s, b)] = cnts.get((s, b), 0) + 1
+    return sums, cnts
+
+
+@pytest.mark.parametrize("S", [0, 37, 1000])
+def test_fold_matches_python_loop(S):
+    rng = np.random.default_rng(11)
+    p = rng.random(3001) * 100
+    m0, nf, nbins, period, fs = 777, 123, 13, 1.234e-5, 16e6
+    sums, cnts, s0 = O.fold(p, m0, nf, period, fs, nbins, S)
+    bs, bc = _brute_fold(p, m0, nf, period, fs, nbins, S)
+    for s in range(sums.shape[0]):
+        for b in range(nbins):
+            assert cnts[s, b] == bc.get((s0 + s, b), 0)
+            assert sums[s, b] == pytest.approx(bs.get((s0 + s, b), 0.0), rel=1e-12, abs=1e-9)
+    assert cnts.sum() == p.size
+
+
+def test_fold_bins_integer_period_exact_counts():
+    """P fs = 1425600 samples (P = 0.0891 s at 16 Msps): the bin of sample n
+    is floor(256 n / 1425600) exactly, except at exact bin edges where the
+    float64 rounding of 1/(P fs) may put it one bin lower."""
+    nbins, P, fs = 256, 0.0891, 16e6
+    n = np.arange(1425600, dtype=np.int64)
+    b = O.fold_bins(n, 0, P, fs, nbins)
+    exact = (n * nbins) // 1425600
+    tie = (n * nbins) % 1425600 == 0
+    assert np.all(b[~tie] == exact[~tie])
+    assert np.all((b[tie] == exact[tie]) | (b[tie] == exact[tie] - 1))
+    counts = np.bincount(b, minlength=nbins)
+    ex_counts = np.bincount(exact, minlength=nbins)
+    assert counts.sum() == n.size
+    assert np.max(np.abs(counts - ex_counts)) <= 1
+    assert set(np.unique(ex_counts)) <= {5568, 5569}
+
+
+def test_dm0_reduces_to_plain_fold_of_power():
+    """DM = 0: H^-1 = 1, no discard, so the method is |x|^2 folded directly."""
+    rng = np.random.default_rng(5)
+    n = 1024
+    iq = rng.integers(-128, 128, size=2 * 3 * n).astype(np.int8)
+    r = O.run(iq, F0, BW, 0.0, n, nbins=7, period_s=2.3e-5, subint_nsamp=500,
+              decim=4, keep_power=True)
+    x = iq[0::2].astype(np.float64) + 1j * iq[1::2]
+    pw = np.abs(x) ** 2
+    assert r["geometry"]["discard"] == 0 and r["n_out"] == 3 * n
+    np.testing.assert_allclose(r["power"], pw, rtol=1e-12, atol=1e-9)
+    bs, bc = _brute_fold(pw, 0, 0, 2.3e-5, 16e6, 7, 500)
+    for (s, b), v in bs.items():
+        assert r["cnts"][s, b] == bc[(s, b)]
+        assert r["sums"][s, b] == pytest.approx(v, rel=1e-10)
+    np.testing.assert_allclose(r["series"], pw.reshape(-1, 4).sum(1), rtol=1e-10)
+
+
+def test_series_fold_and_count_invariants():
+    rng = np.random.default_rng(9)
+    n = 1 << 12
+    iq = rng.integers(-60, 60, size=2 * 5 * n).astype(np.int8)
+    r = O.run(iq, F0, BW, 0.05, n, nbins=32, period_s=1.1e-4, subint_nsamp=3000,
+              decim=16, keep_power=True)
+    g = r["geometry"]
+    assert r["n_out"] == O.n_blocks(5 * n, n, g["hop"]) * g["hop"]
+    assert r["cnts"].sum() == r["n_out"]
+    assert r["series"].sum() == pytest.approx(r["power"].sum(), rel=1e-12)
+    assert r["sums"].sum() == pytest.approx(r["power"].sum(), rel=1e-12)
+    assert r["complete"] == r["n_out"] // 3000
+
+
+# ---------------------------------------------------------------- geometry
+def test_geometry_of_stated_workloads():
+    g0 = O.plan_geometry(F0, BW, 1.0, 1 << 18)
+    assert (g0["n_front"], g0["discard"], g0["hop"]) == (29434, 1 << 16, 196608)
+    g1 = O.plan_geometry(F0, BW, 50.0, 1 << 23)
+    assert (g1["n_front"], g1["discard"], g1["hop"]) == (1471655, 1 << 22, 1 << 22)
+    assert O.n_blocks(960_000_000, 1 << 23, g1["hop"]) == 227
+    g4 = O.plan_geometry(F0, BW, 200.0, 1 << 24)
+    assert (g4["discard"], g4["hop"]) == (12222368, 4554848)
+    gz = O.plan_geometry(F0, BW, 0.0, 1 << 10)
+    assert (gz["n_front"], gz["discard"], gz["hop"]) == (0, 0, 1 << 10)
+    with pytest.raises(ValueError):
+        O.plan_geometry(F0, BW, 200.0, 1 << 20)
+
+
+# ----------------------------------------------------- end to end (config 0)
+def _config0_stream(seed=1, nsamp=8_000_000, dm=1.0):
+    fs = BW * 1e6
+    pad_lo, pad_hi = O.disperse_pads(F0, BW, dm)
+    z = synth.pulsed_noise(seed, pad_lo + nsamp + pad_hi, first_index=-pad_lo, fs_hz=fs)
+    return synth.quantize_int8(O.disperse(z, F0, BW, dm, 1 << 20))
+
+
+@pytest.fixture(scope="module")
+def config0_iq():
+    return _config0_stream()
+
+
+def test_pulse_recovered_at_true_dm(config0_iq):
+    """Dedispersing the config-0 stream recovers the injected pulse: each bin
+    matches 800 (1 + 3 g_bin) + 1/6 within its own statistics."""
+    nbins, P = 256, synth.PERIOD_S
+    r = O.run(config0_iq, F0, BW, 1.0, 1 << 18, nbins, P, subint_nsamp=0, decim=16)
+    g = r["geometry"]
+    assert r["n_out"] == 7_864_320
+    m = np.arange(r["n_out"], dtype=np.int64)
+    b = O.fold_bins(m, g["n_front"], P, g["fs"], nbins)
+    shape = synth.pulse_power_shape(m + g["n_front"], g["fs"])
+    mean_i = 2 * synth.SIGMA ** 2 * shape + 1.0 / 6.0
+    cnt = np.bincount(b, minlength=nbins)
+    want = np.bincount(b, weights=mean_i, minlength=nbins) / cnt
+    sd = np.sqrt(np.bincount(b, weights=mean_i ** 2, minlength=nbins)) / cnt
+    z = (r["profiles"][0] - want) / sd
+    assert np.max(np.abs(z)) < 5.5, np.argmax(np.abs(z))
+    chi2 = np.mean(z ** 2)
+    assert 0.7 < chi2 < 1.4
+    assert abs(int(np.argmax(r["profiles"][0])) - nbins // 2) <= 1
+    np.testing.assert_array_equal(r["cnts"][0], cnt)
+
+
+def test_dm0_processing_leaves_the_dispersion_smear(config0_iq):
+    """Folding the same stream without dedispersion smears the pulse over the
+    ~3.8 ms band delay: lower peak, wider profile (the synthetic analogue of
+    the coherent vs incoherent comparison of Sec. 4)."""
+    nbins, P = 256, synth.PERIOD_S
+    good = O.run(config0_iq, F0, BW, 1.0, 1 << 18, nbins, P)["profiles"][0]
+    raw = O.run(config0_iq, F0, BW, 0.0, 1 << 18, nbins, P)["profiles"][0]
+    base = 800.17
+    pk_good, pk_raw = good.max() - base, raw.max() - base
+    assert pk_raw < 0.6 * pk_good
+    w_good = np.sum(good - base > pk_good / 2)
+    w_raw = np.sum(raw - base > pk_raw / 2)
+    assert w_raw > 2.5 * w_good
