@@ -1,0 +1,657 @@
+// Host runtime behind include/pond.h: plan geometry (float64), device
+// workspace, streaming state (input tail, block counter, sub-integration
+// accumulators) and the launch sequence K1 -> K2 -> K3 -> fold reduction per
+// batch of overlap-save blocks, then the profile finalisation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pond.h"
+#include "pond_internal.hpp"
+
+using namespace pond;
+
+namespace {
+
+thread_local int32_t g_create_status = POND_OK;
+
+constexpr int64_t kMinLog2N = 10;
+constexpr int64_t kMaxLog2N = 24;
+constexpr int kMaxLog2N2 = 10;          // column length cap (K1/K3 tile = 16 columns in LDS)
+constexpr size_t kLdsBytes = 160 * 1024; // gfx950 LDS per workgroup
+constexpr int64_t kHistCapMax = 8192;   // fold histogram entries held in LDS
+constexpr int kCus = 256;
+constexpr int64_t kPartEntries = 1 << 21;  // per-workgroup fold partials: grid * entries <= this
+
+int ilog2(int64_t v) {
+    int r = 0;
+    while ((int64_t(1) << r) < v) ++r;
+    return r;
+}
+
+}  // namespace
+
+struct pond_plan {
+    int device = 0;
+    double f0 = 0, bw = 0, dm = 0, period = 0;
+    double fs = 0, delta_lo = 0, delta_hi = 0, inv_pfs = 0, chirp_a = 0, df = 0;
+    int64_t nfft = 0, n_front = 0, discard = 0, hop = 0;
+    int log2n = 0, log2n1 = 0, log2n2 = 0, hbits = 0;
+    int32_t nbins = 0, precision = 0;
+    int max_batch = 1;
+    size_t elem = 8;
+
+    void* work = nullptr;
+    int8_t* tail[2] = {nullptr, nullptr};
+    int tcur = 0;
+    int64_t tail_start = 0;
+    float2* tw1 = nullptr;
+    float2* tw2 = nullptr;
+    float2* twhi = nullptr;
+    float2* twlo = nullptr;
+    uint64_t* acc_sum = nullptr;
+    uint64_t* acc_cnt = nullptr;
+    int64_t acc_slots = 0;
+    uint64_t* part_sum = nullptr;
+    uint32_t* part_cnt = nullptr;
+    int64_t hist_cap = 0;
+    int k3_grid_max = 0;
+    uint64_t* status = nullptr;  // low 32 bits used
+
+    // per-kernel timing (measurement only)
+    bool timing = false;
+    struct Mark {
+        int kernel;
+        int64_t blocks;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> event_pool;
+    double t_ms[POND_NKERNELS] = {0};
+    int64_t t_launch[POND_NKERNELS] = {0};
+    int64_t t_blocks[POND_NKERNELS] = {0};
+
+    int64_t samples_in = 0;
+    int64_t blocks_done = 0;
+    int64_t subint = -1;
+    bool sticky = false;
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int old = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&old) != hipSuccess) { ok = false; return; }
+        if (old != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+    }
+};
+
+hipEvent_t take_event(pond_plan* p) {
+    if (!p->event_pool.empty()) {
+        hipEvent_t e = p->event_pool.back();
+        p->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Fold finished marks into the sums (events must have completed).
+hipError_t collect_marks(pond_plan* p) {
+    hipError_t err = hipSuccess;
+    for (auto& m : p->marks) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, m.a, m.b);
+        if (e == hipSuccess) {
+            p->t_ms[m.kernel] += ms;
+            p->t_launch[m.kernel] += 1;
+            p->t_blocks[m.kernel] += m.blocks;
+        } else if (err == hipSuccess) {
+            err = e;
+        }
+        p->event_pool.push_back(m.a);
+        p->event_pool.push_back(m.b);
+    }
+    p->marks.clear();
+    return err;
+}
+
+void free_plan_memory(pond_plan* p) {
+    for (auto& m : p->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    p->marks.clear();
+    for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
+    p->event_pool.clear();
+    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->twhi, p->twlo,
+                    p->acc_sum, p->acc_cnt, p->part_sum, p->part_cnt, p->status};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+}
+
+// exp(-2 pi i t / n) for t in [t0, t0 + count) with stride, float64 then float32
+std::vector<float2> twiddles(int64_t n, int64_t count, int64_t stride) {
+    std::vector<float2> w((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t t = (i * stride) % n;
+        const double a = 2.0 * M_PI * (double)t / (double)n;
+        w[(size_t)i] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    return w;
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& v) {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+int64_t n_blocks_for(int64_t nsamp, int64_t nfft, int64_t hop) {
+    return nsamp < nfft ? 0 : (nsamp - nfft) / hop + 1;
+}
+
+int k3_wg_per_cu(size_t lds_bytes) {
+    int w = (int)(kLdsBytes / (lds_bytes ? lds_bytes : 1));
+    if (w < 1) w = 1;
+    if (w > 4) w = 4;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pond_create_status(void) { return g_create_status; }
+
+const char* pond_strerror(int64_t code) {
+    switch (code) {
+        case POND_OK: return "ok";
+        case POND_EINVAL: return "invalid argument or call sequence";
+        case POND_ENOMEM: return "device allocation failed";
+        case POND_EDEVICE: return "HIP runtime error (plan unusable)";
+        default: return code > 0 ? "ok" : "unknown error";
+    }
+}
+
+pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins,
+                               double period_s, int32_t precision, int32_t max_batch) {
+    g_create_status = POND_EINVAL;
+    if (!std::isfinite(f0_mhz) || !std::isfinite(bw_mhz) || !std::isfinite(dm) || !std::isfinite(period_s))
+        return nullptr;
+    if (!(bw_mhz > 0) || !(f0_mhz - bw_mhz / 2 > 0) || !(dm >= 0)) return nullptr;
+    if (nfft <= 0 || (nfft & (nfft - 1)) != 0) return nullptr;
+    const int log2n = ilog2(nfft);
+    if (log2n < kMinLog2N || log2n > kMaxLog2N) return nullptr;
+    if (nbins < 1 || nbins > 65536) return nullptr;
+    if (precision != POND_FP32 && precision != POND_MIXED) return nullptr;
+    const double fs = bw_mhz * 1e6;
+    if (!(period_s > 0) || !(period_s * fs >= 1.0)) return nullptr;
+
+    // Geometry (Sec. 3.7: filter longer than the smear, cyclic edges dropped).
+    const double k_dm = 1.0 / 2.41e-4;  // s MHz^2 per unit DM, the constant of Eq. (1)
+    const double f_lo = f0_mhz - bw_mhz / 2;
+    const double f_hi = f0_mhz + bw_mhz / 2;
+    const double delta_lo = k_dm * dm * (1.0 / (f_lo * f_lo) - 1.0 / (f0_mhz * f0_mhz));
+    const double delta_hi = k_dm * dm * (1.0 / (f0_mhz * f0_mhz) - 1.0 / (f_hi * f_hi));
+    const double front_d = std::ceil(delta_hi * fs);
+    const double back_d = std::ceil(delta_lo * fs);
+    if (!(front_d + back_d < (double)nfft)) return nullptr;
+    const int64_t n_front = (int64_t)front_d;
+    const int64_t s = n_front + (int64_t)back_d;
+    int64_t discard = 0;
+    if (s > 0) {
+        int64_t p2 = 16;
+        while (p2 < s) p2 <<= 1;
+        discard = p2 <= nfft / 2 ? p2 : ((s + 15) / 16) * 16;
+    }
+    const int64_t hop = nfft - discard;
+    if (hop <= 0) return nullptr;
+
+    pond_plan* p = new (std::nothrow) pond_plan();
+    if (!p) {
+        g_create_status = POND_ENOMEM;
+        return nullptr;
+    }
+    g_create_status = POND_EDEVICE;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return nullptr;
+    }
+    p->f0 = f0_mhz;
+    p->bw = bw_mhz;
+    p->dm = dm;
+    p->period = period_s;
+    p->fs = fs;
+    p->delta_lo = delta_lo;
+    p->delta_hi = delta_hi;
+    p->inv_pfs = 1.0 / (period_s * fs);
+    p->chirp_a = dm / (2.41e-10 * f0_mhz * f0_mhz);
+    p->df = bw_mhz / (double)nfft;
+    p->nfft = nfft;
+    p->n_front = n_front;
+    p->discard = discard;
+    p->hop = hop;
+    p->log2n = log2n;
+    p->log2n2 = log2n / 2 < kMaxLog2N2 ? log2n / 2 : kMaxLog2N2;
+    p->log2n1 = log2n - p->log2n2;
+    p->hbits = (log2n + 1) / 2;
+    p->nbins = nbins;
+    p->precision = precision;
+    p->elem = precision == POND_MIXED ? 4 : 8;
+    if (max_batch <= 0) {
+        int64_t b = ((int64_t)1 << 29) / (nfft * (int64_t)p->elem);
+        max_batch = (int)(b < 1 ? 1 : (b > 16 ? 16 : b));
+    }
+    p->max_batch = max_batch;
+
+    const size_t k3_static = k3_static_lds(p->log2n2);
+    int64_t cap = (int64_t)((kLdsBytes - k3_static) / 12);
+    p->hist_cap = cap < kHistCapMax ? cap : kHistCapMax;
+    p->k3_grid_max = kCus * 4;
+
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    chk(hipMalloc(&p->work, (size_t)max_batch * (size_t)nfft * p->elem));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->tail[0]), (size_t)nfft * 2));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->tail[1]), (size_t)nfft * 2));
+    const int64_t n1 = (int64_t)1 << p->log2n1, n2 = (int64_t)1 << p->log2n2;
+    if (e == hipSuccess) chk(upload(&p->tw1, twiddles(n1, n1, 1)));
+    if (e == hipSuccess) chk(upload(&p->tw2, twiddles(n2, n2, 1)));
+    if (e == hipSuccess) chk(upload(&p->twhi, twiddles(nfft, nfft >> p->hbits, (int64_t)1 << p->hbits)));
+    if (e == hipSuccess) chk(upload(&p->twlo, twiddles(nfft, (int64_t)1 << p->hbits, 1)));
+    p->acc_slots = 4;
+    chk(hipMalloc(reinterpret_cast<void**>(&p->acc_sum), (size_t)p->acc_slots * nbins * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->acc_cnt), (size_t)p->acc_slots * nbins * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->part_sum), (size_t)kPartEntries * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->part_cnt), (size_t)kPartEntries * 4));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->status), 8));
+    if (e == hipSuccess) chk(hipMemset(p->acc_sum, 0, (size_t)p->acc_slots * nbins * 8));
+    if (e == hipSuccess) chk(hipMemset(p->acc_cnt, 0, (size_t)p->acc_slots * nbins * 8));
+    if (e == hipSuccess) chk(hipMemset(p->status, 0, 8));
+    if (e == hipSuccess) chk(hipDeviceSynchronize());
+    if (e != hipSuccess) {
+        g_create_status = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? POND_ENOMEM : POND_EDEVICE;
+        free_plan_memory(p);
+        delete p;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    g_create_status = POND_OK;
+    return p;
+}
+
+pond_plan* pond_plan_create(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins,
+                            double period_s) {
+    return pond_plan_create_ex(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, POND_FP32, 0);
+}
+
+void pond_plan_destroy(pond_plan* p) {
+    if (!p) return;
+    {
+        DeviceGuard g(p->device);
+        if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
+        (void)hipDeviceSynchronize();
+        free_plan_memory(p);
+    }
+    delete p;
+}
+
+int32_t pond_plan_query(pond_plan* p, pond_info* out) {
+    if (!p || !out) return POND_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->nfft = p->nfft;
+    out->n_front = p->n_front;
+    out->discard = p->discard;
+    out->hop = p->hop;
+    out->n1 = (int64_t)1 << p->log2n1;
+    out->n2 = (int64_t)1 << p->log2n2;
+    out->samples_in = p->samples_in;
+    out->outputs_done = p->blocks_done * p->hop;
+    out->max_batch = p->max_batch;
+    out->fs_hz = p->fs;
+    out->delta_lo_s = p->delta_lo;
+    out->delta_hi_s = p->delta_hi;
+    out->inv_pfs = p->inv_pfs;
+    out->nbins = p->nbins;
+    out->precision = p->precision;
+    if (p->sticky) return POND_EDEVICE;
+    DeviceGuard g(p->device);
+    uint64_t st = 0;
+    hipError_t e = hipStreamSynchronize(p->last_stream);
+    if (e == hipSuccess) e = hipMemcpy(&st, p->status, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        p->sticky = true;
+        return POND_EDEVICE;
+    }
+    out->status = (uint32_t)st;
+    return POND_OK;
+}
+
+int32_t pond_plan_set_timing(pond_plan* p, int32_t enable) {
+    if (!p) return POND_EINVAL;
+    if (p->sticky) return POND_EDEVICE;
+    DeviceGuard g(p->device);
+    if (!p->marks.empty()) {
+        if (hipStreamSynchronize(p->last_stream) != hipSuccess) {
+            p->sticky = true;
+            return POND_EDEVICE;
+        }
+        (void)collect_marks(p);
+    }
+    for (int k = 0; k < POND_NKERNELS; ++k) {
+        p->t_ms[k] = 0;
+        p->t_launch[k] = 0;
+        p->t_blocks[k] = 0;
+    }
+    p->timing = enable != 0;
+    return POND_OK;
+}
+
+int32_t pond_plan_kernel_times(pond_plan* p, pond_kernel_times* out) {
+    if (!p || !out) return POND_EINVAL;
+    if (p->sticky) return POND_EDEVICE;
+    DeviceGuard g(p->device);
+    if (hipStreamSynchronize(p->last_stream) != hipSuccess || collect_marks(p) != hipSuccess) {
+        p->sticky = true;
+        return POND_EDEVICE;
+    }
+    for (int k = 0; k < POND_NKERNELS; ++k) {
+        out->ms[k] = p->t_ms[k];
+        out->launches[k] = p->t_launch[k];
+        out->blocks[k] = p->t_blocks[k];
+    }
+    return POND_OK;
+}
+
+int32_t pond_plan_expect(const pond_plan* p, int64_t nsamp, int64_t subint, int64_t* n_profiles,
+                         int64_t* n_outputs) {
+    if (!p || nsamp < 0 || subint < 0) return POND_EINVAL;
+    const int64_t m_before = p->blocks_done * p->hop;
+    const int64_t s_open = subint > 0 ? m_before / subint : 0;
+    int64_t np = 0, no = 0;
+    if (nsamp == 0) {
+        const int64_t in_open = subint > 0 ? m_before - s_open * subint : m_before;
+        np = in_open > 0 ? 1 : 0;
+    } else {
+        const int64_t m_after = n_blocks_for(p->samples_in + nsamp, p->nfft, p->hop) * p->hop;
+        no = m_after - m_before;
+        np = subint > 0 ? m_after / subint - s_open : 0;
+    }
+    if (n_profiles) *n_profiles = np;
+    if (n_outputs) *n_outputs = no;
+    return POND_OK;
+}
+
+static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t subint, float* profiles,
+                        int64_t max_profiles, int32_t decim, float* series, int64_t series_cap,
+                        int64_t* n_series_out, bool want_series, void* stream_ptr) {
+    if (!p) return POND_EINVAL;
+    if (p->sticky) return POND_EDEVICE;
+    if (n_series_out) *n_series_out = 0;
+    const bool flush = (iq == nullptr && nsamp == 0);
+    if (!flush) {
+        if (nsamp < 0) return POND_EINVAL;
+        if (nsamp > 0 && (iq == nullptr || (reinterpret_cast<uintptr_t>(iq) & 1u))) return POND_EINVAL;
+    }
+    if (subint < 0 || max_profiles < 0) return POND_EINVAL;
+    if (p->subint >= 0 && subint != p->subint) return POND_EINVAL;
+    if (decim <= 0) decim = 16;
+    if (decim != 1 && decim != 2 && decim != 4 && decim != 8 && decim != 16) return POND_EINVAL;
+    if (want_series && series_cap < 0) return POND_EINVAL;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
+
+    const int64_t hop = p->hop;
+    const int32_t nbins = p->nbins;
+    const int64_t m_before = p->blocks_done * hop;
+    const int64_t s_open = subint > 0 ? m_before / subint : 0;
+
+    DeviceGuard guard(p->device);
+    if (!guard.ok) {
+        p->sticky = true;
+        return POND_EDEVICE;
+    }
+    hipError_t e = hipSuccess;
+    auto fail = [&](hipError_t x) -> int64_t {
+        (void)x;
+        (void)hipGetLastError();
+        p->sticky = true;
+        return POND_EDEVICE;
+    };
+    // Launch through `timed` so that, with timing on, each kernel is
+    // bracketed by events on the call's stream.
+    auto timed = [&](int kernel, int64_t blocks, auto&& launch) -> hipError_t {
+        if (!p->timing) return launch();
+        hipEvent_t ea = take_event(p), eb = take_event(p);
+        if (!ea || !eb) return hipErrorOutOfMemory;
+        hipError_t r = hipEventRecord(ea, stream);
+        if (r == hipSuccess) r = launch();
+        if (r == hipSuccess) r = hipEventRecord(eb, stream);
+        p->marks.push_back({kernel, blocks, ea, eb});
+        return r;
+    };
+
+    if (flush) {
+        const int64_t in_open = subint > 0 ? m_before - s_open * subint : m_before;
+        const int64_t nprof = in_open > 0 ? 1 : 0;
+        if (nprof > max_profiles || (nprof && !profiles)) return POND_EINVAL;
+        if (nprof) {
+            e = timed(4, 0, [&] { return launch_fold_finalize(p->acc_sum, p->acc_cnt, nbins, 1, 1, profiles, stream); });
+            if (e != hipSuccess) return fail(e);
+        }
+        e = launch_zero_u64(p->status, 1, stream);
+        if (e != hipSuccess) return fail(e);
+        p->samples_in = 0;
+        p->blocks_done = 0;
+        p->tail_start = 0;
+        p->subint = -1;
+        p->last_stream = stream;
+        return nprof;
+    }
+
+    const int64_t total = p->samples_in + nsamp;
+    const int64_t nb_total = n_blocks_for(total, p->nfft, hop);
+    const int64_t m_after = nb_total * hop;
+    int64_t n_complete = 0, n_touched = 0;
+    if (subint > 0) {
+        n_complete = m_after / subint - s_open;
+        n_touched = m_after > m_before ? (m_after - 1) / subint - s_open + 1 : 0;
+    } else {
+        n_touched = m_after > m_before ? 1 : 0;
+    }
+    if (n_complete > max_profiles || (n_complete > 0 && !profiles)) return POND_EINVAL;
+    const int64_t groups = (m_after - m_before) / decim;
+    if (want_series && (groups > series_cap || (groups > 0 && !series))) return POND_EINVAL;
+
+    // Grow the accumulator ring if this call touches more sub-integrations.
+    if (n_touched > p->acc_slots) {
+        int64_t slots = p->acc_slots;
+        while (slots < n_touched) slots *= 2;
+        uint64_t *ns = nullptr, *nc = nullptr;
+        e = hipMallocAsync(reinterpret_cast<void**>(&ns), (size_t)slots * nbins * 8, stream);
+        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&nc), (size_t)slots * nbins * 8, stream);
+        if (e != hipSuccess) {
+            if (ns) (void)hipFreeAsync(ns, stream);
+            (void)hipGetLastError();
+            return POND_ENOMEM;
+        }
+        e = launch_zero_u64(ns, slots * nbins, stream);
+        if (e == hipSuccess) e = launch_zero_u64(nc, slots * nbins, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(ns, p->acc_sum, (size_t)nbins * 8, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(nc, p->acc_cnt, (size_t)nbins * 8, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess) e = hipFreeAsync(p->acc_sum, stream);
+        if (e == hipSuccess) e = hipFreeAsync(p->acc_cnt, stream);
+        if (e != hipSuccess) return fail(e);
+        p->acc_sum = ns;
+        p->acc_cnt = nc;
+        p->acc_slots = slots;
+    }
+
+    const int64_t n1 = (int64_t)1 << p->log2n1;
+    const int n2log = p->log2n2;
+    const int s_mix = n2log / 2;  // column-pass scale exponent of K1
+    const float k1_scale = std::ldexp(1.0f, -s_mix);
+    const float k2_scale = std::ldexp(1.0f, -p->log2n1);
+    const float k3_scale = std::ldexp(1.0f, -(n2log - s_mix));
+
+    int64_t b = p->blocks_done;
+    while (b < nb_total) {
+        int64_t nb = nb_total - b < p->max_batch ? nb_total - b : p->max_batch;
+        int64_t s_lo = 0, nsub = 1;
+        for (;;) {
+            if (subint > 0) {
+                s_lo = (b * hop) / subint;
+                const int64_t s_hi = ((b + nb) * hop - 1) / subint;
+                nsub = s_hi - s_lo + 1;
+            }
+            if (nsub * nbins <= p->hist_cap || nb == 1) break;
+            nb = (nb + 1) / 2;
+        }
+        const int64_t entries = nsub * nbins;
+        const bool global_mode = entries > p->hist_cap;
+
+        K1Args a1;
+        a1.tail = p->tail[p->tcur];
+        a1.tail_start = p->tail_start;
+        a1.in = iq;
+        a1.in_start = p->samples_in;
+        a1.hop = hop;
+        a1.block0 = b;
+        a1.nblocks = (int32_t)nb;
+        a1.log2n1 = p->log2n1;
+        a1.work = p->work;
+        a1.tw2 = p->tw2;
+        a1.scale = k1_scale;
+        e = timed(0, nb, [&] { return launch_k1(p->precision, n2log, a1, stream); });
+        if (e != hipSuccess) return fail(e);
+
+        K2Args a2;
+        a2.work = p->work;
+        a2.rows = nb << n2log;
+        a2.log2n2 = n2log;
+        a2.log2n = p->log2n;
+        a2.tw1 = p->tw1;
+        a2.twhi = p->twhi;
+        a2.twlo = p->twlo;
+        a2.hbits = p->hbits;
+        a2.chirp_a = p->chirp_a;
+        a2.f0 = p->f0;
+        a2.df = p->df;
+        a2.scale = k2_scale;
+        e = timed(1, nb, [&] { return launch_k2(p->precision, p->log2n1, a2, stream); });
+        if (e != hipSuccess) return fail(e);
+
+        K3Args a3;
+        a3.work = p->work;
+        a3.nblocks = (int32_t)nb;
+        a3.log2n1 = p->log2n1;
+        a3.hop = hop;
+        a3.n_front = p->n_front;
+        a3.block0 = b;
+        a3.tw2 = p->tw2;
+        a3.scale = k3_scale;
+        a3.series = want_series ? series : nullptr;
+        a3.series_base = m_before / decim;
+        a3.decim = decim;
+        a3.nbins = nbins;
+        a3.inv_pfs = p->inv_pfs;
+        a3.subint = subint;
+        a3.s_base = s_lo;
+        a3.entries = (int32_t)entries;
+        a3.global_mode = global_mode ? 1 : 0;
+        a3.part_sum = p->part_sum;
+        a3.part_cnt = p->part_cnt;
+        a3.acc_sum = p->acc_sum;
+        a3.acc_cnt = p->acc_cnt;
+        a3.acc_s0 = s_open;
+        a3.status = reinterpret_cast<uint32_t*>(p->status);
+        const size_t dyn = global_mode ? 0 : (size_t)entries * 12;
+        const int64_t items = nb * (n1 / 16);
+        int64_t grid = kCus * k3_wg_per_cu(k3_static_lds(n2log) + dyn);
+        if (grid > p->k3_grid_max) grid = p->k3_grid_max;
+        if (!global_mode && grid * entries > kPartEntries) grid = kPartEntries / entries;
+        const int64_t items8 = (items + 7) & ~int64_t(7);
+        if (grid > items8) grid = items8;
+        grid &= ~int64_t(7);
+        if (grid < 8) grid = 8;
+        e = timed(2, nb, [&] { return launch_k3(p->precision, n2log, a3, (int)grid, dyn, stream); });
+        if (e != hipSuccess) return fail(e);
+        if (!global_mode) {
+            e = timed(3, nb, [&] {
+                return launch_fold_reduce(p->part_sum, p->part_cnt, (int)grid, (int)entries, p->acc_sum, p->acc_cnt,
+                                          (s_lo - s_open) * nbins, stream);
+            });
+            if (e != hipSuccess) return fail(e);
+        }
+        b += nb;
+    }
+
+    if (n_complete > 0) {
+        e = timed(4, 0, [&] {
+            return launch_fold_finalize(p->acc_sum, p->acc_cnt, nbins, (int)n_complete, (int)n_touched, profiles,
+                                        stream);
+        });
+        if (e != hipSuccess) return fail(e);
+    }
+
+    // Keep the samples future blocks need: absolute [nb_total * hop, total).
+    const int64_t new_start = nb_total * hop;
+    int8_t* dst = p->tail[p->tcur ^ 1];
+    int64_t filled = 0;
+    if (p->samples_in > new_start) {
+        const int64_t from = new_start > p->tail_start ? new_start : p->tail_start;
+        const int64_t cnt = p->samples_in - from;
+        if (cnt > 0) {
+            e = hipMemcpyAsync(dst, p->tail[p->tcur] + 2 * (from - p->tail_start), (size_t)cnt * 2,
+                               hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return fail(e);
+            filled = cnt;
+        }
+    }
+    {
+        const int64_t from = new_start > p->samples_in ? new_start : p->samples_in;
+        const int64_t cnt = total - from;
+        if (cnt > 0) {
+            e = hipMemcpyAsync(dst + 2 * filled, iq + 2 * (from - p->samples_in), (size_t)cnt * 2,
+                               hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return fail(e);
+        }
+    }
+    p->tcur ^= 1;
+    p->tail_start = new_start;
+    p->samples_in = total;
+    p->blocks_done = nb_total;
+    p->subint = subint;
+    p->last_stream = stream;
+    if (n_series_out) *n_series_out = want_series ? groups : 0;
+    return n_complete;
+}
+
+int64_t pond_dedisperse_fold(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t subint_nsamp, float* profiles,
+                             int64_t max_profiles, void* hip_stream) {
+    return run_call(p, iq, nsamp, subint_nsamp, profiles, max_profiles, 16, nullptr, 0, nullptr, false, hip_stream);
+}
+
+int64_t pond_dedisperse_series(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t subint_nsamp, float* profiles,
+                               int64_t max_profiles, int32_t decim, float* series, int64_t series_cap,
+                               int64_t* n_series_out, void* hip_stream) {
+    return run_call(p, iq, nsamp, subint_nsamp, profiles, max_profiles, decim, series, series_cap, n_series_out, true,
+                    hip_stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal interface between the host runtime (pond_api.cpp) and the HIP
+// kernels (pond_kernels.hip).  Plain structs of pointers and sizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pond {
+
+// Fixed-point scale of the fold accumulators: a power p is accumulated as
+// round(p * 2^16) in an unsigned 64-bit integer, so sums are exact and
+// independent of the order in which workgroups add them.
+constexpr double kFoldScale = 65536.0;
+constexpr double kFoldRangeLimit = 1099511627776.0;  // 2^40: flag larger single contributions
+
+enum Precision { kFp32 = 0, kMixed = 1 };
+
+// K1: int8 unpack + forward column FFTs (length n2, stride n1).
+struct K1Args {
+    const int8_t* tail;     // device ring holding absolute samples [tail_start, in_start)
+    int64_t tail_start;
+    const int8_t* in;       // this call's samples, absolute [in_start, ...)
+    int64_t in_start;
+    int64_t hop;
+    int64_t block0;         // absolute index of the launch's first block
+    int32_t nblocks;
+    int32_t log2n1;
+    void* work;             // [nblocks][n2][n1] complex, storage type of the form
+    const float2* tw2;      // exp(-2 pi i t / n2), t < n2
+    float scale;            // power-of-two output scale
+};
+
+// K2: four-step twiddle, forward row FFT (length n1), chirp, inverse row
+// FFT, conjugate twiddle.
+struct K2Args {
+    void* work;
+    int64_t rows;           // nblocks * n2
+    int32_t log2n2;
+    int32_t log2n;
+    const float2* tw1;      // exp(-2 pi i t / n1), t < n1
+    const float2* twhi;     // exp(-2 pi i (t << hbits) / n)
+    const float2* twlo;     // exp(-2 pi i t / n), t < 2^hbits
+    int32_t hbits;
+    double chirp_a;         // dm / (2.41e-10 f0^2)
+    double f0;              // MHz
+    double df;              // bw / n, MHz per bin
+    float scale;            // power-of-two scale applied on output
+};
+
+// K3: inverse column FFTs, detection, decimation, fold partials.
+struct K3Args {
+    const void* work;
+    int32_t nblocks;
+    int32_t log2n1;
+    int64_t hop;
+    int64_t n_front;
+    int64_t block0;
+    const float2* tw2;
+    float scale;            // power-of-two scale of the inverse column output
+    // series
+    float* series;          // NULL: no series this call
+    int64_t series_base;    // group index (in units of decim) of series[0]
+    int32_t decim;
+    // fold
+    int32_t nbins;
+    double inv_pfs;
+    int64_t subint;         // outputs per sub-integration, 0 = one open-ended
+    int64_t s_base;         // first sub-integration this launch can touch
+    int32_t entries;        // (sub-integrations spanned) * nbins
+    int32_t global_mode;    // 1: atomics straight into acc (histogram too big for LDS)
+    uint64_t* part_sum;     // [grid][entries]
+    uint32_t* part_cnt;
+    uint64_t* acc_sum;      // global accumulators, slot-major [slot][nbins]
+    uint64_t* acc_cnt;
+    int64_t acc_s0;         // sub-integration held by accumulator slot 0
+    uint32_t* status;
+};
+
+// Launchers; each returns the HIP error of the launch.
+hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s);
+hipError_t launch_k2(int prec, int log2n1, const K2Args& a, hipStream_t s);
+hipError_t launch_k3(int prec, int log2n2, const K3Args& a, int grid, size_t dyn_lds, hipStream_t s);
+hipError_t launch_fold_reduce(const uint64_t* part_sum, const uint32_t* part_cnt, int nparts, int entries,
+                              uint64_t* acc_sum, uint64_t* acc_cnt, int64_t acc_off, hipStream_t s);
+hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins, int n_complete, int n_touched,
+                                float* profiles, hipStream_t s);
+hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s);
+
+// Static LDS bytes of the K3 tile for a column length 2^log2n2.
+size_t k3_static_lds(int log2n2);
+// Threads per workgroup of each kernel.
+int k1_threads(int log2n2);
+int k2_threads(int log2n1);
+int k3_threads(int log2n2);
+
+}  // namespace pond

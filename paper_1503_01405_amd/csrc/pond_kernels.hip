@@ -1,0 +1,461 @@
+// HIP kernels of the coherent-dedispersion + fold path (gfx950).
+//
+// One overlap-save block of n = n1 * n2 samples is transformed with the
+// four-step factorisation (input index n = n1_ + n1 * n2_, spectrum index
+// k = k2 + n2 * k1):
+//   K1  column FFTs of length n2 over the int8 input (stride n1), written as
+//       rows [k2][n1];
+//   K2  per row k2: twiddle W_n^(n1_ k2), forward row FFT of length n1,
+//       multiply bin k by the inverse ISM response exp(-2 pi i turns_k)
+//       (Sec. 3.7, Eq. (4); turns in float64 reduced mod 1 before the
+//       float32 sine/cosine), inverse row FFT, twiddle W_n^-(n1_ k2);
+//   K3  inverse column FFTs of length n2, 1/n scaling, |y|^2 (square-law
+//       detection), sums of `decim` consecutive powers (the integrated time
+//       series of Sec. 4) and the fold of every kept output into
+//       (sub-integration, bin) accumulators (Sec. 3.4.1 / Sec. 3.7).
+// Only K1 reads the input and only K3 produces outputs, so one block costs
+// three passes over its complex intermediate.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "pond_fft.hpp"
+#include "pond_internal.hpp"
+
+namespace pond {
+
+// --------------------------------------------------------- storage forms
+template <class T>
+struct Elem;
+template <>
+struct Elem<float2> {
+    __device__ __forceinline__ static float2 load(const float2* p) { return *p; }
+    __device__ __forceinline__ static void store(float2* p, float2 v) { *p = v; }
+};
+template <>
+struct Elem<__half2> {
+    __device__ __forceinline__ static float2 load(const __half2* p) { return __half22float2(*p); }
+    __device__ __forceinline__ static void store(__half2* p, float2 v) { *p = __float22half2_rn(v); }
+};
+
+// ------------------------------------------------------------------- K1
+template <int LOG2N2, class T>
+__global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
+    constexpr int L = 1 << LOG2N2;
+    constexpr int TPV = L / 16;
+    __shared__ float2 lds[16 * L];
+
+    const int n1 = 1 << a.log2n1;
+    const int tiles_per_block = n1 >> 4;
+    const int ntiles = a.nblocks * tiles_per_block;
+    const int tile = xcd_logical(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int b = tile / tiles_per_block;
+    const int t = tile - b * tiles_per_block;
+    const int c = threadIdx.x & 15;
+    const int j = threadIdx.x >> 4;
+    const int col = 16 * t + c;
+
+    const int64_t start = (a.block0 + b) * a.hop + col;  // absolute sample of row 0
+    float2 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int64_t abs = start + ((int64_t)(j + TPV * e) << a.log2n1);
+        const int8_t* p = abs < a.in_start ? a.tail + 2 * (abs - a.tail_start) : a.in + 2 * (abs - a.in_start);
+        const short s = *reinterpret_cast<const short*>(p);
+        v[e] = make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)(s >> 8));
+    }
+    fft_wg<LOG2N2, -1>(
+        v, j, a.tw2, [&](int pos) { return lds[pos * 16 + c]; },
+        [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
+
+    T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2)) + col;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int k2 = j + TPV * e;
+        Elem<T>::store(out + ((int64_t)k2 << a.log2n1), cscale(v[e], a.scale));
+    }
+}
+
+// ------------------------------------------------------------------- K2
+template <int LOG2N1>
+struct K2Shape {
+    static constexpr int L = 1 << LOG2N1;
+    static constexpr int TPV = L / 16;
+    static constexpr int ROWS = TPV >= 256 ? 1 : 256 / TPV;
+    static constexpr int THREADS = ROWS * TPV;
+};
+
+__device__ __forceinline__ float2 fourstep_twiddle(const float2* __restrict__ hi, const float2* __restrict__ lo,
+                                                   uint32_t r, int hbits) {
+    return cmul(hi[r >> hbits], lo[r & ((1u << hbits) - 1u)]);
+}
+
+template <int LOG2N1, class T>
+__global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS) k2_row(K2Args a) {
+    using Sh = K2Shape<LOG2N1>;
+    constexpr int L = Sh::L;
+    constexpr int TPV = Sh::TPV;
+    __shared__ float2 lds[Sh::ROWS * L];
+
+    const int r = threadIdx.x / TPV;
+    const int j = threadIdx.x - r * TPV;
+    const int64_t row = (int64_t)blockIdx.x * Sh::ROWS + r;
+    const bool valid = row < a.rows;
+    const uint32_t k2 = (uint32_t)(row & ((1 << a.log2n2) - 1));
+    const uint32_t nmask = (1u << a.log2n) - 1u;
+    T* rowp = reinterpret_cast<T*>(a.work) + (valid ? (row << LOG2N1) : 0);
+    float2* my = lds + r * L;
+
+    float2 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int pos = j + TPV * e;
+        float2 x = valid ? Elem<T>::load(rowp + pos) : make_float2(0.f, 0.f);
+        const float2 w = fourstep_twiddle(a.twhi, a.twlo, ((uint32_t)pos * k2) & nmask, a.hbits);
+        v[e] = cmul(x, w);
+    }
+    auto ld = [&](int pos) { return my[pos]; };
+    auto st = [&](int pos, float2 x) { my[pos] = x; };
+    fft_wg<LOG2N1, -1>(v, j, a.tw1, ld, st);
+
+    // v[e] is spectrum bin k = k2 + n2 * k1 with k1 = j + TPV e.
+    const int64_t n = 1ll << a.log2n;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int64_t k1 = j + TPV * e;
+        const int64_t k = (int64_t)k2 + (k1 << a.log2n2);
+        const int64_t kk = k < (n >> 1) ? k : k - n;
+        const double f = (double)kk * a.df;
+        const double turns = a.chirp_a * (f * f) / (a.f0 + f);
+        const double frac = turns - rint(turns);
+        float sn, cs;
+        sincospif(2.0f * (float)frac, &sn, &cs);
+        v[e] = cmul(v[e], make_float2(cs, -sn));
+    }
+    fft_wg<LOG2N1, +1>(v, j, a.tw1, ld, st);
+
+    if (valid) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int pos = j + TPV * e;
+            const float2 w = fourstep_twiddle(a.twhi, a.twlo, ((uint32_t)pos * k2) & nmask, a.hbits);
+            Elem<T>::store(rowp + pos, cscale(cmulc(v[e], w), a.scale));
+        }
+    }
+}
+
+// ------------------------------------------------------------------- K3
+template <int LOG2N2>
+struct K3Shape {
+    static constexpr int L = 1 << LOG2N2;
+    static constexpr int TPV = L / 16;
+    static constexpr int THREADS = L;
+    static constexpr size_t LDS = sizeof(float2) * 16 * L;
+};
+
+__device__ __forceinline__ float xor_sum(float v, int mask) { return v + __shfl_xor(v, mask, 16); }
+
+template <int LOG2N2, class T>
+__global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
+    using Sh = K3Shape<LOG2N2>;
+    constexpr int L = Sh::L;
+    constexpr int TPV = Sh::TPV;
+    __shared__ float2 lds[16 * L];
+    extern __shared__ uint64_t dyn_u64[];
+    uint64_t* hsum = dyn_u64;
+    uint32_t* hcnt = reinterpret_cast<uint32_t*>(dyn_u64 + (a.global_mode ? 0 : a.entries));
+
+    const int c = threadIdx.x & 15;
+    const int j = threadIdx.x >> 4;
+    const int lane = threadIdx.x & 63;
+    const int n1 = 1 << a.log2n1;
+    const int tiles_per_block = n1 >> 4;
+    const int items = a.nblocks * tiles_per_block;
+    const int r0 = (int)(a.n_front & 15);
+
+    if (!a.global_mode) {
+        for (int i = threadIdx.x; i < a.entries; i += blockDim.x) {
+            hsum[i] = 0;
+            hcnt[i] = 0;
+        }
+    }
+    // Items are split into 8 contiguous chunks, one per XCD, so that the
+    // workgroups running together on one XCD handle neighbouring tiles.
+    const int per_xcd = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7;
+    const int local = blockIdx.x >> 3;
+    const int chunk = (items + 7) >> 3;
+    const int it_end = min(items, (xcd + 1) * chunk);
+    uint32_t flags = 0;
+
+    for (int item = xcd * chunk + local; item < it_end; item += per_xcd) {
+        const int b = item / tiles_per_block;
+        const int t = item - b * tiles_per_block;
+        const int colu = r0 + 16 * t + c;           // unwrapped column of lane c
+        const int col = colu & (n1 - 1);
+        const int shift = colu >> a.log2n1;          // 1 for wrapped columns of the last tile
+        const bool wrap_tile = (r0 + 16 * t + 15) >= n1;
+
+        const T* in = reinterpret_cast<const T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2)) + col;
+        float2 v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = Elem<T>::load(in + ((int64_t)(j + TPV * e) << a.log2n1));
+        fft_wg<LOG2N2, +1>(
+            v, j, a.tw2, [&](int pos) { return lds[pos * 16 + c]; },
+            [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
+
+        float p[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float2 y = cscale(v[e], a.scale);
+            p[e] = fmaf(y.x, y.x, y.y * y.y);
+        }
+        if (wrap_tile) {
+            // Lanes of wrapped columns hold the output of the next row.
+            float* pf = reinterpret_cast<float*>(lds);
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 16; ++e) pf[(j + TPV * e) * 16 + c] = p[e];
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int rsrc = j + TPV * e + shift;
+                p[e] = rsrc < L ? pf[rsrc * 16 + c] : 0.f;
+            }
+        }
+
+        const int64_t blk_out0 = (a.block0 + b) * a.hop;  // output index of this block's first kept output
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int q = j + TPV * e;
+            const int64_t nstart = (int64_t)(r0 + 16 * t) + ((int64_t)q << a.log2n1);
+            const int64_t off = nstart - a.n_front;
+            const bool valid = off >= 0 && off < a.hop;
+            const int64_t m0 = blk_out0 + off;     // output index of lane 0 of the group
+            const float pv = p[e];
+            const float s2 = xor_sum(pv, 1);
+            const float s4 = xor_sum(s2, 2);
+            const float s8 = xor_sum(s4, 4);
+            const float s16 = xor_sum(s8, 8);
+            if (!isfinite(pv)) flags |= 1u;
+            if (a.series && valid && (c & (a.decim - 1)) == 0) {
+                const float sd = a.decim == 1 ? pv : a.decim == 2 ? s2 : a.decim == 4 ? s4 : a.decim == 8 ? s8 : s16;
+                a.series[(m0 + c) / a.decim - a.series_base] = sd;
+            }
+            // fold: bin and sub-integration of this lane's own output
+            const int64_t m = m0 + c;
+            const double x = (double)(m + a.n_front) * a.inv_pfs;
+            const double fr = x - floor(x);
+            int bin = (int)(fr * (double)a.nbins);
+            bin = bin < a.nbins - 1 ? bin : a.nbins - 1;
+            const int64_t sub = a.subint > 0 ? m / a.subint : 0;
+            const int key = (int)(sub - a.s_base) * a.nbins + bin;
+            const int key0 = __shfl(key, lane & 48, 64);
+            const uint64_t bal = __ballot(key == key0);
+            const bool same = ((bal >> (lane & 48)) & 0xffffull) == 0xffffull;
+            if (valid) {
+                float val;
+                uint32_t cnt;
+                bool act;
+                if (same) {
+                    val = s16;
+                    cnt = 16;
+                    act = (c == 0);
+                } else {
+                    val = pv;
+                    cnt = 1;
+                    act = true;
+                }
+                if (act) {
+                    const double dv = (double)val * kFoldScale;
+                    if (!(dv < kFoldRangeLimit * kFoldScale)) flags |= 2u;
+                    const uint64_t fx = isfinite(val) ? (uint64_t)__double2ull_rn(dv) : 0ull;
+                    if (a.global_mode) {
+                        const int64_t gk = (sub - a.acc_s0) * a.nbins + bin;
+                        atomicAdd((unsigned long long*)&a.acc_sum[gk], (unsigned long long)fx);
+                        atomicAdd((unsigned long long*)&a.acc_cnt[gk], (unsigned long long)cnt);
+                    } else {
+                        atomicAdd((unsigned long long*)&hsum[key], (unsigned long long)fx);
+                        atomicAdd(&hcnt[key], cnt);
+                    }
+                }
+            }
+        }
+    }
+    if (flags) atomicOr(a.status, flags);
+    if (!a.global_mode) {
+        __syncthreads();
+        uint64_t* ps = a.part_sum + (int64_t)blockIdx.x * a.entries;
+        uint32_t* pc = a.part_cnt + (int64_t)blockIdx.x * a.entries;
+        for (int i = threadIdx.x; i < a.entries; i += blockDim.x) {
+            ps[i] = hsum[i];
+            pc[i] = hcnt[i];
+        }
+    }
+}
+
+// ------------------------------------------------------ fold reduction
+// Sum the per-workgroup partial histograms (integer, so order-free) and
+// add them to the accumulators.  Grid: x over entries, y over part chunks.
+constexpr int kReduceChunk = 32;
+__global__ void __launch_bounds__(256) fold_reduce(const uint64_t* __restrict__ ps, const uint32_t* __restrict__ pc,
+                                                   int nparts, int entries, uint64_t* acc_sum, uint64_t* acc_cnt,
+                                                   int64_t acc_off) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= entries) return;
+    const int p0 = blockIdx.y * kReduceChunk;
+    const int p1 = min(nparts, p0 + kReduceChunk);
+    uint64_t s = 0, n = 0;
+    for (int q = p0; q < p1; ++q) {
+        s += ps[(int64_t)q * entries + i];
+        n += pc[(int64_t)q * entries + i];
+    }
+    if (n) {
+        atomicAdd((unsigned long long*)&acc_sum[acc_off + i], (unsigned long long)s);
+        atomicAdd((unsigned long long*)&acc_cnt[acc_off + i], (unsigned long long)n);
+    }
+}
+
+// Write the profiles of the first n_complete slots, then move slot
+// n_complete (the still-open sub-integration, if any) to slot 0 and clear
+// the rest of the n_touched slots.  One thread per bin.
+__global__ void __launch_bounds__(256) fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins, int n_complete,
+                                                     int n_touched, float* profiles) {
+    const int bin = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bin >= nbins) return;
+    for (int k = 0; k < n_complete; ++k) {
+        const uint64_t s = acc_sum[(int64_t)k * nbins + bin];
+        const uint64_t n = acc_cnt[(int64_t)k * nbins + bin];
+        profiles[(int64_t)k * nbins + bin] = n ? (float)(((double)s / kFoldScale) / (double)n) : 0.f;
+    }
+    if (n_complete > 0) {
+        uint64_t cs = 0, cn = 0;
+        if (n_complete < n_touched) {
+            cs = acc_sum[(int64_t)n_complete * nbins + bin];
+            cn = acc_cnt[(int64_t)n_complete * nbins + bin];
+        }
+        acc_sum[bin] = cs;
+        acc_cnt[bin] = cn;
+        for (int k = 1; k < n_touched; ++k) {
+            acc_sum[(int64_t)k * nbins + bin] = 0;
+            acc_cnt[(int64_t)k * nbins + bin] = 0;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) zero_u64(uint64_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------- launchers
+template <class T, int LOG2N2>
+static hipError_t k1_one(const K1Args& a, hipStream_t s) {
+    const int ntiles = a.nblocks * ((1 << a.log2n1) >> 4);
+    const int grid = (ntiles + 7) & ~7;
+    hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t k1_dispatch(int log2n2, const K1Args& a, hipStream_t s) {
+    switch (log2n2) {
+        case 5: return k1_one<T, 5>(a, s);
+        case 6: return k1_one<T, 6>(a, s);
+        case 7: return k1_one<T, 7>(a, s);
+        case 8: return k1_one<T, 8>(a, s);
+        case 9: return k1_one<T, 9>(a, s);
+        case 10: return k1_one<T, 10>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s) {
+    return prec == kMixed ? k1_dispatch<__half2>(log2n2, a, s) : k1_dispatch<float2>(log2n2, a, s);
+}
+
+template <class T, int LOG2N1>
+static hipError_t k2_one(const K2Args& a, hipStream_t s) {
+    using Sh = K2Shape<LOG2N1>;
+    const int64_t grid = (a.rows + Sh::ROWS - 1) / Sh::ROWS;
+    hipLaunchKernelGGL((k2_row<LOG2N1, T>), dim3((unsigned)grid), dim3(Sh::THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t k2_dispatch(int log2n1, const K2Args& a, hipStream_t s) {
+    switch (log2n1) {
+        case 5: return k2_one<T, 5>(a, s);
+        case 6: return k2_one<T, 6>(a, s);
+        case 7: return k2_one<T, 7>(a, s);
+        case 8: return k2_one<T, 8>(a, s);
+        case 9: return k2_one<T, 9>(a, s);
+        case 10: return k2_one<T, 10>(a, s);
+        case 11: return k2_one<T, 11>(a, s);
+        case 12: return k2_one<T, 12>(a, s);
+        case 13: return k2_one<T, 13>(a, s);
+        case 14: return k2_one<T, 14>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_k2(int prec, int log2n1, const K2Args& a, hipStream_t s) {
+    return prec == kMixed ? k2_dispatch<__half2>(log2n1, a, s) : k2_dispatch<float2>(log2n1, a, s);
+}
+
+template <class T, int LOG2N2>
+static hipError_t k3_one(const K3Args& a, int grid, size_t dyn, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k3_colinv_detect_fold<LOG2N2, T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(160 * 1024 - K3Shape<LOG2N2>::LDS));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k3_colinv_detect_fold<LOG2N2, T>), dim3(grid), dim3(1 << LOG2N2), dyn, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t k3_dispatch(int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s) {
+    switch (log2n2) {
+        case 5: return k3_one<T, 5>(a, grid, dyn, s);
+        case 6: return k3_one<T, 6>(a, grid, dyn, s);
+        case 7: return k3_one<T, 7>(a, grid, dyn, s);
+        case 8: return k3_one<T, 8>(a, grid, dyn, s);
+        case 9: return k3_one<T, 9>(a, grid, dyn, s);
+        case 10: return k3_one<T, 10>(a, grid, dyn, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_k3(int prec, int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s) {
+    return prec == kMixed ? k3_dispatch<__half2>(log2n2, a, grid, dyn, s) : k3_dispatch<float2>(log2n2, a, grid, dyn, s);
+}
+
+hipError_t launch_fold_reduce(const uint64_t* ps, const uint32_t* pc, int nparts, int entries, uint64_t* acc_sum,
+                              uint64_t* acc_cnt, int64_t acc_off, hipStream_t s) {
+    dim3 grid((entries + 255) / 256, (nparts + kReduceChunk - 1) / kReduceChunk);
+    hipLaunchKernelGGL(fold_reduce, grid, dim3(256), 0, s, ps, pc, nparts, entries, acc_sum, acc_cnt, acc_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins, int n_complete, int n_touched,
+                                float* profiles, hipStream_t s) {
+    hipLaunchKernelGGL(fold_finalize, dim3((nbins + 255) / 256), dim3(256), 0, s, acc_sum, acc_cnt, nbins,
+                       n_complete, n_touched, profiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+size_t k3_static_lds(int log2n2) { return sizeof(float2) * 16 * ((size_t)1 << log2n2); }
+int k1_threads(int log2n2) { return 1 << log2n2; }
+int k3_threads(int log2n2) { return 1 << log2n2; }
+int k2_threads(int log2n1) {
+    const int tpv = (1 << log2n1) / 16;
+    return tpv >= 256 ? tpv : 256;
+}
+
+}  // namespace pond

@@ -1,0 +1,246 @@
+"""ctypes binding of libpond.so (include/pond.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device buffers are passed as torch CUDA tensors (their data_ptr())
+and streams as torch.cuda.Stream objects (their cuda_stream handle).  If
+the library has not been built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpond.so")
+
+POND_OK = 0
+POND_EINVAL = -1
+POND_ENOMEM = -2
+POND_EDEVICE = -3
+
+POND_FP32 = 0
+POND_MIXED = 1
+
+POND_STATUS_NONFINITE = 1
+POND_STATUS_RANGE = 2
+
+EXPORTS = (
+    "pond_plan_create", "pond_plan_create_ex", "pond_create_status",
+    "pond_dedisperse_fold", "pond_dedisperse_series", "pond_plan_query",
+    "pond_plan_expect", "pond_plan_destroy", "pond_strerror",
+    "pond_plan_set_timing", "pond_plan_kernel_times",
+)
+KERNEL_NAMES = ("k1_unpack_colfft", "k2_row", "k3_colinv_detect_fold", "fold_reduce", "fold_finalize")
+
+
+class PondError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = int(code)
+        msg = _lib.pond_strerror(int(code)).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+class pond_info(ctypes.Structure):
+    _fields_ = [
+        ("nfft", ctypes.c_int64), ("n_front", ctypes.c_int64),
+        ("discard", ctypes.c_int64), ("hop", ctypes.c_int64),
+        ("n1", ctypes.c_int64), ("n2", ctypes.c_int64),
+        ("samples_in", ctypes.c_int64), ("outputs_done", ctypes.c_int64),
+        ("max_batch", ctypes.c_int64),
+        ("fs_hz", ctypes.c_double), ("delta_lo_s", ctypes.c_double),
+        ("delta_hi_s", ctypes.c_double), ("inv_pfs", ctypes.c_double),
+        ("nbins", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("status", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class pond_kernel_times(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5),
+                ("blocks", ctypes.c_int64 * 5)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python paper_1503_01405_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.pond_plan_create.argtypes = [dbl, dbl, dbl, i64, i32, dbl]
+    lib.pond_plan_create.restype = P
+    lib.pond_plan_create_ex.argtypes = [dbl, dbl, dbl, i64, i32, dbl, i32, i32]
+    lib.pond_plan_create_ex.restype = P
+    lib.pond_create_status.argtypes = []
+    lib.pond_create_status.restype = i32
+    lib.pond_dedisperse_fold.argtypes = [P, P, i64, i64, P, i64, P]
+    lib.pond_dedisperse_fold.restype = i64
+    lib.pond_dedisperse_series.argtypes = [P, P, i64, i64, P, i64, i32, P, i64,
+                                           ctypes.POINTER(i64), P]
+    lib.pond_dedisperse_series.restype = i64
+    lib.pond_plan_query.argtypes = [P, ctypes.POINTER(pond_info)]
+    lib.pond_plan_query.restype = i32
+    lib.pond_plan_expect.argtypes = [P, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.pond_plan_expect.restype = i32
+    lib.pond_plan_destroy.argtypes = [P]
+    lib.pond_plan_destroy.restype = None
+    lib.pond_plan_set_timing.argtypes = [P, i32]
+    lib.pond_plan_set_timing.restype = i32
+    lib.pond_plan_kernel_times.argtypes = [P, ctypes.POINTER(pond_kernel_times)]
+    lib.pond_plan_kernel_times.restype = i32
+    lib.pond_strerror.argtypes = [i64]
+    lib.pond_strerror.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = None
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _ptr(t):
+    """Device address of a tensor (or None/int)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------- C-ABI-named wrappers
+def pond_plan_create(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision=POND_FP32, max_batch=0):
+    """Create a plan; returns the opaque handle (int).  Raises PondError."""
+    h = _lib.pond_plan_create_ex(float(f0_mhz), float(bw_mhz), float(dm), int(nfft), int(nbins),
+                                 float(period_s), int(precision), int(max_batch))
+    if not h:
+        raise PondError(_lib.pond_create_status(), "pond_plan_create")
+    return h
+
+
+def pond_dedisperse_fold(plan, iq, nsamp, subint_nsamp, profiles, max_profiles, stream=None):
+    return _lib.pond_dedisperse_fold(plan, _ptr(iq), int(nsamp), int(subint_nsamp), _ptr(profiles),
+                                     int(max_profiles), _stream(stream))
+
+
+def pond_dedisperse_series(plan, iq, nsamp, subint_nsamp, profiles, max_profiles, decim, series,
+                           series_cap, stream=None):
+    """Returns (profiles written or error code, series values written)."""
+    n = ctypes.c_int64(0)
+    r = _lib.pond_dedisperse_series(plan, _ptr(iq), int(nsamp), int(subint_nsamp), _ptr(profiles),
+                                    int(max_profiles), int(decim), _ptr(series), int(series_cap),
+                                    ctypes.byref(n), _stream(stream))
+    return r, n.value
+
+
+def pond_plan_query(plan):
+    info = pond_info()
+    r = _lib.pond_plan_query(plan, ctypes.byref(info))
+    if r != POND_OK:
+        raise PondError(r, "pond_plan_query")
+    return {name: getattr(info, name) for name, _ in pond_info._fields_}
+
+
+def pond_plan_expect(plan, nsamp, subint_nsamp):
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    r = _lib.pond_plan_expect(plan, int(nsamp), int(subint_nsamp), ctypes.byref(a), ctypes.byref(b))
+    if r != POND_OK:
+        raise PondError(r, "pond_plan_expect")
+    return a.value, b.value
+
+
+def pond_plan_destroy(plan):
+    _lib.pond_plan_destroy(plan)
+
+
+def pond_plan_set_timing(plan, enable):
+    r = _lib.pond_plan_set_timing(plan, int(bool(enable)))
+    if r != POND_OK:
+        raise PondError(r, "pond_plan_set_timing")
+
+
+def pond_plan_kernel_times(plan):
+    """{kernel name: (ms, launches, blocks)} since timing was enabled."""
+    t = pond_kernel_times()
+    r = _lib.pond_plan_kernel_times(plan, ctypes.byref(t))
+    if r != POND_OK:
+        raise PondError(r, "pond_plan_kernel_times")
+    return {KERNEL_NAMES[i]: (t.ms[i], t.launches[i], t.blocks[i]) for i in range(5)}
+
+
+# ------------------------------------------------------- convenience class
+class Plan:
+    """A dedispersion + fold plan on the current torch device.
+
+    ``process(iq)`` appends a device int8 I/Q tensor and returns the
+    profiles completed by the call (float32, [k, nbins]) and, if asked, the
+    new decimated series values; ``flush()`` ends the stream and returns the
+    open sub-integration's profile.  Output tensors are allocated with torch
+    on the plan's device.
+    """
+
+    def __init__(self, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision="fp32",
+                 max_batch=0, subint_nsamp=0, decim=16):
+        prec = {"fp32": POND_FP32, "mixed": POND_MIXED}.get(precision, precision)
+        self.handle = pond_plan_create(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, prec, max_batch)
+        self.nbins = int(nbins)
+        self.subint = int(subint_nsamp)
+        self.decim = int(decim)
+
+    def info(self):
+        return pond_plan_query(self.handle)
+
+    def process(self, iq, want_series=True, stream=None):
+        import torch
+        nsamp = iq.numel() // 2
+        if nsamp == 0:   # a NULL/0 call would end the stream
+            empty = torch.empty((0, self.nbins), dtype=torch.float32, device=iq.device)
+            return empty, (torch.empty(0, dtype=torch.float32, device=iq.device) if want_series else None)
+        nprof, nout = pond_plan_expect(self.handle, nsamp, self.subint)
+        prof = torch.empty((max(nprof, 0), self.nbins), dtype=torch.float32, device=iq.device)
+        if want_series:
+            ser = torch.empty(nout // self.decim, dtype=torch.float32, device=iq.device)
+            r, ns = pond_dedisperse_series(self.handle, iq, nsamp, self.subint, prof, nprof,
+                                           self.decim, ser, ser.numel(), stream)
+        else:
+            ser, ns = None, 0
+            r = pond_dedisperse_fold(self.handle, iq, nsamp, self.subint, prof, nprof, stream)
+        if r < 0:
+            raise PondError(r, "process")
+        return prof[:r], (ser[:ns] if ser is not None else None)
+
+    def flush(self, device=None, stream=None):
+        import torch
+        nprof, _ = pond_plan_expect(self.handle, 0, self.subint)
+        prof = torch.empty((nprof, self.nbins), dtype=torch.float32,
+                           device=device if device is not None else torch.device("cuda"))
+        r = pond_dedisperse_fold(self.handle, None, 0, self.subint, prof, nprof, stream)
+        if r < 0:
+            raise PondError(r, "flush")
+        return prof[:r]
+
+    def close(self):
+        if self.handle:
+            pond_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -11,9 +11,10 @@ forward model and lives there.
 
 Recipe (one stream):
   * each complex sample is I + iQ with I, Q independent N(0, sigma^2),
-    sigma = 20, drawn from numpy's PCG64 ``default_rng(seed)`` as
-    ``standard_normal((n, 2))`` in chunks (the draw sequence does not depend
-    on the chunking);
+    sigma = 20.  Samples are drawn in chunks of 2^22: chunk c (samples
+    [c 2^22, (c+1) 2^22)) comes from ``standard_normal((n, 2))`` of a numpy
+    Generator on ``PCG64(seed).jumped(c)``, so chunks can be drawn in
+    parallel and any sample range is reproducible on its own;
   * a pulse of Gaussian shape (full width at half maximum ``fwhm_s``) centred
     at rotational phase ``phase0`` multiplies the noise amplitude by
     sqrt(1 + peak * g(t)), so the expected power is (1 + peak * g) times the
@@ -24,6 +25,8 @@ Recipe (one stream):
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -35,7 +38,9 @@ FWHM_S = 1.0e-3       # pulse full width at half maximum
 PEAK = 3.0            # pulse peak power in units of the noise power
 PHASE0 = 0.5          # rotational phase of the pulse centre
 
-_CHUNK = 1 << 22
+_CHUNK_LOG2 = 22
+_CHUNK = 1 << _CHUNK_LOG2
+_THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
 def pulse_gain(sample_index, fs_hz, period_s=PERIOD_S, fwhm_s=FWHM_S,
@@ -58,15 +63,35 @@ def pulse_power_shape(sample_index, fs_hz, period_s=PERIOD_S, fwhm_s=FWHM_S,
     return pulse_gain(sample_index, fs_hz, period_s, fwhm_s, peak, phase0) ** 2
 
 
-def noise(seed: int, nsamp: int, sigma: float = SIGMA, chunk: int = _CHUNK):
+def _chunk_normals(seed: int, c: int, n: int):
+    """The first n (I, Q) standard-normal pairs of chunk c."""
+    g = np.random.Generator(np.random.PCG64(seed).jumped(c))
+    return g.standard_normal((n, 2))
+
+
+def _for_chunks(nsamp: int, fn):
+    """Call fn(c, start, stop) for every chunk overlapping [0, nsamp), on a
+    thread pool (numpy's generators and ufuncs release the GIL)."""
+    nch = (nsamp + _CHUNK - 1) >> _CHUNK_LOG2
+    spans = [(c, c << _CHUNK_LOG2, min(nsamp, (c + 1) << _CHUNK_LOG2)) for c in range(nch)]
+    if len(spans) <= 1 or _THREADS == 1:
+        for sp in spans:
+            fn(*sp)
+        return
+    with ThreadPoolExecutor(_THREADS) as ex:
+        list(ex.map(lambda sp: fn(*sp), spans))
+
+
+def noise(seed: int, nsamp: int, sigma: float = SIGMA):
     """Complex128 Gaussian noise I + iQ, each component N(0, sigma^2)."""
-    rng = np.random.default_rng(seed)
     out = np.empty(nsamp, dtype=np.complex128)
-    for s in range(0, nsamp, chunk):
-        e = min(nsamp, s + chunk)
-        d = rng.standard_normal((e - s, 2))
+
+    def fill(c, s, e):
+        d = _chunk_normals(seed, c, e - s)
         out[s:e].real = d[:, 0] * sigma
         out[s:e].imag = d[:, 1] * sigma
+
+    _for_chunks(nsamp, fill)
     return out
 
 
@@ -98,36 +123,37 @@ def quantize_int8(z):
 def pulsed_stream_int8(seed: int, nsamp: int, fs_hz: float = BW_MHZ * 1e6,
                        period_s: float = PERIOD_S, fwhm_s: float = FWHM_S,
                        peak: float = PEAK, phase0: float = PHASE0,
-                       sigma: float = SIGMA, chunk: int = _CHUNK):
+                       sigma: float = SIGMA):
     """Undispersed pulsed noise quantised to int8, built chunk by chunk.
 
     Equal to ``quantize_int8(pulsed_noise(seed, nsamp, ...))`` but never
-    holds more than one chunk in float64, so a 60 s stream (1.92 GB of int8)
-    can be built on a host with modest memory.
+    holds more than a few chunks in float64, so a 60 s stream (1.92 GB of
+    int8) can be built on a host with modest memory.
     """
-    rng = np.random.default_rng(seed)
     out = np.empty(2 * nsamp, dtype=np.int8)
-    for s in range(0, nsamp, chunk):
-        e = min(nsamp, s + chunk)
-        d = rng.standard_normal((e - s, 2))
+
+    def fill(c, s, e):
+        d = _chunk_normals(seed, c, e - s)
         gain = pulse_gain(np.arange(s, e, dtype=np.int64), fs_hz, period_s,
                           fwhm_s, peak, phase0)
         d *= (sigma * gain)[:, None]
         np.rint(d, out=d)
         np.clip(d, -128, 127, out=d)
         out[2 * s:2 * e] = d.astype(np.int8).reshape(-1)
+
+    _for_chunks(nsamp, fill)
     return out
 
 
-def white_stream_int8(seed: int, nsamp: int, sigma: float = SIGMA,
-                      chunk: int = _CHUNK):
+def white_stream_int8(seed: int, nsamp: int, sigma: float = SIGMA):
     """Pure noise quantised to int8 (no pulse)."""
-    rng = np.random.default_rng(seed)
     out = np.empty(2 * nsamp, dtype=np.int8)
-    for s in range(0, nsamp, chunk):
-        e = min(nsamp, s + chunk)
-        d = rng.standard_normal((e - s, 2)) * sigma
+
+    def fill(c, s, e):
+        d = _chunk_normals(seed, c, e - s) * sigma
         np.rint(d, out=d)
         np.clip(d, -128, 127, out=d)
         out[2 * s:2 * e] = d.astype(np.int8).reshape(-1)
+
+    _for_chunks(nsamp, fill)
     return out

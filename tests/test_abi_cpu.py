@@ -1,0 +1,60 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/pond.h declares, and rejects invalid plans before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pond.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pond_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_four_path_calls():
+    names = _declared()
+    for n in ("pond_plan_create", "pond_dedisperse_fold", "pond_dedisperse_series", "pond_plan_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1503_01405_amd.pond as B
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(_declared()) <= set(B.EXPORTS)
+
+
+@pytest.mark.parametrize("args", [
+    (326.5, 16.0, 1.0, (1 << 18) + 1, 256, 0.0891),   # nfft not a power of two
+    (326.5, 16.0, 1.0, 1 << 9, 256, 0.0891),          # nfft below 2^10
+    (326.5, 16.0, 1.0, 1 << 25, 256, 0.0891),         # nfft above 2^24
+    (326.5, 16.0, -1.0, 1 << 18, 256, 0.0891),        # negative DM
+    (326.5, 16.0, float("nan"), 1 << 18, 256, 0.0891),
+    (326.5, 0.0, 1.0, 1 << 18, 256, 0.0891),          # zero bandwidth
+    (5.0, 16.0, 1.0, 1 << 18, 256, 0.0891),           # band edge below 0 MHz
+    (326.5, 16.0, 1.0, 1 << 18, 0, 0.0891),           # no bins
+    (326.5, 16.0, 1.0, 1 << 18, 65537, 0.0891),       # too many bins
+    (326.5, 16.0, 1.0, 1 << 18, 256, 0.0),            # period
+    (326.5, 16.0, 1.0, 1 << 18, 256, 1e-9),           # period shorter than a sample
+    (326.5, 16.0, 200.0, 1 << 20, 256, 0.0891),       # smear longer than the FFT
+])
+def test_invalid_plans_are_rejected_before_device_work(args):
+    import paper_1503_01405_amd as P
+    with pytest.raises(P.PondError) as ei:
+        P.pond_plan_create(*args)
+    assert ei.value.code == P.POND_EINVAL
+
+
+def test_null_plan_calls():
+    import paper_1503_01405_amd.pond as B
+    lib = B.lib()
+    assert lib.pond_dedisperse_fold(None, None, 0, 0, None, 0, None) == B.POND_EINVAL
+    assert lib.pond_plan_query(None, None) == B.POND_EINVAL
+    assert lib.pond_plan_expect(None, 0, 0, None, None) == B.POND_EINVAL
+    lib.pond_plan_destroy(None)
+    assert lib.pond_strerror(B.POND_EDEVICE)

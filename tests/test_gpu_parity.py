@@ -1,0 +1,164 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (relative L2 error against the oracle):
+  float32 form: profiles 1e-6, series 1e-5
+  mixed form:   profiles 1e-4 (the stated accuracy target), series 1e-2
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import dispersed_pulsar_stream, gpu_run, oracle_run, profile_rel_l2, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": (1e-6, 1e-5), "mixed": (1e-4, 1e-2)}
+
+
+@pytest.fixture(scope="module")
+def config0_iq():
+    # 0.5 s at 16 Msps, pulsed noise dispersed at DM 1 (seed 1)
+    return dispersed_pulsar_stream(1, 8_000_000, 1.0)
+
+
+@pytest.fixture(scope="module")
+def config0_oracle(config0_iq):
+    return oracle_run(config0_iq, 1.0, 1 << 18, 256, synth.PERIOD_S, subint=0, decim=16)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_config0_parity(config0_iq, config0_oracle, precision):
+    print(f"case: config0 DM1 N=2^18 256 bins {precision}", flush=True)
+    prof, ser = gpu_run(config0_iq, 1.0, 1 << 18, 256, synth.PERIOD_S, precision=precision)
+    oprof, oser, _ = config0_oracle
+    assert prof.shape == oprof.shape == (1, 256)
+    assert ser.shape == oser.shape == (7_864_320 // 16,)
+    ep, es = profile_rel_l2(prof, oprof), rel_l2(ser, oser)
+    print(f"{precision}: profile rel-L2 {ep:.3e}  series rel-L2 {es:.3e}")
+    tp, ts = TOL[precision]
+    assert ep <= tp and es <= ts
+    # the pulse is where it was injected
+    assert abs(int(np.argmax(prof[0])) - 128) <= 1
+
+
+# (nfft, dm, nbins, period, subint, decim, nsamp): ragged lengths, n_front
+# not a multiple of 16 (the wrapped tile), DM 0 (no discard), several
+# sub-integrations with boundaries inside blocks.
+CASES = [
+    (1 << 10, 0.0, 16, 3.1e-5, 0, 16, 5000),
+    (1 << 10, 0.003, 7, 2.9e-5, 777, 4, 9001),
+    (1 << 11, 0.01, 64, 1.0e-4, 3000, 16, 20011),
+    (1 << 12, 0.0, 33, 7.7e-4, 10000, 8, 40007),
+    (1 << 13, 0.05, 100, 1.3e-3, 25000, 2, 60013),
+    (1 << 15, 0.3, 256, 2.2e-3, 0, 1, 150001),
+    (1 << 16, 0.7, 1024, 5.0e-3, 100000, 16, 400003),
+    (1 << 17, 1.3, 512, 1.1e-2, 333333, 16, 700001),
+    (1 << 19, 3.1, 256, 3.3e-2, 0, 16, 1500007),
+    (1 << 20, 7.0, 2048, 0.0891, 1_000_000, 16, 3000017),
+    (1 << 21, 13.0, 128, 0.25, 0, 16, 4200011),
+    (1 << 22, 20.0, 1024, 0.0891, 2_000_000, 16, 8_500_003),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"n{c[0].bit_length() - 1}_dm{c[1]}")
+def test_sizes_geometry_parity(case):
+    nfft, dm, nbins, period, subint, decim, nsamp = case
+    print(f"case: nfft=2^{nfft.bit_length() - 1} dm={dm} nbins={nbins} S={subint} decim={decim} nsamp={nsamp}",
+          flush=True)
+    iq = synth.white_stream_int8(nfft + 17, nsamp)
+    oprof, oser, r = oracle_run(iq, dm, nfft, nbins, period, subint=subint, decim=decim)
+    prof, ser = gpu_run(iq, dm, nfft, nbins, period, subint=subint, decim=decim)
+    assert prof.shape == oprof.shape
+    assert ser.shape == oser.shape
+    ep, es = profile_rel_l2(prof, oprof), rel_l2(ser, oser)
+    print(f"profile rel-L2 {ep:.3e} series rel-L2 {es:.3e}")
+    assert ep <= 1e-6 and es <= 1e-5
+
+
+@pytest.mark.parametrize("log2n", [23, 24])
+def test_large_fft_parity(log2n):
+    """The production block lengths (2^23 rows x cols = 2^13 x 2^10 and
+    2^24 = 2^14 x 2^10), a few blocks, element by element."""
+    nfft = 1 << log2n
+    dm = 50.0 if log2n == 23 else 200.0
+    nsamp = nfft + 3 * (nfft // 2) + 12345 if log2n == 23 else nfft + 1000
+    print(f"case: large nfft=2^{log2n} dm={dm} nsamp={nsamp}", flush=True)
+    iq = synth.white_stream_int8(log2n, nsamp)
+    oprof, oser, r = oracle_run(iq, dm, nfft, 1024, synth.PERIOD_S, subint=0, decim=16)
+    for precision in ("fp32", "mixed"):
+        prof, ser = gpu_run(iq, dm, nfft, 1024, synth.PERIOD_S, precision=precision)
+        ep, es = profile_rel_l2(prof, oprof), rel_l2(ser, oser)
+        print(f"{precision}: profile rel-L2 {ep:.3e} series rel-L2 {es:.3e}")
+        tp, ts = TOL[precision]
+        assert ep <= tp and es <= ts
+
+
+def test_histogram_too_big_for_lds_uses_global_accumulators():
+    """nbins * sub-integrations per launch beyond the LDS histogram: the
+    kernel adds straight into the device accumulators; same results."""
+    nfft, dm, nbins, period, subint = 1 << 14, 0.2, 20000, 3.0e-3, 12000
+    iq = synth.white_stream_int8(99, 200_000)
+    oprof, oser, _ = oracle_run(iq, dm, nfft, nbins, period, subint=subint)
+    prof, ser = gpu_run(iq, dm, nfft, nbins, period, subint=subint)
+    assert profile_rel_l2(prof, oprof) <= 1e-6
+    assert rel_l2(ser, oser) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_chunking_invariance_is_bitwise(precision):
+    """Any split of one stream into calls gives bit-identical outputs."""
+    nfft, dm, nbins, period, subint = 1 << 16, 0.9, 300, 4.1e-3, 150001
+    nsamp = 1_200_007
+    iq = synth.white_stream_int8(5, nsamp)
+    p1, s1 = gpu_run(iq, dm, nfft, nbins, period, subint=subint, precision=precision)
+    rng = np.random.default_rng(0)
+    chunks = list(rng.integers(0, 90_000, size=40)) + [0, 1, 7, nfft - 1, nfft + 1]
+    chunks.append(nsamp)
+    p2, s2 = gpu_run(iq, dm, nfft, nbins, period, subint=subint, precision=precision,
+                     chunks=[int(c) for c in chunks], max_batch=3)
+    np.testing.assert_array_equal(p1, p2)
+    np.testing.assert_array_equal(s1, s2)
+
+
+def test_run_twice_is_bitwise_deterministic():
+    nfft, dm = 1 << 18, 1.0
+    iq = synth.white_stream_int8(8, 2_000_000)
+    a = gpu_run(iq, dm, nfft, 256, synth.PERIOD_S, subint=300_000)
+    b = gpu_run(iq, dm, nfft, 256, synth.PERIOD_S, subint=300_000)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_short_and_empty_streams():
+    """Fewer samples than one block: no outputs, flush writes nothing."""
+    prof, ser = gpu_run(synth.white_stream_int8(3, 1000), 1.0, 1 << 18, 64, 0.01)
+    assert prof.shape == (0, 64) and ser.size == 0
+    prof, ser = gpu_run(np.zeros(0, np.int8), 0.0, 1 << 10, 8, 0.001, chunks=[0])
+    assert prof.shape == (0, 8) and ser.size == 0
+
+
+def test_abi_errors_leave_state_untouched():
+    import torch
+    import paper_1503_01405_amd as P
+    h = P.pond_plan_create(326.5, 16.0, 1.0, 1 << 16, 32, 0.01)
+    try:
+        x = torch.zeros(2 * 200_000, dtype=torch.int8, device="cuda")
+        prof = torch.empty((10, 32), device="cuda")
+        assert P.pond_dedisperse_fold(h, x, -1, 0, prof, 10) == P.POND_EINVAL
+        assert P.pond_dedisperse_fold(h, None, 5, 0, prof, 10) == P.POND_EINVAL
+        assert P.pond_dedisperse_fold(h, x.data_ptr() + 1, 5, 0, prof, 10) == P.POND_EINVAL
+        # S = 10000 completes more than 10 profiles in the first call: too little capacity
+        assert P.pond_dedisperse_fold(h, x, 200_000, 10_000, prof, 10) == P.POND_EINVAL
+        assert P.pond_plan_query(h)["samples_in"] == 0
+        r, n = P.pond_dedisperse_series(h, x, 200_000, 0, prof, 10, 3, None, 0)
+        assert r == P.POND_EINVAL
+        r, n = P.pond_dedisperse_series(h, x, 200_000, 0, prof, 10, 16, None, 0)
+        assert r == P.POND_EINVAL   # series groups complete but no capacity
+        assert P.pond_dedisperse_fold(h, x, 200_000, 0, prof, 10) == 0
+        assert P.pond_dedisperse_fold(h, x, 1000, 5, prof, 10) == P.POND_EINVAL  # S changed
+        info = P.pond_plan_query(h)
+        assert info["samples_in"] == 200_000 and info["status"] == 0
+        assert P.pond_dedisperse_fold(h, None, 0, 0, prof, 10) == 1          # flush
+        assert P.pond_plan_query(h)["samples_in"] == 0
+    finally:
+        P.pond_plan_destroy(h)
