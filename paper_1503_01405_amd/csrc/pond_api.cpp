@@ -51,8 +51,7 @@ struct pond_plan {
     int64_t tail_start = 0;
     float2* tw1 = nullptr;
     float2* tw2 = nullptr;
-    float2* twhi = nullptr;
-    float2* twlo = nullptr;
+    float4* table = nullptr;
     uint64_t* acc_sum = nullptr;
     uint64_t* acc_cnt = nullptr;
     int64_t acc_slots = 0;
@@ -136,7 +135,7 @@ void free_plan_memory(pond_plan* p) {
     p->marks.clear();
     for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     p->event_pool.clear();
-    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->twhi, p->twlo,
+    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->table,
                     p->acc_sum, p->acc_cnt, p->part_sum, p->part_cnt, p->status};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -273,8 +272,9 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     const int64_t n1 = (int64_t)1 << p->log2n1, n2 = (int64_t)1 << p->log2n2;
     if (e == hipSuccess) chk(upload(&p->tw1, twiddles(n1, n1, 1)));
     if (e == hipSuccess) chk(upload(&p->tw2, twiddles(n2, n2, 1)));
-    if (e == hipSuccess) chk(upload(&p->twhi, twiddles(nfft, nfft >> p->hbits, (int64_t)1 << p->hbits)));
-    if (e == hipSuccess) chk(upload(&p->twlo, twiddles(nfft, (int64_t)1 << p->hbits, 1)));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->table), (size_t)nfft * sizeof(float4)));
+    if (e == hipSuccess)
+        chk(launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, nullptr));
     p->acc_slots = 4;
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_sum), (size_t)p->acc_slots * nbins * 8));
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_cnt), (size_t)p->acc_slots * nbins * 8));
@@ -542,16 +542,10 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
 
         K2Args a2;
         a2.work = p->work;
-        a2.rows = nb << n2log;
+        a2.nblocks = (int32_t)nb;
         a2.log2n2 = n2log;
-        a2.log2n = p->log2n;
         a2.tw1 = p->tw1;
-        a2.twhi = p->twhi;
-        a2.twlo = p->twlo;
-        a2.hbits = p->hbits;
-        a2.chirp_a = p->chirp_a;
-        a2.f0 = p->f0;
-        a2.df = p->df;
+        a2.table = p->table;
         a2.scale = k2_scale;
         e = timed(1, nb, [&] { return launch_k2(p->precision, p->log2n1, a2, stream); });
         if (e != hipSuccess) return fail(e);

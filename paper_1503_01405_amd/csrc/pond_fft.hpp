@@ -164,47 +164,113 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl<N>(static_cast<F&&>(f), std::make_integer_sequence<int, N>{});
 }
 
-// One Stockham stage of radix R on the 16 values of thread j.
-// tw[t] = exp(-2 pi i t / L) (float32 from float64), t in [0, L).
+// ------------------------------------------------------------ twiddles
+// exp(-2 pi i u / 16) for a compile-time u.
+template <int U>
+__device__ __forceinline__ float2 w16() {
+    constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+    constexpr float h = 0.70710678118654752440f;
+    constexpr float cs[16][2] = {{1.f, 0.f},  {c1, -s1},  {h, -h},   {s1, -c1},  {0.f, -1.f}, {-s1, -c1},
+                                 {-h, -h},    {-c1, -s1}, {-1.f, 0.f}, {-c1, s1}, {-h, h},     {-s1, c1},
+                                 {0.f, 1.f},  {s1, c1},   {h, h},    {c1, s1}};
+    return make_float2(cs[U & 15][0], cs[U & 15][1]);
+}
+
+// p[q] = w^q for q = 1..R-1 (p[0] unused), products at most four deep.
+template <int R>
+__device__ __forceinline__ void powers(float2 w, float2 (&p)[R]) {
+    p[0] = make_float2(1.f, 0.f);
+    if constexpr (R > 1) p[1] = w;
+    if constexpr (R > 2) p[2] = cmul(w, w);
+    if constexpr (R > 3) p[3] = cmul(p[2], w);
+    if constexpr (R > 4) {
+        p[4] = cmul(p[2], p[2]);
+        p[5] = cmul(p[4], w);
+        p[6] = cmul(p[4], p[2]);
+        p[7] = cmul(p[4], p[3]);
+    }
+    if constexpr (R > 8) {
+        p[8] = cmul(p[4], p[4]);
+#pragma unroll
+        for (int q = 9; q < 16; ++q) p[q] = cmul(p[8], p[q - 8]);
+    }
+}
+
+// Per-thread twiddle bases of every stage of a length-L transform, read once
+// from tw[t] = exp(-2 pi i t / L):
+//   radix-16 stage with NS > 1: exp(-2 pi i k / (16 NS)), k = j mod NS
+//     (one butterfly per thread; its twiddles are the powers of the base);
+//   final stage of radix R < 16 (NS = L / R): exp(-2 pi i j / L); butterfly
+//     u of the thread has base exp(-2 pi i (j + u L/16) / L) = base * W16^u.
+template <int LOG2L>
+struct StageBases {
+    float2 b[Sched<LOG2L>::kStages];
+    __device__ __forceinline__ void load(int j, const float2* __restrict__ tw) {
+        using S = Sched<LOG2L>;
+        constexpr int L = 1 << LOG2L;
+        static_for<S::kStages>([&](auto si) {
+            constexpr int s = decltype(si)::value;
+            constexpr int NS = S::ns(s);
+            constexpr int R = S::radix(s);
+            if constexpr (NS > 1) {
+                if constexpr (R == 16) b[s] = tw[(j & (NS - 1)) * (L / (16 * NS))];
+                else b[s] = tw[j];
+            } else {
+                b[s] = make_float2(1.f, 0.f);
+            }
+        });
+    }
+};
+
+// One Stockham stage of radix R on the 16 values of thread j.  Butterfly u
+// (index jp = j + TPV u, k = jp mod NS) reads positions jp + q L/R, which
+// are registers u + q BF, twiddles input q by W_{NS R}^(q k), and writes
+// output q to position (jp - k) R + k + q NS.
 template <int L, int R, int NS, int DIR, bool LAST, class Store>
-__device__ __forceinline__ void stockham_stage(float2 (&v)[16], int j, const float2* __restrict__ tw,
-                                               Store&& st) {
+__device__ __forceinline__ void stockham_stage(float2 (&v)[16], int j, float2 base, Store&& st) {
+    // Opaque to the optimiser: the twiddle powers and LDS addresses of a
+    // stage are recomputed at each use instead of being shared between the
+    // forward and inverse transforms (or hoisted out of loops) and held in
+    // registers, which costs occupancy.
+    asm volatile("" : "+v"(base.x), "+v"(base.y), "+v"(j));
     constexpr int BF = 16 / R;
     constexpr int TPV = L / 16;
-#pragma unroll
-    for (int u = 0; u < BF; ++u) {
+    float2 pw[R];
+    if constexpr (NS > 1 && R == 16) powers<R>(base, pw);
+    static_for<BF>([&](auto ui) {
+        constexpr int u = decltype(ui)::value;
         const int jp = j + TPV * u;
         const int k = jp & (NS - 1);
         float2 w[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) w[q] = v[u + q * BF];
         if constexpr (NS > 1) {
-            constexpr int TS = L / (NS * R);
-#pragma unroll
-            for (int q = 1; q < R; ++q) {
-                const float2 t = tw[q * k * TS];
-                w[q] = DIR < 0 ? cmul(w[q], t) : cmulc(w[q], t);
+            if constexpr (R < 16) {
+                const float2 bu = u == 0 ? base : cmul(base, w16<u>());
+                powers<R>(bu, pw);
             }
+#pragma unroll
+            for (int q = 1; q < R; ++q) w[q] = DIR < 0 ? cmul(w[q], pw[q]) : cmulc(w[q], pw[q]);
         }
         Dft<R, DIR>::run(w);
         if constexpr (LAST) {
 #pragma unroll
             for (int q = 0; q < R; ++q) v[u + q * BF] = w[q];
         } else {
-            const int base = (jp - k) * R + k;
+            const int basep = (jp - k) * R + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) st(base + q * NS, w[q]);
+            for (int q = 0; q < R; ++q) st(basep + q * NS, w[q]);
         }
-    }
+    });
 }
 
 // Full length-L transform (DIR = -1 forward, +1 inverse, unnormalised) of
 // the vector held by thread j.  ld(pos) / st(pos, val) access this
-// vector's LDS slot; the caller guarantees every thread of the workgroup
-// calls this together (it contains barriers).
+// vector's LDS slot; every thread of the workgroup must call this together
+// (it contains barriers).
 template <int LOG2L, int DIR, class Load, class Store>
-__device__ __forceinline__ void fft_wg(float2 (&v)[16], int j, const float2* __restrict__ tw,
-                                       Load&& ld, Store&& st) {
+__device__ __forceinline__ void fft_wg(float2 (&v)[16], int j, const StageBases<LOG2L>& tb, Load&& ld,
+                                       Store&& st) {
     using S = Sched<LOG2L>;
     constexpr int L = 1 << LOG2L;
     constexpr int TPV = L / 16;
@@ -215,12 +281,12 @@ __device__ __forceinline__ void fft_wg(float2 (&v)[16], int j, const float2* __r
         constexpr bool LAST = (s == S::kStages - 1);
         if constexpr (!LAST) {
             __syncthreads();
-            stockham_stage<L, R, NS, DIR, false>(v, j, tw, st);
+            stockham_stage<L, R, NS, DIR, false>(v, j, tb.b[s], st);
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < 16; ++e) v[e] = ld(j + TPV * e);
         } else {
-            stockham_stage<L, R, NS, DIR, true>(v, j, tw, st);
+            stockham_stage<L, R, NS, DIR, true>(v, j, tb.b[s], st);
         }
     });
 }

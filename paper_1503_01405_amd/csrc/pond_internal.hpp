@@ -32,18 +32,14 @@ struct K1Args {
 
 // K2: four-step twiddle, forward row FFT (length n1), chirp, inverse row
 // FFT, conjugate twiddle.
+constexpr int kK2BlocksPerWg = 4;  // blocks sharing one row's chirp and twiddles
+
 struct K2Args {
     void* work;
-    int64_t rows;           // nblocks * n2
+    int32_t nblocks;
     int32_t log2n2;
-    int32_t log2n;
     const float2* tw1;      // exp(-2 pi i t / n1), t < n1
-    const float2* twhi;     // exp(-2 pi i (t << hbits) / n)
-    const float2* twlo;     // exp(-2 pi i t / n), t < 2^hbits
-    int32_t hbits;
-    double chirp_a;         // dm / (2.41e-10 f0^2)
-    double f0;              // MHz
-    double df;              // bw / n, MHz per bin
+    const float4* table;    // [n2][n1]: four-step twiddle (x, y), inverse ISM response (z, w)
     float scale;            // power-of-two scale applied on output
 };
 
@@ -85,6 +81,8 @@ hipError_t launch_fold_reduce(const uint64_t* part_sum, const uint32_t* part_cnt
 hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins, int n_complete, int n_touched,
                                 float* profiles, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s);
+hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
+                                 hipStream_t s);
 
 // Static LDS bytes of the K3 tile for a column length 2^log2n2.
 size_t k3_static_lds(int log2n2);

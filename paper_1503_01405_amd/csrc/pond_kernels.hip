@@ -37,6 +37,23 @@ struct Elem<__half2> {
     __device__ __forceinline__ static void store(__half2* p, float2 v) { *p = __float22half2_rn(v); }
 };
 
+// Access at a uniform base pointer plus a 32-bit byte offset (lets the
+// compiler use the scalar-base + vector-offset addressing form).
+template <class T>
+__device__ __forceinline__ const T* at(const T* base, uint32_t byte_off) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ T* at(T* base, uint32_t byte_off) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+// Hide a value from the optimiser so that expressions depending on it are
+// recomputed where used instead of being hoisted and kept in registers.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // ------------------------------------------------------------------- K1
 template <int LOG2N2, class T>
 __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
@@ -55,24 +72,33 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     const int j = threadIdx.x >> 4;
     const int col = 16 * t + c;
 
-    const int64_t start = (a.block0 + b) * a.hop + col;  // absolute sample of row 0
+    // Block samples [0, split) come from the carried tail, the rest from
+    // this call's input; both bases are uniform, offsets are 32-bit.
+    const int64_t bstart = (a.block0 + b) * a.hop;
+    const int64_t split64 = a.in_start - bstart;
+    const uint32_t split = split64 <= 0 ? 0u : (uint32_t)min(split64, (int64_t)1 << (a.log2n1 + LOG2N2));
+    const int8_t* tbase = a.tail + 2 * (bstart - a.tail_start);
+    const int8_t* ibase = a.in + 2 * (bstart - a.in_start);
     float2 v[16];
+    const uint32_t o0 = opaque((uint32_t)col);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int64_t abs = start + ((int64_t)(j + TPV * e) << a.log2n1);
-        const int8_t* p = abs < a.in_start ? a.tail + 2 * (abs - a.tail_start) : a.in + 2 * (abs - a.in_start);
+        const uint32_t off = o0 + ((uint32_t)(j + TPV * e) << a.log2n1);
+        const int8_t* p = off < split ? tbase + 2 * off : ibase + 2 * off;
         const short s = *reinterpret_cast<const short*>(p);
         v[e] = make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)(s >> 8));
     }
+    StageBases<LOG2N2> tb;
+    tb.load(j, a.tw2);
     fft_wg<LOG2N2, -1>(
-        v, j, a.tw2, [&](int pos) { return lds[pos * 16 + c]; },
-        [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
+        v, j, tb, [&](int pos) { return lds[pos * 16 + c]; }, [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
 
-    T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2)) + col;
+    T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
+    const uint32_t w0 = opaque((uint32_t)col);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int k2 = j + TPV * e;
-        Elem<T>::store(out + ((int64_t)k2 << a.log2n1), cscale(v[e], a.scale));
+        const uint32_t k2 = j + TPV * e;
+        Elem<T>::store(at(out, (w0 + (k2 << a.log2n1)) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
     }
 }
 
@@ -83,63 +109,96 @@ struct K2Shape {
     static constexpr int TPV = L / 16;
     static constexpr int ROWS = TPV >= 256 ? 1 : 256 / TPV;
     static constexpr int THREADS = ROWS * TPV;
+    static constexpr int STRIDE = L + L / 16;  // LDS row stride: one pad slot per 16 values
 };
 
-__device__ __forceinline__ float2 fourstep_twiddle(const float2* __restrict__ hi, const float2* __restrict__ lo,
-                                                   uint32_t r, int hbits) {
-    return cmul(hi[r >> hbits], lo[r & ((1u << hbits) - 1u)]);
+// Row table of the middle pass, one float4 per (k2, k1):
+//   (x, y) = W_n^(k1 k2) = exp(-2 pi i (k1 k2 mod n) / n), the four-step twiddle
+//   (z, w) = exp(-2 pi i turns_k), k = k2 + n2 k1, the inverse ISM response
+//            of Sec. 3.7 / Eq. (4); turns_k and its reduction mod 1 are float64.
+// Built once per plan; every block reads the same table.
+__global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, int log2n1, int log2n2,
+                                                       double chirp_a, double f0, double df) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
+    const int64_t n = 1ll << log2n;
+    if (i >= n) return;
+    const int64_t k2 = i >> log2n1;
+    const int64_t k1 = i & ((1ll << log2n1) - 1);
+    const int64_t r = (k1 * k2) & (n - 1);
+    double s, c;
+    sincospi(2.0 * (double)r / (double)n, &s, &c);
+    const int64_t k = k2 + (k1 << log2n2);
+    const int64_t kk = k < (n >> 1) ? k : k - n;
+    const double f = (double)kk * df;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double cs, cc;
+    sincospi(2.0 * frac, &cs, &cc);
+    tab[i] = make_float4((float)c, (float)-s, (float)cc, (float)-cs);
 }
 
+// One workgroup takes row k2 (ROWS rows for short rows) of up to
+// kK2BlocksPerWg consecutive blocks, so each table row is fetched from HBM
+// once and re-read from L2 by the following blocks.
 template <int LOG2N1, class T>
-__global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS) k2_row(K2Args a) {
+__global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+k2_row(K2Args a) {
     using Sh = K2Shape<LOG2N1>;
     constexpr int L = Sh::L;
     constexpr int TPV = Sh::TPV;
-    __shared__ float2 lds[Sh::ROWS * L];
+    __shared__ float2 lds[Sh::ROWS * Sh::STRIDE];
 
     const int r = threadIdx.x / TPV;
     const int j = threadIdx.x - r * TPV;
-    const int64_t row = (int64_t)blockIdx.x * Sh::ROWS + r;
-    const bool valid = row < a.rows;
-    const uint32_t k2 = (uint32_t)(row & ((1 << a.log2n2) - 1));
-    const uint32_t nmask = (1u << a.log2n) - 1u;
-    T* rowp = reinterpret_cast<T*>(a.work) + (valid ? (row << LOG2N1) : 0);
-    float2* my = lds + r * L;
+    const int n2 = 1 << a.log2n2;
+    const int row = blockIdx.x * Sh::ROWS + r;
+    const bool valid = row < n2;
+    float2* my = lds + r * Sh::STRIDE;
+    auto ld = [&](int pos) { return my[pos + (pos >> 4)]; };
+    auto st = [&](int pos, float2 x) { my[pos + (pos >> 4)] = x; };
 
-    float2 v[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int pos = j + TPV * e;
-        float2 x = valid ? Elem<T>::load(rowp + pos) : make_float2(0.f, 0.f);
-        const float2 w = fourstep_twiddle(a.twhi, a.twlo, ((uint32_t)pos * k2) & nmask, a.hbits);
-        v[e] = cmul(x, w);
-    }
-    auto ld = [&](int pos) { return my[pos]; };
-    auto st = [&](int pos, float2 x) { my[pos] = x; };
-    fft_wg<LOG2N1, -1>(v, j, a.tw1, ld, st);
+    StageBases<LOG2N1> tb;
+    tb.load(j, a.tw1);
+    // Uniform base pointers plus 32-bit per-thread offsets (rows beyond n2,
+    // possible only for the shortest rows, re-read the last row and never
+    // store).
+    const int row0 = min((int)blockIdx.x * Sh::ROWS, n2 - 1);
+    const uint32_t toff = (uint32_t)(min(r, n2 - 1 - row0) << LOG2N1) + (uint32_t)j;
+    const float4* tab = a.table + ((int64_t)row0 << LOG2N1);
 
-    // v[e] is spectrum bin k = k2 + n2 * k1 with k1 = j + TPV e.
-    const int64_t n = 1ll << a.log2n;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int64_t k1 = j + TPV * e;
-        const int64_t k = (int64_t)k2 + (k1 << a.log2n2);
-        const int64_t kk = k < (n >> 1) ? k : k - n;
-        const double f = (double)kk * a.df;
-        const double turns = a.chirp_a * (f * f) / (a.f0 + f);
-        const double frac = turns - rint(turns);
-        float sn, cs;
-        sincospif(2.0f * (float)frac, &sn, &cs);
-        v[e] = cmul(v[e], make_float2(cs, -sn));
-    }
-    fft_wg<LOG2N1, +1>(v, j, a.tw1, ld, st);
-
-    if (valid) {
+    const int b0 = blockIdx.y * kK2BlocksPerWg;
+    const int b1 = min(a.nblocks, b0 + kK2BlocksPerWg);
+    for (int b = b0; b < b1; ++b) {
+        T* rows = reinterpret_cast<T*>(a.work) + ((((int64_t)b << a.log2n2) + row0) << LOG2N1);
+        float2 v[16];
+        uint32_t to = opaque(toff);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int pos = j + TPV * e;
-            const float2 w = fourstep_twiddle(a.twhi, a.twlo, ((uint32_t)pos * k2) & nmask, a.hbits);
-            Elem<T>::store(rowp + pos, cscale(cmulc(v[e], w), a.scale));
+            const float2 x = Elem<T>::load(at(rows, (to + TPV * e) * (uint32_t)sizeof(T)));
+            const float4 t = *at(tab, (to + TPV * e) * 16u);
+            v[e] = cmul(x, make_float2(t.x, t.y));
+        }
+        fft_wg<LOG2N1, -1>(v, j, tb, ld, st);
+        // Re-read the table (from L1/L2) rather than keep it live across the
+        // transforms: registers are the occupancy limit of this kernel.
+        asm volatile("" ::: "memory");
+        to = opaque(toff);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float4 t = *at(tab, (to + TPV * e) * 16u);
+            v[e] = cmul(v[e], make_float2(t.z, t.w));
+        }
+        fft_wg<LOG2N1, +1>(v, j, tb, ld, st);
+        asm volatile("" ::: "memory");
+        to = opaque(toff);
+        if (valid) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const float4 t = *at(tab, (to + TPV * e) * 16u);
+                Elem<T>::store(at(rows, (to + TPV * e) * (uint32_t)sizeof(T)),
+                               cscale(cmulc(v[e], make_float2(t.x, t.y)), a.scale));
+            }
         }
     }
 }
@@ -187,6 +246,8 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     const int chunk = (items + 7) >> 3;
     const int it_end = min(items, (xcd + 1) * chunk);
     uint32_t flags = 0;
+    StageBases<LOG2N2> tb;
+    tb.load(j, a.tw2);
 
     for (int item = xcd * chunk + local; item < it_end; item += per_xcd) {
         const int b = item / tiles_per_block;
@@ -196,43 +257,37 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         const int shift = colu >> a.log2n1;          // 1 for wrapped columns of the last tile
         const bool wrap_tile = (r0 + 16 * t + 15) >= n1;
 
-        const T* in = reinterpret_cast<const T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2)) + col;
+        const T* in = reinterpret_cast<const T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
+        const uint32_t o0 = opaque((uint32_t)col);
         float2 v[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = Elem<T>::load(in + ((int64_t)(j + TPV * e) << a.log2n1));
+        for (int e = 0; e < 16; ++e)
+            v[e] = Elem<T>::load(at(in, (o0 + ((uint32_t)(j + TPV * e) << a.log2n1)) * (uint32_t)sizeof(T)));
         fft_wg<LOG2N2, +1>(
-            v, j, a.tw2, [&](int pos) { return lds[pos * 16 + c]; },
-            [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
+            v, j, tb, [&](int pos) { return lds[pos * 16 + c]; }, [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
 
-        float p[16];
+        // Detected powers go through LDS, [row][column]: lanes of wrapped
+        // columns read the next row, and the epilogue below walks the rows
+        // one at a time without holding 16 powers in registers.
+        float* pf = reinterpret_cast<float*>(lds);
+        __syncthreads();
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const float2 y = cscale(v[e], a.scale);
-            p[e] = fmaf(y.x, y.x, y.y * y.y);
+            pf[(j + TPV * e) * 16 + c] = fmaf(y.x, y.x, y.y * y.y);
         }
-        if (wrap_tile) {
-            // Lanes of wrapped columns hold the output of the next row.
-            float* pf = reinterpret_cast<float*>(lds);
-            __syncthreads();
-#pragma unroll
-            for (int e = 0; e < 16; ++e) pf[(j + TPV * e) * 16 + c] = p[e];
-            __syncthreads();
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int rsrc = j + TPV * e + shift;
-                p[e] = rsrc < L ? pf[rsrc * 16 + c] : 0.f;
-            }
-        }
+        __syncthreads();
 
         const int64_t blk_out0 = (a.block0 + b) * a.hop;  // output index of this block's first kept output
-#pragma unroll
+#pragma unroll 2
         for (int e = 0; e < 16; ++e) {
             const int q = j + TPV * e;
             const int64_t nstart = (int64_t)(r0 + 16 * t) + ((int64_t)q << a.log2n1);
             const int64_t off = nstart - a.n_front;
             const bool valid = off >= 0 && off < a.hop;
             const int64_t m0 = blk_out0 + off;     // output index of lane 0 of the group
-            const float pv = p[e];
+            const int rsrc = q + (wrap_tile ? shift : 0);
+            const float pv = rsrc < L ? pf[rsrc * 16 + c] : 0.f;
             const float s2 = xor_sum(pv, 1);
             const float s4 = xor_sum(s2, 2);
             const float s8 = xor_sum(s4, 4);
@@ -377,8 +432,9 @@ hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s) {
 template <class T, int LOG2N1>
 static hipError_t k2_one(const K2Args& a, hipStream_t s) {
     using Sh = K2Shape<LOG2N1>;
-    const int64_t grid = (a.rows + Sh::ROWS - 1) / Sh::ROWS;
-    hipLaunchKernelGGL((k2_row<LOG2N1, T>), dim3((unsigned)grid), dim3(Sh::THREADS), 0, s, a);
+    const int gx = ((1 << a.log2n2) + Sh::ROWS - 1) / Sh::ROWS;
+    const int gy = (a.nblocks + kK2BlocksPerWg - 1) / kK2BlocksPerWg;
+    hipLaunchKernelGGL((k2_row<LOG2N1, T>), dim3(gx, gy), dim3(Sh::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -441,6 +497,14 @@ hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins,
                                 float* profiles, hipStream_t s) {
     hipLaunchKernelGGL(fold_finalize, dim3((nbins + 255) / 256), dim3(256), 0, s, acc_sum, acc_cnt, nbins,
                        n_complete, n_touched, profiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
+                                 hipStream_t s) {
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    hipLaunchKernelGGL(k2_build_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n1, log2n2,
+                       chirp_a, f0, df);
     return hipGetLastError();
 }
 
