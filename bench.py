@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--forms", default="fp32,mixed")
     ap.add_argument("--cpu-blocks", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (a known-size "
+                         "reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
@@ -137,6 +140,15 @@ def main():
     log(f"generated {NSAMP} samples in {time.perf_counter() - t:.1f} s")
     x = torch.from_numpy(iq).to("cuda:0")
     torch.cuda.synchronize()
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n} bytes device-to-device")
+        del src, dst
 
     forms = [f for f in args.forms.split(",") if f]
     res = {}

@@ -32,8 +32,6 @@ struct K1Args {
 
 // K2: four-step twiddle, forward row FFT (length n1), chirp, inverse row
 // FFT, conjugate twiddle.
-constexpr int kK2BlocksPerWg = 4;  // blocks sharing one row's chirp and twiddles
-
 struct K2Args {
     void* work;
     int32_t nblocks;

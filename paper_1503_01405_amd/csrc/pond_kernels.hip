@@ -138,21 +138,28 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
     tab[i] = make_float4((float)c, (float)-s, (float)cc, (float)-cs);
 }
 
-// One workgroup takes row k2 (ROWS rows for short rows) of up to
-// kK2BlocksPerWg consecutive blocks, so each table row is fetched from HBM
-// once and re-read from L2 by the following blocks.
+// One workgroup takes row k2 (ROWS rows for short rows) of one block.  The
+// workgroups of one row for all blocks of the launch get consecutive logical
+// indices on one XCD, so they run together and share the row's table entries
+// through that XCD's L2 (the table is then fetched from HBM about once per
+// launch).
 template <int LOG2N1, class T>
 __global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k2_row(K2Args a) {
     using Sh = K2Shape<LOG2N1>;
-    constexpr int L = Sh::L;
     constexpr int TPV = Sh::TPV;
     __shared__ float2 lds[Sh::ROWS * Sh::STRIDE];
 
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    const int n2 = 1 << a.log2n2;
+    const int row_groups = (n2 + Sh::ROWS - 1) / Sh::ROWS;
+    if (logical >= row_groups * a.nblocks) return;
+    const int rg = logical / a.nblocks;
+    const int b = logical - rg * a.nblocks;
+
     const int r = threadIdx.x / TPV;
     const int j = threadIdx.x - r * TPV;
-    const int n2 = 1 << a.log2n2;
-    const int row = blockIdx.x * Sh::ROWS + r;
+    const int row = rg * Sh::ROWS + r;
     const bool valid = row < n2;
     float2* my = lds + r * Sh::STRIDE;
     auto ld = [&](int pos) { return my[pos + (pos >> 4)]; };
@@ -163,42 +170,38 @@ k2_row(K2Args a) {
     // Uniform base pointers plus 32-bit per-thread offsets (rows beyond n2,
     // possible only for the shortest rows, re-read the last row and never
     // store).
-    const int row0 = min((int)blockIdx.x * Sh::ROWS, n2 - 1);
+    const int row0 = min(rg * Sh::ROWS, n2 - 1);
     const uint32_t toff = (uint32_t)(min(r, n2 - 1 - row0) << LOG2N1) + (uint32_t)j;
     const float4* tab = a.table + ((int64_t)row0 << LOG2N1);
+    T* rows = reinterpret_cast<T*>(a.work) + ((((int64_t)b << a.log2n2) + row0) << LOG2N1);
 
-    const int b0 = blockIdx.y * kK2BlocksPerWg;
-    const int b1 = min(a.nblocks, b0 + kK2BlocksPerWg);
-    for (int b = b0; b < b1; ++b) {
-        T* rows = reinterpret_cast<T*>(a.work) + ((((int64_t)b << a.log2n2) + row0) << LOG2N1);
-        float2 v[16];
-        uint32_t to = opaque(toff);
+    float2 v[16];
+    uint32_t to = opaque(toff);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const float2 x = Elem<T>::load(at(rows, (to + TPV * e) * (uint32_t)sizeof(T)));
+        const float4 t = *at(tab, (to + TPV * e) * 16u);
+        v[e] = cmul(x, make_float2(t.x, t.y));
+    }
+    fft_wg<LOG2N1, -1>(v, j, tb, ld, st);
+    // Re-read the table (from L2) rather than keep it live across the
+    // transforms: registers are the occupancy limit of this kernel.
+    asm volatile("" ::: "memory");
+    to = opaque(toff);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const float4 t = *at(tab, (to + TPV * e) * 16u);
+        v[e] = cmul(v[e], make_float2(t.z, t.w));
+    }
+    fft_wg<LOG2N1, +1>(v, j, tb, ld, st);
+    asm volatile("" ::: "memory");
+    to = opaque(toff);
+    if (valid) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const float2 x = Elem<T>::load(at(rows, (to + TPV * e) * (uint32_t)sizeof(T)));
             const float4 t = *at(tab, (to + TPV * e) * 16u);
-            v[e] = cmul(x, make_float2(t.x, t.y));
-        }
-        fft_wg<LOG2N1, -1>(v, j, tb, ld, st);
-        // Re-read the table (from L1/L2) rather than keep it live across the
-        // transforms: registers are the occupancy limit of this kernel.
-        asm volatile("" ::: "memory");
-        to = opaque(toff);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const float4 t = *at(tab, (to + TPV * e) * 16u);
-            v[e] = cmul(v[e], make_float2(t.z, t.w));
-        }
-        fft_wg<LOG2N1, +1>(v, j, tb, ld, st);
-        asm volatile("" ::: "memory");
-        to = opaque(toff);
-        if (valid) {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const float4 t = *at(tab, (to + TPV * e) * 16u);
-                Elem<T>::store(at(rows, (to + TPV * e) * (uint32_t)sizeof(T)),
-                               cscale(cmulc(v[e], make_float2(t.x, t.y)), a.scale));
-            }
+            Elem<T>::store(at(rows, (to + TPV * e) * (uint32_t)sizeof(T)),
+                           cscale(cmulc(v[e], make_float2(t.x, t.y)), a.scale));
         }
     }
 }
@@ -212,25 +215,63 @@ struct K3Shape {
     static constexpr size_t LDS = sizeof(float2) * 16 * L;
 };
 
-__device__ __forceinline__ float xor_sum(float v, int mask) { return v + __shfl_xor(v, mask, 16); }
+// Fold phase of output m (float64, as specified): x = (m + n_front) * inv_pfs,
+// bin = min(floor(frac(x) * nbins), nbins - 1); also returns floor(x), the
+// pulse number, so that equal bins in different periods are told apart.
+__device__ __forceinline__ int fold_bin(int64_t m, int64_t n_front, double inv_pfs, int nbins, double* turn) {
+    const double x = (double)(m + n_front) * inv_pfs;
+    const double fl = floor(x);
+    *turn = fl;
+    const int bin = (int)((x - fl) * (double)nbins);
+    return bin < nbins - 1 ? bin : nbins - 1;
+}
+
+// Sub-integration of output m relative to s_base (d = m - s_base*S >= 0),
+// without a 64-bit division: float64 estimate, then an exact integer fix-up.
+__device__ __forceinline__ int64_t subint_rel(int64_t d, int64_t S, double inv_s) {
+    int64_t k = (int64_t)((double)d * inv_s);
+    const int64_t r = d - k * S;
+    if (r < 0) --k;
+    else if (r >= S) ++k;
+    return k;
+}
+
+// Add `val` (a power or a sum of `cnt` powers) to histogram entry `key`.
+__device__ __forceinline__ void fold_add(const K3Args& a, uint64_t* hsum, uint32_t* hcnt, int64_t sub_rel, int bin,
+                                         float val, uint32_t cnt, uint32_t& flags) {
+    const double dv = (double)val * kFoldScale;
+    if (!(dv < kFoldRangeLimit * kFoldScale)) flags |= 2u;
+    const uint64_t fx = isfinite(val) ? (uint64_t)__double2ull_rn(dv) : 0ull;
+    if (a.global_mode) {
+        const int64_t gk = (sub_rel + a.s_base - a.acc_s0) * a.nbins + bin;
+        atomicAdd((unsigned long long*)&a.acc_sum[gk], (unsigned long long)fx);
+        atomicAdd((unsigned long long*)&a.acc_cnt[gk], (unsigned long long)cnt);
+    } else {
+        const int key = (int)sub_rel * a.nbins + bin;
+        atomicAdd((unsigned long long*)&hsum[key], (unsigned long long)fx);
+        atomicAdd(&hcnt[key], cnt);
+    }
+}
 
 template <int LOG2N2, class T>
 __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     using Sh = K3Shape<LOG2N2>;
     constexpr int L = Sh::L;
     constexpr int TPV = Sh::TPV;
+    constexpr int PSTRIDE = 20;  // floats per row of the power buffer (16 + 4 pad, 16-byte aligned)
     __shared__ float2 lds[16 * L];
     extern __shared__ uint64_t dyn_u64[];
     uint64_t* hsum = dyn_u64;
     uint32_t* hcnt = reinterpret_cast<uint32_t*>(dyn_u64 + (a.global_mode ? 0 : a.entries));
+    float* pf = reinterpret_cast<float*>(lds);
 
     const int c = threadIdx.x & 15;
     const int j = threadIdx.x >> 4;
-    const int lane = threadIdx.x & 63;
     const int n1 = 1 << a.log2n1;
     const int tiles_per_block = n1 >> 4;
     const int items = a.nblocks * tiles_per_block;
     const int r0 = (int)(a.n_front & 15);
+    const double inv_s = a.subint > 0 ? 1.0 / (double)a.subint : 0.0;
 
     if (!a.global_mode) {
         for (int i = threadIdx.x; i < a.entries; i += blockDim.x) {
@@ -252,10 +293,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     for (int item = xcd * chunk + local; item < it_end; item += per_xcd) {
         const int b = item / tiles_per_block;
         const int t = item - b * tiles_per_block;
-        const int colu = r0 + 16 * t + c;           // unwrapped column of lane c
-        const int col = colu & (n1 - 1);
-        const int shift = colu >> a.log2n1;          // 1 for wrapped columns of the last tile
-        const bool wrap_tile = (r0 + 16 * t + 15) >= n1;
+        const int col = (r0 + 16 * t + c) & (n1 - 1);
 
         const T* in = reinterpret_cast<const T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
         const uint32_t o0 = opaque((uint32_t)col);
@@ -266,74 +304,89 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         fft_wg<LOG2N2, +1>(
             v, j, tb, [&](int pos) { return lds[pos * 16 + c]; }, [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
 
-        // Detected powers go through LDS, [row][column]: lanes of wrapped
-        // columns read the next row, and the epilogue below walks the rows
-        // one at a time without holding 16 powers in registers.
-        float* pf = reinterpret_cast<float*>(lds);
+        // Detected powers to LDS, one row of 16 columns per output row.
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const float2 y = cscale(v[e], a.scale);
-            pf[(j + TPV * e) * 16 + c] = fmaf(y.x, y.x, y.y * y.y);
+            pf[(j + TPV * e) * PSTRIDE + c] = fmaf(y.x, y.x, y.y * y.y);
         }
         __syncthreads();
 
-        const int64_t blk_out0 = (a.block0 + b) * a.hop;  // output index of this block's first kept output
-#pragma unroll 2
-        for (int e = 0; e < 16; ++e) {
-            const int q = j + TPV * e;
-            const int64_t nstart = (int64_t)(r0 + 16 * t) + ((int64_t)q << a.log2n1);
-            const int64_t off = nstart - a.n_front;
-            const bool valid = off >= 0 && off < a.hop;
-            const int64_t m0 = blk_out0 + off;     // output index of lane 0 of the group
-            const int rsrc = q + (wrap_tile ? shift : 0);
-            const float pv = rsrc < L ? pf[rsrc * 16 + c] : 0.f;
-            const float s2 = xor_sum(pv, 1);
-            const float s4 = xor_sum(s2, 2);
-            const float s8 = xor_sum(s4, 4);
-            const float s16 = xor_sum(s8, 8);
-            if (!isfinite(pv)) flags |= 1u;
-            if (a.series && valid && (c & (a.decim - 1)) == 0) {
-                const float sd = a.decim == 1 ? pv : a.decim == 2 ? s2 : a.decim == 4 ? s4 : a.decim == 8 ? s8 : s16;
-                a.series[(m0 + c) / a.decim - a.series_base] = sd;
+        // Thread q takes group q: outputs n = r0 + 16 t + n1 q + [0, 16),
+        // i.e. 16 consecutive kept outputs (columns that wrap past n1 hold
+        // them one row further down).
+        const int q = threadIdx.x;
+        const int64_t nstart = (int64_t)(r0 + 16 * t) + ((int64_t)q << a.log2n1);
+        const int64_t off = nstart - a.n_front;
+        float p[16];
+        if (r0 + 16 * t + 15 < n1) {
+            const float4* row = reinterpret_cast<const float4*>(pf + q * PSTRIDE);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float4 x4 = row[i];
+                p[4 * i] = x4.x;
+                p[4 * i + 1] = x4.y;
+                p[4 * i + 2] = x4.z;
+                p[4 * i + 3] = x4.w;
             }
-            // fold: bin and sub-integration of this lane's own output
-            const int64_t m = m0 + c;
-            const double x = (double)(m + a.n_front) * a.inv_pfs;
-            const double fr = x - floor(x);
-            int bin = (int)(fr * (double)a.nbins);
-            bin = bin < a.nbins - 1 ? bin : a.nbins - 1;
-            const int64_t sub = a.subint > 0 ? m / a.subint : 0;
-            const int key = (int)(sub - a.s_base) * a.nbins + bin;
-            const int key0 = __shfl(key, lane & 48, 64);
-            const uint64_t bal = __ballot(key == key0);
-            const bool same = ((bal >> (lane & 48)) & 0xffffull) == 0xffffull;
-            if (valid) {
-                float val;
-                uint32_t cnt;
-                bool act;
-                if (same) {
-                    val = s16;
-                    cnt = 16;
-                    act = (c == 0);
-                } else {
-                    val = pv;
-                    cnt = 1;
-                    act = true;
-                }
-                if (act) {
-                    const double dv = (double)val * kFoldScale;
-                    if (!(dv < kFoldRangeLimit * kFoldScale)) flags |= 2u;
-                    const uint64_t fx = isfinite(val) ? (uint64_t)__double2ull_rn(dv) : 0ull;
-                    if (a.global_mode) {
-                        const int64_t gk = (sub - a.acc_s0) * a.nbins + bin;
-                        atomicAdd((unsigned long long*)&a.acc_sum[gk], (unsigned long long)fx);
-                        atomicAdd((unsigned long long*)&a.acc_cnt[gk], (unsigned long long)cnt);
-                    } else {
-                        atomicAdd((unsigned long long*)&hsum[key], (unsigned long long)fx);
-                        atomicAdd(&hcnt[key], cnt);
-                    }
-                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int rsrc = q + ((r0 + 16 * t + i) >> a.log2n1);
+                p[i] = rsrc < L ? pf[rsrc * PSTRIDE + i] : 0.f;
+            }
+        }
+        if (off < 0 || off >= a.hop) continue;
+
+        // Group sum and the decimated series (sums of `decim` consecutive
+        // powers, pairwise).
+        float s2[8], s4[4], s8[2];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s2[i] = p[2 * i] + p[2 * i + 1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s4[i] = s2[2 * i] + s2[2 * i + 1];
+        s8[0] = s4[0] + s4[1];
+        s8[1] = s4[2] + s4[3];
+        const float s16 = s8[0] + s8[1];
+        const int64_t m0 = (a.block0 + b) * a.hop + off;  // first output of the group
+        if (a.series) {
+            float* sp = a.series + (m0 / a.decim - a.series_base);
+            if (a.decim == 16) {
+                sp[0] = s16;
+            } else if (a.decim == 8) {
+                sp[0] = s8[0];
+                sp[1] = s8[1];
+            } else if (a.decim == 4) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sp[i] = s4[i];
+            } else if (a.decim == 2) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) sp[i] = s2[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) sp[i] = p[i];
+            }
+        }
+        if (!isfinite(s16)) flags |= 1u;
+
+        // Fold: one contribution when all 16 outputs share period, bin and
+        // sub-integration (the first and last decide, phase being monotone),
+        // otherwise one per output.
+        double t0, t15;
+        const int bin0 = fold_bin(m0, a.n_front, a.inv_pfs, a.nbins, &t0);
+        const int bin15 = fold_bin(m0 + 15, a.n_front, a.inv_pfs, a.nbins, &t15);
+        const int64_t d0 = m0 - a.s_base * a.subint;
+        const int64_t sub0 = a.subint > 0 ? subint_rel(d0, a.subint, inv_s) : 0;
+        const int64_t sub15 = a.subint > 0 ? subint_rel(d0 + 15, a.subint, inv_s) : 0;
+        if (bin0 == bin15 && t0 == t15 && sub0 == sub15) {
+            fold_add(a, hsum, hcnt, sub0, bin0, s16, 16, flags);
+        } else {
+            for (int i = 0; i < 16; ++i) {
+                double ti;
+                const int bi = fold_bin(m0 + i, a.n_front, a.inv_pfs, a.nbins, &ti);
+                const int64_t si = a.subint > 0 ? subint_rel(d0 + i, a.subint, inv_s) : 0;
+                fold_add(a, hsum, hcnt, si, bi, p[i], 1, flags);
             }
         }
     }
@@ -432,9 +485,9 @@ hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s) {
 template <class T, int LOG2N1>
 static hipError_t k2_one(const K2Args& a, hipStream_t s) {
     using Sh = K2Shape<LOG2N1>;
-    const int gx = ((1 << a.log2n2) + Sh::ROWS - 1) / Sh::ROWS;
-    const int gy = (a.nblocks + kK2BlocksPerWg - 1) / kK2BlocksPerWg;
-    hipLaunchKernelGGL((k2_row<LOG2N1, T>), dim3(gx, gy), dim3(Sh::THREADS), 0, s, a);
+    const int groups = ((1 << a.log2n2) + Sh::ROWS - 1) / Sh::ROWS * a.nblocks;
+    const int grid = (groups + 7) & ~7;
+    hipLaunchKernelGGL((k2_row<LOG2N1, T>), dim3(grid), dim3(Sh::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
