@@ -53,6 +53,39 @@ def algorithmic_bytes(kernel, blocks, elem, nfft, hop):
     return 0
 
 
+def kernel_source_hash():
+    """sha256[:16] over the HIP/C++ sources of the library (as recorded in
+    the committed rocprofv3 summaries)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1503_01405_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_prefix):
+    """HBM bytes per dispatch of a kernel from the committed counter summary,
+    or None if the summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_bytes_dm50_nfft2e23_mixed.txt")
+    if not os.path.exists(path):
+        return None
+    src = None
+    with open(path) as fh:
+        lines = fh.read().splitlines()
+    for ln in lines:
+        if ln.startswith("kernel source sha256[:16]:"):
+            src = ln.rsplit(":", 1)[1].strip()
+    if src != kernel_source_hash():
+        return None
+    for ln in lines:
+        if ln.startswith("TRAFFIC ") and kernel_prefix in ln and "__half2" in ln:
+            kv = dict(t.split("=") for t in ln.split() if "=" in t)
+            return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    return None
+
+
 def run_form(precision, x, steps, warmup):
     import torch
     import paper_1503_01405_amd as P
@@ -168,9 +201,14 @@ def main():
     ms, launches, blocks = kt[dom]
     algo = algorithmic_bytes(dom, blocks, elem, NFFT, hop)
     achieved = algo / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    avg_s = ms / 1e3 / max(launches, 1)
+    meas = measured_traffic(dom) if head == "mixed" else None
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                avg_launch_us=round(ms / max(launches, 1) * 1e3, 2), blocks_per_launch=blocks / max(launches, 1))
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=round(meas / avg_s / 1e9, 1) if meas else None,
+                traffic_bytes_per_launch=meas,
+                algorithmic_bytes_per_launch=int(algo / max(launches, 1)),
+                avg_launch_us=round(avg_s * 1e6, 2), blocks_per_launch=round(blocks / max(launches, 1), 3))
 
     forms_out = {}
     for f, r in res.items():
