@@ -59,9 +59,12 @@ typedef struct pond_plan pond_plan;
 
 /* Precision forms. */
 #define POND_FP32   0  /* float32 storage and arithmetic                                   */
-#define POND_MIXED  1  /* float16 storage between passes, fp16 matrix-core DFT stages with
-                          fp32 accumulation and power-of-two stage scaling; chirp and fold
-                          phases stay float64                                               */
+#define POND_MIXED  1  /* float16 storage between passes; the radix-16 stages of the column
+                          passes run as 16-point DFT matrix products on the matrix cores
+                          (float16 operands, float32 accumulation, power-of-two stage
+                          scaling); chirp and fold phases stay float64                      */
+#define POND_MIXED_VALU 2  /* float16 storage between passes, every butterfly in float32
+                              vector arithmetic                                            */
 
 /* Status bits reported by pond_plan_query().status (sticky until flush). */
 #define POND_STATUS_NONFINITE  1u  /* a detected power was inf or NaN (fp16 overflow)        */
@@ -82,7 +85,7 @@ typedef struct pond_info {
     double  delta_hi_s;    /* advance of band top relative to f0                   */
     double  inv_pfs;       /* 1 / (period_s * fs_hz)                               */
     int32_t nbins;
-    int32_t precision;     /* POND_FP32 or POND_MIXED                              */
+    int32_t precision;     /* POND_FP32, POND_MIXED or POND_MIXED_VALU             */
     uint32_t status;       /* POND_STATUS_* bits (read synchronously)              */
     int32_t reserved;
 } pond_info;
@@ -106,8 +109,9 @@ pond_plan* pond_plan_create(double f0_mhz, double bw_mhz, double dm,
                             int64_t nfft, int32_t nbins, double period_s);
 
 /*
- * As pond_plan_create with a precision form (POND_FP32 or POND_MIXED) and a
- * cap on overlap-save blocks per launch (max_batch <= 0 picks a default).
+ * As pond_plan_create with a precision form (POND_FP32, POND_MIXED or
+ * POND_MIXED_VALU) and a cap on overlap-save blocks per launch (max_batch
+ * <= 0 picks a default).
  */
 pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm,
                                int64_t nfft, int32_t nbins, double period_s,

@@ -196,7 +196,7 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     const int log2n = ilog2(nfft);
     if (log2n < kMinLog2N || log2n > kMaxLog2N) return nullptr;
     if (nbins < 1 || nbins > 65536) return nullptr;
-    if (precision != POND_FP32 && precision != POND_MIXED) return nullptr;
+    if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU) return nullptr;
     const double fs = bw_mhz * 1e6;
     if (!(period_s > 0) || !(period_s * fs >= 1.0)) return nullptr;
 
@@ -250,7 +250,7 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     p->hbits = (log2n + 1) / 2;
     p->nbins = nbins;
     p->precision = precision;
-    p->elem = precision == POND_MIXED ? 4 : 8;
+    p->elem = precision == POND_FP32 ? 8 : 4;
     if (max_batch <= 0) {
         int64_t b = ((int64_t)1 << 29) / (nfft * (int64_t)p->elem);
         max_batch = (int)(b < 1 ? 1 : (b > 16 ? 16 : b));
@@ -504,10 +504,12 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
 
     const int64_t n1 = (int64_t)1 << p->log2n1;
     const int n2log = p->log2n2;
-    const int s_mix = n2log / 2;  // column-pass scale exponent of K1
-    const float k1_scale = std::ldexp(1.0f, -s_mix);
+    // Power-of-two pass scales, 1/n overall: the forward column pass is
+    // normalised (1/n2), the row pass scales by 1/n1, the inverse column
+    // pass by 1, so every stored intermediate stays within the input range.
+    const float k1_scale = std::ldexp(1.0f, -n2log);
     const float k2_scale = std::ldexp(1.0f, -p->log2n1);
-    const float k3_scale = std::ldexp(1.0f, -(n2log - s_mix));
+    const float k3_scale = 1.0f;
 
     int64_t b = p->blocks_done;
     while (b < nb_total) {

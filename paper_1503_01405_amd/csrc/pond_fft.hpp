@@ -291,6 +291,158 @@ __device__ __forceinline__ void fft_wg(float2 (&v)[16], int j, const StageBases<
     });
 }
 
+// ------------------------------------------------- matrix-core DFT-16
+// A 16-point complex DFT is a real 32 x 32 matrix product; the 16 x 32 half
+// that yields real (or imaginary) outputs is one v_mfma_f32_16x16x32_f16
+// operand.  Lane layout of that instruction (wave64): lane l holds
+//   A[l % 16][8 (l / 16) + t]   and   B[8 (l / 16) + t][l % 16],  t < 8,
+//   D[4 (l / 16) + t][l % 16],  t < 4.
+// With the input vector interleaved as (Re x0, Im x0, Re x1, ...) along K,
+// lane (g = l / 16, n = l % 16) supplies inputs q = 4g..4g+3 of vector n and
+// receives outputs s = 4g..4g+3 of vector n.
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// The DFT matrix is carried as a float16 pair hi + lo (lo = the rounding
+// error of hi): a single float16 matrix would give every output a fixed
+// ~1e-4 gain error, which does not average out in a folded profile.
+struct Dft16Operands {
+    half8_t re_hi, re_lo, im_hi, im_lo;
+};
+
+__device__ __forceinline__ floatx4_t mfma16x16x32(const half8_t& hi, const half8_t& lo, const half8_t& b) {
+    const floatx4_t z = {0.f, 0.f, 0.f, 0.f};
+    const floatx4_t c = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo, b, z, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void split_half(float x, _Float16& hi, _Float16& lo) {
+    hi = (_Float16)x;
+    lo = (_Float16)(x - (float)hi);
+}
+
+// cos and sin of 2 pi e / 16, e < 16 (float32 nearest to the exact values).
+__constant__ const float kCos16[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                                       0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                                       -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+                                       0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+
+// This lane's A operands for scale * exp(DIR 2 pi i q s / 16): rows of real
+// outputs hold (Re c, -Im c) per input q, rows of imaginary outputs (Im c, Re c).
+template <int DIR>
+__device__ __forceinline__ Dft16Operands dft16_operands(int lane, float scale) {
+    const int s = lane & 15;
+    const int g = lane >> 4;
+    Dft16Operands m;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int e = ((4 * g + t) * s) & 15;
+        const float cs = kCos16[e], sn = kCos16[(e + 12) & 15];  // sin x = cos(x - pi/2)
+        const float cr = scale * cs, ci = scale * (DIR < 0 ? -sn : sn);
+        _Float16 h, l;
+        split_half(cr, h, l);
+        m.re_hi[2 * t] = h;
+        m.re_lo[2 * t] = l;
+        m.im_hi[2 * t + 1] = h;
+        m.im_lo[2 * t + 1] = l;
+        split_half(-ci, h, l);
+        m.re_hi[2 * t + 1] = h;
+        m.re_lo[2 * t + 1] = l;
+        split_half(ci, h, l);
+        m.im_hi[2 * t] = h;
+        m.im_lo[2 * t] = l;
+    }
+    return m;
+}
+
+// One radix-16 Stockham stage on matrix cores for 16 interleaved columns of
+// length L (thread c = tid % 16, j = tid / 16; wave lane = 16 (j % 4) + c).
+// The wave owns butterflies jp = (j & ~3) + b, b < 4, one MFMA batch each
+// (the 16 columns share the butterfly's twiddles).  src(pos) returns this
+// lane's column at pos; dst(pos, y) receives outputs.  If SYNC, a barrier
+// separates all reads from all writes (in-place LDS stages).
+template <int L, int NS, int DIR, bool SYNC, class Src, class Dst>
+__device__ __forceinline__ void mfma16_stage_cols(int j, const Dft16Operands& m, const float2* __restrict__ tw,
+                                                  Src&& src, Dst&& dst) {
+    asm volatile("" : "+v"(j));
+    const int g = j & 3;
+    const int jb = j & ~3;
+    floatx4_t dre[4], dim[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int jp = jb + b;
+        const int k = jp & (NS - 1);
+        half8_t bv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int q = 4 * g + t;
+            float2 x = src(jp + q * (L / 16));
+            if constexpr (NS > 1) {
+                const float2 w = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(tw) +
+                                                                  (uint32_t)(q * k * (L / (16 * NS))) * 8u);
+                x = DIR < 0 ? cmul(x, w) : cmulc(x, w);
+            }
+            bv[2 * t] = (_Float16)x.x;
+            bv[2 * t + 1] = (_Float16)x.y;
+        }
+        dre[b] = mfma16x16x32(m.re_hi, m.re_lo, bv);
+        dim[b] = mfma16x16x32(m.im_hi, m.im_lo, bv);
+    }
+    if constexpr (SYNC) __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int jp = jb + b;
+        const int k = jp & (NS - 1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dst((jp - k) * 16 + k + (4 * g + t) * NS, make_float2(dre[b][t], dim[b][t]));
+    }
+}
+
+// Length-L transform of 16 interleaved columns with the radix-16 stages on
+// matrix cores (operands in float16, accumulation in float32) and the final
+// small-radix stage, if any, in float32 arithmetic.  Each radix-16 stage is
+// scaled by scale16 (folded into the matrix), the small stage by scale_rem.
+// in(pos) gives the first stage's input for this lane's column; out(pos, y)
+// receives every output of this lane's column exactly once.  lds(pos) is
+// the float2 slot of this column at pos.  With OUT_SYNC a barrier precedes
+// the first out() call (out may then reuse the LDS).  Contains barriers.
+template <int LOG2L, int DIR, bool OUT_SYNC, class In, class Lds, class Out>
+__device__ __forceinline__ void colfft_mfma(int c, int j, const float2* __restrict__ tw, const StageBases<LOG2L>& tb,
+                                            float scale16, float scale_rem, In&& in, Lds&& lds, Out&& out) {
+    using S = Sched<LOG2L>;
+    constexpr int L = 1 << LOG2L;
+    constexpr int TPV = L / 16;
+    // A wave must hold 4 butterflies of 16 columns: L >= 64.
+    static_assert(LOG2L >= 6, "matrix-core column transform needs columns of at least 64 points");
+    const Dft16Operands m = dft16_operands<DIR>(threadIdx.x & 63, scale16);
+    auto from_lds = [&](int pos) { return lds(pos); };
+    auto to_lds = [&](int pos, float2 y) { lds(pos) = y; };
+    static_for<S::kFull>([&](auto si) {
+        constexpr int s = decltype(si)::value;
+        constexpr int NS = S::ns(s);
+        constexpr bool LAST = (s == S::kStages - 1);
+        if constexpr (s == 0) {
+            if constexpr (LAST) mfma16_stage_cols<L, NS, DIR, OUT_SYNC>(j, m, tw, in, out);
+            else mfma16_stage_cols<L, NS, DIR, false>(j, m, tw, in, to_lds);
+        } else {
+            __syncthreads();
+            if constexpr (LAST) mfma16_stage_cols<L, NS, DIR, true>(j, m, tw, from_lds, out);
+            else mfma16_stage_cols<L, NS, DIR, true>(j, m, tw, from_lds, to_lds);
+        }
+    });
+    if constexpr (S::kRem > 1) {
+        constexpr int s = S::kStages - 1;
+        __syncthreads();
+        float2 v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = lds(j + TPV * e);
+        stockham_stage<L, S::kRem, S::ns(s), DIR, true>(v, j, tb.b[s], [](int, float2) {});
+        if constexpr (OUT_SYNC) __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 16; ++e) out(j + TPV * e, cscale(v[e], scale_rem));
+    }
+}
+
 // ------------------------------------------------------------- misc
 // Workgroup index remapped so that consecutive logical indices run on the
 // same XCD (workgroups are dispatched round-robin over the 8 XCDs).

@@ -13,7 +13,7 @@ namespace pond {
 constexpr double kFoldScale = 65536.0;
 constexpr double kFoldRangeLimit = 1099511627776.0;  // 2^40: flag larger single contributions
 
-enum Precision { kFp32 = 0, kMixed = 1 };
+enum Precision { kFp32 = 0, kMixed = 1, kMixedValu = 2 };
 
 // K1: int8 unpack + forward column FFTs (length n2, stride n1).
 struct K1Args {

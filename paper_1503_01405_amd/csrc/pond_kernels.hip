@@ -18,6 +18,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pond_fft.hpp"
 #include "pond_internal.hpp"
 
@@ -55,7 +57,7 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
 }
 
 // ------------------------------------------------------------------- K1
-template <int LOG2N2, class T>
+template <int LOG2N2, class T, bool MFMA>
 __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     constexpr int L = 1 << LOG2N2;
     constexpr int TPV = L / 16;
@@ -79,26 +81,38 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     const uint32_t split = split64 <= 0 ? 0u : (uint32_t)min(split64, (int64_t)1 << (a.log2n1 + LOG2N2));
     const int8_t* tbase = a.tail + 2 * (bstart - a.tail_start);
     const int8_t* ibase = a.in + 2 * (bstart - a.in_start);
-    float2 v[16];
     const uint32_t o0 = opaque((uint32_t)col);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const uint32_t off = o0 + ((uint32_t)(j + TPV * e) << a.log2n1);
+    auto load_in = [&](int pos) {
+        const uint32_t off = o0 + ((uint32_t)pos << a.log2n1);
         const int8_t* p = off < split ? tbase + 2 * off : ibase + 2 * off;
         const short s = *reinterpret_cast<const short*>(p);
-        v[e] = make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)(s >> 8));
-    }
+        return make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)(s >> 8));
+    };
+    T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
     StageBases<LOG2N2> tb;
     tb.load(j, a.tw2);
-    fft_wg<LOG2N2, -1>(
-        v, j, tb, [&](int pos) { return lds[pos * 16 + c]; }, [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
-
-    T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
-    const uint32_t w0 = opaque((uint32_t)col);
+    if constexpr (MFMA && LOG2N2 >= 6) {
+        // Normalised forward pass (1/16 per radix-16 stage, folded into the
+        // DFT matrix): no float16 value can exceed the input range.
+        const uint32_t w0 = opaque((uint32_t)col);
+        colfft_mfma<LOG2N2, -1, false>(
+            c, j, a.tw2, tb, 1.0f / 16.0f, 1.0f / (float)Sched<LOG2N2>::kRem, load_in,
+            [&](int pos) -> float2& { return lds[pos * 16 + c]; },
+            [&](int pos, float2 y) {
+                Elem<T>::store(at(out, (w0 + ((uint32_t)pos << a.log2n1)) * (uint32_t)sizeof(T)), y);
+            });
+    } else {
+        float2 v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const uint32_t k2 = j + TPV * e;
-        Elem<T>::store(at(out, (w0 + (k2 << a.log2n1)) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+        for (int e = 0; e < 16; ++e) v[e] = load_in(j + TPV * e);
+        fft_wg<LOG2N2, -1>(
+            v, j, tb, [&](int pos) { return lds[pos * 16 + c]; }, [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
+        const uint32_t w0 = opaque((uint32_t)col);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const uint32_t k2 = j + TPV * e;
+            Elem<T>::store(at(out, (w0 + (k2 << a.log2n1)) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+        }
     }
 }
 
@@ -253,7 +267,7 @@ __device__ __forceinline__ void fold_add(const K3Args& a, uint64_t* hsum, uint32
     }
 }
 
-template <int LOG2N2, class T>
+template <int LOG2N2, class T, bool MFMA>
 __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     using Sh = K3Shape<LOG2N2>;
     constexpr int L = Sh::L;
@@ -297,21 +311,35 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 
         const T* in = reinterpret_cast<const T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
         const uint32_t o0 = opaque((uint32_t)col);
-        float2 v[16];
+        auto load_in = [&](int pos) {
+            return Elem<T>::load(at(in, (o0 + ((uint32_t)pos << a.log2n1)) * (uint32_t)sizeof(T)));
+        };
+        if constexpr (MFMA && LOG2N2 >= 6) {
+            __syncthreads();  // the previous item's epilogue has finished with the LDS
+            colfft_mfma<LOG2N2, +1, true>(
+                c, j, a.tw2, tb, 1.0f, 1.0f, load_in, [&](int pos) -> float2& { return lds[pos * 16 + c]; },
+                [&](int pos, float2 y) {
+                    const float2 z = cscale(y, a.scale);
+                    pf[pos * PSTRIDE + c] = fmaf(z.x, z.x, z.y * z.y);
+                });
+            __syncthreads();
+        } else {
+            float2 v[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e)
-            v[e] = Elem<T>::load(at(in, (o0 + ((uint32_t)(j + TPV * e) << a.log2n1)) * (uint32_t)sizeof(T)));
-        fft_wg<LOG2N2, +1>(
-            v, j, tb, [&](int pos) { return lds[pos * 16 + c]; }, [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
+            for (int e = 0; e < 16; ++e) v[e] = load_in(j + TPV * e);
+            fft_wg<LOG2N2, +1>(
+                v, j, tb, [&](int pos) { return lds[pos * 16 + c]; },
+                [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
 
-        // Detected powers to LDS, one row of 16 columns per output row.
-        __syncthreads();
+            // Detected powers to LDS, one row of 16 columns per output row.
+            __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const float2 y = cscale(v[e], a.scale);
-            pf[(j + TPV * e) * PSTRIDE + c] = fmaf(y.x, y.x, y.y * y.y);
+            for (int e = 0; e < 16; ++e) {
+                const float2 y = cscale(v[e], a.scale);
+                pf[(j + TPV * e) * PSTRIDE + c] = fmaf(y.x, y.x, y.y * y.y);
+            }
+            __syncthreads();
         }
-        __syncthreads();
 
         // Thread q takes group q: outputs n = r0 + 16 t + n1 q + [0, 16),
         // i.e. 16 consecutive kept outputs (columns that wrap past n1 hold
@@ -457,29 +485,33 @@ __global__ void __launch_bounds__(256) zero_u64(uint64_t* p, int64_t n) {
 }
 
 // ---------------------------------------------------------- launchers
-template <class T, int LOG2N2>
+template <class T, bool MFMA, int LOG2N2>
 static hipError_t k1_one(const K1Args& a, hipStream_t s) {
     const int ntiles = a.nblocks * ((1 << a.log2n1) >> 4);
     const int grid = (ntiles + 7) & ~7;
-    hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
+    hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, MFMA>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
     return hipGetLastError();
 }
 
-template <class T>
+template <class T, bool MFMA>
 static hipError_t k1_dispatch(int log2n2, const K1Args& a, hipStream_t s) {
     switch (log2n2) {
-        case 5: return k1_one<T, 5>(a, s);
-        case 6: return k1_one<T, 6>(a, s);
-        case 7: return k1_one<T, 7>(a, s);
-        case 8: return k1_one<T, 8>(a, s);
-        case 9: return k1_one<T, 9>(a, s);
-        case 10: return k1_one<T, 10>(a, s);
+        case 5: return k1_one<T, MFMA, 5>(a, s);
+        case 6: return k1_one<T, MFMA, 6>(a, s);
+        case 7: return k1_one<T, MFMA, 7>(a, s);
+        case 8: return k1_one<T, MFMA, 8>(a, s);
+        case 9: return k1_one<T, MFMA, 9>(a, s);
+        case 10: return k1_one<T, MFMA, 10>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s) {
-    return prec == kMixed ? k1_dispatch<__half2>(log2n2, a, s) : k1_dispatch<float2>(log2n2, a, s);
+    switch (prec) {
+        case kMixed: return k1_dispatch<__half2, true>(log2n2, a, s);
+        case kMixedValu: return k1_dispatch<__half2, false>(log2n2, a, s);
+        default: return k1_dispatch<float2, false>(log2n2, a, s);
+    }
 }
 
 template <class T, int LOG2N1>
@@ -509,34 +541,38 @@ static hipError_t k2_dispatch(int log2n1, const K2Args& a, hipStream_t s) {
 }
 
 hipError_t launch_k2(int prec, int log2n1, const K2Args& a, hipStream_t s) {
-    return prec == kMixed ? k2_dispatch<__half2>(log2n1, a, s) : k2_dispatch<float2>(log2n1, a, s);
+    return prec == kFp32 ? k2_dispatch<float2>(log2n1, a, s) : k2_dispatch<__half2>(log2n1, a, s);
 }
 
-template <class T, int LOG2N2>
+template <class T, bool MFMA, int LOG2N2>
 static hipError_t k3_one(const K3Args& a, int grid, size_t dyn, hipStream_t s) {
     static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k3_colinv_detect_fold<LOG2N2, T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)(160 * 1024 - K3Shape<LOG2N2>::LDS));
+        reinterpret_cast<const void*>(&k3_colinv_detect_fold<LOG2N2, T, MFMA>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - K3Shape<LOG2N2>::LDS));
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k3_colinv_detect_fold<LOG2N2, T>), dim3(grid), dim3(1 << LOG2N2), dyn, s, a);
+    hipLaunchKernelGGL((k3_colinv_detect_fold<LOG2N2, T, MFMA>), dim3(grid), dim3(1 << LOG2N2), dyn, s, a);
     return hipGetLastError();
 }
 
-template <class T>
+template <class T, bool MFMA>
 static hipError_t k3_dispatch(int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s) {
     switch (log2n2) {
-        case 5: return k3_one<T, 5>(a, grid, dyn, s);
-        case 6: return k3_one<T, 6>(a, grid, dyn, s);
-        case 7: return k3_one<T, 7>(a, grid, dyn, s);
-        case 8: return k3_one<T, 8>(a, grid, dyn, s);
-        case 9: return k3_one<T, 9>(a, grid, dyn, s);
-        case 10: return k3_one<T, 10>(a, grid, dyn, s);
+        case 5: return k3_one<T, MFMA, 5>(a, grid, dyn, s);
+        case 6: return k3_one<T, MFMA, 6>(a, grid, dyn, s);
+        case 7: return k3_one<T, MFMA, 7>(a, grid, dyn, s);
+        case 8: return k3_one<T, MFMA, 8>(a, grid, dyn, s);
+        case 9: return k3_one<T, MFMA, 9>(a, grid, dyn, s);
+        case 10: return k3_one<T, MFMA, 10>(a, grid, dyn, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_k3(int prec, int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s) {
-    return prec == kMixed ? k3_dispatch<__half2>(log2n2, a, grid, dyn, s) : k3_dispatch<float2>(log2n2, a, grid, dyn, s);
+    switch (prec) {
+        case kMixed: return k3_dispatch<__half2, true>(log2n2, a, grid, dyn, s);
+        case kMixedValu: return k3_dispatch<__half2, false>(log2n2, a, grid, dyn, s);
+        default: return k3_dispatch<float2, false>(log2n2, a, grid, dyn, s);
+    }
 }
 
 hipError_t launch_fold_reduce(const uint64_t* ps, const uint32_t* pc, int nparts, int entries, uint64_t* acc_sum,

@@ -20,6 +20,7 @@ POND_EDEVICE = -3
 
 POND_FP32 = 0
 POND_MIXED = 1
+POND_MIXED_VALU = 2
 
 POND_STATUS_NONFINITE = 1
 POND_STATUS_RANGE = 2
@@ -190,7 +191,7 @@ class Plan:
 
     def __init__(self, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision="fp32",
                  max_batch=0, subint_nsamp=0, decim=16):
-        prec = {"fp32": POND_FP32, "mixed": POND_MIXED}.get(precision, precision)
+        prec = {"fp32": POND_FP32, "mixed": POND_MIXED, "mixed_valu": POND_MIXED_VALU}.get(precision, precision)
         self.handle = pond_plan_create(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, prec, max_batch)
         self.nbins = int(nbins)
         self.subint = int(subint_nsamp)

@@ -12,7 +12,8 @@ from gpu_helpers import dispersed_pulsar_stream, gpu_run, oracle_run, profile_re
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": (1e-6, 1e-5), "mixed": (1e-4, 1e-2)}
+TOL = {"fp32": (1e-6, 1e-5), "mixed": (1e-4, 1e-2), "mixed_valu": (1e-4, 1e-2)}
+FORMS = ["fp32", "mixed", "mixed_valu"]
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +27,7 @@ def config0_oracle(config0_iq):
     return oracle_run(config0_iq, 1.0, 1 << 18, 256, synth.PERIOD_S, subint=0, decim=16)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+@pytest.mark.parametrize("precision", FORMS)
 def test_config0_parity(config0_iq, config0_oracle, precision):
     print(f"case: config0 DM1 N=2^18 256 bins {precision}", flush=True)
     prof, ser = gpu_run(config0_iq, 1.0, 1 << 18, 256, synth.PERIOD_S, precision=precision)
@@ -67,12 +68,14 @@ def test_sizes_geometry_parity(case):
           flush=True)
     iq = synth.white_stream_int8(nfft + 17, nsamp)
     oprof, oser, r = oracle_run(iq, dm, nfft, nbins, period, subint=subint, decim=decim)
-    prof, ser = gpu_run(iq, dm, nfft, nbins, period, subint=subint, decim=decim)
-    assert prof.shape == oprof.shape
-    assert ser.shape == oser.shape
-    ep, es = profile_rel_l2(prof, oprof), rel_l2(ser, oser)
-    print(f"profile rel-L2 {ep:.3e} series rel-L2 {es:.3e}")
-    assert ep <= 1e-6 and es <= 1e-5
+    for precision in FORMS:
+        prof, ser = gpu_run(iq, dm, nfft, nbins, period, subint=subint, decim=decim, precision=precision)
+        assert prof.shape == oprof.shape
+        assert ser.shape == oser.shape
+        ep, es = profile_rel_l2(prof, oprof), rel_l2(ser, oser)
+        print(f"{precision}: profile rel-L2 {ep:.3e} series rel-L2 {es:.3e}")
+        tp, ts = TOL[precision]
+        assert ep <= tp and es <= ts, precision
 
 
 @pytest.mark.parametrize("log2n", [23, 24])
@@ -85,7 +88,7 @@ def test_large_fft_parity(log2n):
     print(f"case: large nfft=2^{log2n} dm={dm} nsamp={nsamp}", flush=True)
     iq = synth.white_stream_int8(log2n, nsamp)
     oprof, oser, r = oracle_run(iq, dm, nfft, 1024, synth.PERIOD_S, subint=0, decim=16)
-    for precision in ("fp32", "mixed"):
+    for precision in FORMS:
         prof, ser = gpu_run(iq, dm, nfft, 1024, synth.PERIOD_S, precision=precision)
         ep, es = profile_rel_l2(prof, oprof), rel_l2(ser, oser)
         print(f"{precision}: profile rel-L2 {ep:.3e} series rel-L2 {es:.3e}")
@@ -104,7 +107,7 @@ def test_histogram_too_big_for_lds_uses_global_accumulators():
     assert rel_l2(ser, oser) <= 1e-5
 
 
-@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+@pytest.mark.parametrize("precision", FORMS)
 def test_chunking_invariance_is_bitwise(precision):
     """Any split of one stream into calls gives bit-identical outputs."""
     nfft, dm, nbins, period, subint = 1 << 16, 0.9, 300, 4.1e-3, 150001
