@@ -86,7 +86,7 @@ def measured_traffic(kernel_prefix):
     return None
 
 
-def run_form(precision, x, steps, warmup):
+def run_form(precision, x, steps, warmup, graph=False):
     import torch
     import paper_1503_01405_amd as P
 
@@ -124,9 +124,26 @@ def run_form(precision, x, steps, warmup):
     ev_ms = ev0.elapsed_time(ev1) / steps
     kt = P.pond_plan_kernel_times(plan.handle)
     P.pond_plan_set_timing(plan.handle, False)
-    plan.close()
     ms = max(wall, ev_ms)
-    return dict(ms_per_step=ms, ms_events=ev_ms, ms_wall=wall, outputs=nout, kernels=kt, info=info)
+    res = dict(ms_per_step=ms, ms_events=ev_ms, ms_wall=wall, outputs=nout, kernels=kt, info=info)
+    if graph:
+        # the same step captured once into a HIP graph and replayed
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            stream = torch.cuda.current_stream()
+            step()
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        res["graph_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
+        del g
+    plan.close()
+    return res
 
 
 def cpu_baseline(iq_np, nblocks):
@@ -153,6 +170,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--forms", default="fp32,mixed_valu,mixed")
     ap.add_argument("--cpu-blocks", type=int, default=16)
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the step captured once into a HIP graph and replayed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
@@ -186,7 +205,7 @@ def main():
     forms = [f for f in args.forms.split(",") if f]
     res = {}
     for f in forms:
-        res[f] = run_form(f, x, args.steps, args.warmup)
+        res[f] = run_form(f, x, args.steps, args.warmup, graph=args.graph)
         log(f"{f}: {res[f]['ms_per_step']:.3f} ms/step  kernels {res[f]['kernels']}")
 
     head = "mixed" if "mixed" in res else forms[0]
@@ -215,6 +234,8 @@ def main():
         v = r["outputs"] / (r["ms_per_step"] / 1e3) / 1e6
         forms_out[f] = dict(value=round(v, 2), xrealtime=round(v / 16.0, 1), ms_per_step=round(r["ms_per_step"], 3),
                             kernel_ms_per_step={k: round(kv[0] / args.steps, 4) for k, kv in r["kernels"].items()})
+        if "graph_ms_per_step" in r:
+            forms_out[f]["graph_ms_per_step"] = round(r["graph_ms_per_step"], 3)
 
     out = {
         "metric": METRIC,

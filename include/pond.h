@@ -197,6 +197,39 @@ int32_t pond_plan_kernel_times(pond_plan* p, pond_kernel_times* out);
 /* Destroy a plan (NULL-safe); waits for the plan's pending work. */
 void pond_plan_destroy(pond_plan* p);
 
+/*
+ * DM-trial search (one stream dedispersed and folded at many trial DMs).
+ * Each trial t is processed exactly as a single-DM plan of FFT length
+ * N_t = clamp(2 discard_t, nfft_min, nfft_max) (discard_t by the plan
+ * rule above), except that all trials of one N_t share one block grid with
+ * hop = N_t / 2 and therefore one forward transform per block; each keeps
+ * its own n_front_t.  dms (host, ntrials values >= 0), nfft_min/nfft_max
+ * powers of two in [2^10, 2^24]; every trial needs discard_t <= nfft_max/2.
+ * precision as for pond_plan_create_ex.  Returns NULL on invalid arguments
+ * or allocation/device failure.
+ */
+typedef struct pond_search pond_search;
+pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms, int32_t ntrials,
+                                int32_t nbins, double period_s, int64_t nfft_min, int64_t nfft_max,
+                                int32_t precision);
+
+/*
+ * Fold one whole stream (iq: device, 2*nsamp int8) at every trial DM and
+ * write profiles (device, ntrials*nbins float32): trial t's mean detected
+ * power per bin over all outputs of its fully covered blocks (one open-ended
+ * sub-integration; fold phase as above with that trial's n_front).
+ * Asynchronous on hip_stream.  Returns POND_OK, POND_EINVAL or POND_EDEVICE.
+ */
+int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* profiles,
+                        void* hip_stream);
+
+/* FFT length, n_front and hop of trial t. */
+int32_t pond_search_trial(const pond_search* s, int32_t t, int64_t* nfft, int64_t* n_front,
+                          int64_t* hop);
+
+/* Destroy a search (NULL-safe); waits for its pending work. */
+void pond_search_destroy(pond_search* s);
+
 /* Static text for a return code. */
 const char* pond_strerror(int64_t code);
 

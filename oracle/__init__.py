@@ -11,4 +11,5 @@ from .pond_oracle import (DM_CONST_S, DM_CONST_TURNS, plan_geometry, n_blocks,  
                           dedispersion_chirp, unpack, dedisperse_block, dedisperse,
                           detect, decimate, fold_bins, fold, profiles_from, run,
                           disperse_pads, disperse, dispersion_delay_s,
-                          residual_smear_ms, fft_length_eq1)
+                          residual_smear_ms, fft_length_eq1, search_geometry, search,
+                          profile_snr)

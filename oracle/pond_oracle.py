@@ -169,15 +169,21 @@ def dedisperse_block(x_block, chirp, n_front, hop, workers=None):
 
 
 def dedisperse(x, f0_mhz, bw_mhz, dm, nfft, first_block=0, nblocks=None,
-               batch=8, workers=None):
+               batch=8, workers=None, hop=None):
     """Dedispersed voltages of blocks [first_block, first_block + nblocks).
 
     Block b covers input samples [b*hop, b*hop + nfft); its kept outputs are
     outputs m = b*hop + j for j in [0, hop) (input sample m + n_front).
+    `hop` may be given to impose a common block grid (it must not exceed the
+    plan's own hop, so the kept window stays clear of the cyclic edges).
     Returns (y, m0) with y complex128 and m0 the output index of y[0].
     """
     g = plan_geometry(f0_mhz, bw_mhz, dm, nfft)
-    hop, n_front = g["hop"], g["n_front"]
+    n_front = g["n_front"]
+    if hop is None:
+        hop = g["hop"]
+    elif not (0 < hop <= g["hop"]):
+        raise ValueError("imposed hop must be in (0, plan hop]")
     total = n_blocks(x.size, nfft, hop)
     if nblocks is None:
         nblocks = total - first_block
@@ -248,7 +254,7 @@ def profiles_from(sums, cnts):
 
 
 def run(iq, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, subint_nsamp=0,
-        decim=16, batch=8, workers=None, keep_power=False):
+        decim=16, batch=8, workers=None, keep_power=False, hop=None):
     """The whole path over one stream, every fully covered block.
 
     Returns a dict with
@@ -262,7 +268,9 @@ def run(iq, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, subint_nsamp=0,
     """
     g = plan_geometry(f0_mhz, bw_mhz, dm, nfft)
     x = unpack(iq)
-    hop, n_front = g["hop"], g["n_front"]
+    n_front = g["n_front"]
+    if hop is None:
+        hop = g["hop"]
     nb = n_blocks(x.size, nfft, hop)
     n_out = nb * hop
     series = np.empty(n_out // decim, dtype=np.float64)
@@ -273,7 +281,7 @@ def run(iq, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, subint_nsamp=0,
     for b0 in range(0, nb, batch):
         k = min(batch, nb - b0)
         y, m0 = dedisperse(x, f0_mhz, bw_mhz, dm, nfft, first_block=b0,
-                           nblocks=k, batch=batch, workers=workers)
+                           nblocks=k, batch=batch, workers=workers, hop=hop)
         p = detect(y)
         series[m0 // decim:(m0 + p.size) // decim] = decimate(p, decim)
         s, c, s0 = fold(p, m0, n_front, period_s, g["fs"], nbins, subint_nsamp)
@@ -282,6 +290,7 @@ def run(iq, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, subint_nsamp=0,
         if keep_power:
             power[m0:m0 + p.size] = p
     complete = (n_out // subint_nsamp) if subint_nsamp > 0 else 0
+    g = dict(g, hop=hop)
     return dict(geometry=g, n_out=n_out, series=series, sums=sums, cnts=cnts,
                 profiles=profiles_from(sums, cnts), complete=complete,
                 power=power)
@@ -316,3 +325,56 @@ def disperse(z, f0_mhz, bw_mhz, dm, nfft):
         y = sfft.ifft(sfft.fft(zp[b * hop:b * hop + nfft]) * H)
         out[b * hop:(b + 1) * hop] = y[pad_lo:pad_lo + hop]
     return out[:n_keep]
+
+
+# --------------------------------------------------------------------------
+# DM-trial search (one stream folded at many trial DMs)
+# --------------------------------------------------------------------------
+def search_geometry(f0_mhz, bw_mhz, dms, nfft_min=1 << 20, nfft_max=1 << 23):
+    """Per-trial FFT length and common block grid of a DM search.
+
+    Reading: each trial takes discard_t by the plan rule (C3) and
+    N_t = clamp(2 discard_t, nfft_min, nfft_max); trials with equal N_t form
+    a group that shares one block grid with hop = N_t / 2 (every trial's
+    kept window [n_front_t, n_front_t + hop) stays clear of the cyclic
+    edges because discard_t <= N_t / 2), so the forward transform of a
+    block is shared by the whole group.  Returns a list of dicts.
+    """
+    out = []
+    for dm in dms:
+        g = plan_geometry(f0_mhz, bw_mhz, dm, nfft_max)
+        if g["discard"] > nfft_max // 2:
+            raise ValueError(f"DM {dm}: smear too long for nfft_max")
+        n = max(nfft_min, min(nfft_max, 2 * g["discard"]))
+        gn = plan_geometry(f0_mhz, bw_mhz, dm, n)
+        out.append(dict(dm=float(dm), nfft=n, n_front=gn["n_front"], hop=n // 2))
+    return out
+
+
+def search(iq, f0_mhz, bw_mhz, dms, nbins, period_s, nfft_min=1 << 20,
+           nfft_max=1 << 23, workers=None):
+    """Folded profile (mean power per bin over every output of the stream)
+    of each trial DM, each trial dedispersed as in `run` with its own chirp
+    and n_front on its group's block grid."""
+    geo = search_geometry(f0_mhz, bw_mhz, dms, nfft_min, nfft_max)
+    profs = []
+    for t in geo:
+        r = run(iq, f0_mhz, bw_mhz, t["dm"], t["nfft"], nbins, period_s,
+                subint_nsamp=0, decim=16, workers=workers, hop=t["hop"])
+        profs.append(r["profiles"][0] if r["n_out"] else np.zeros(nbins))
+    return np.array(profs), geo
+
+
+def profile_snr(profile, on_frac=0.1):
+    """Peak signal-to-noise of a folded profile: (max - median) over the
+    standard deviation of the bins outside the +-on_frac window around the
+    peak."""
+    p = np.asarray(profile, dtype=np.float64)
+    n = p.size
+    k = int(np.argmax(p))
+    w = max(1, int(on_frac * n))
+    mask = np.ones(n, dtype=bool)
+    for d in range(-w, w + 1):
+        mask[(k + d) % n] = False
+    off = p[mask]
+    return float((p[k] - np.median(off)) / off.std())

@@ -8,4 +8,5 @@ from .pond import (POND_EDEVICE, POND_EINVAL, POND_ENOMEM, POND_FP32, POND_MIXED
                    POND_OK, POND_STATUS_NONFINITE, POND_STATUS_RANGE, Plan, PondError,
                    pond_dedisperse_fold, pond_dedisperse_series, pond_plan_create,
                    pond_plan_destroy, pond_plan_expect, pond_plan_kernel_times,
-                   pond_plan_query, pond_plan_set_timing)
+                   pond_plan_query, pond_plan_set_timing, pond_search_create, pond_search_destroy,
+                   pond_search_run, pond_search_trial)

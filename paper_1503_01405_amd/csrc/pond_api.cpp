@@ -22,10 +22,6 @@ thread_local int32_t g_create_status = POND_OK;
 constexpr int64_t kMinLog2N = 10;
 constexpr int64_t kMaxLog2N = 24;
 constexpr int kMaxLog2N2 = 10;          // column length cap (K1/K3 tile = 16 columns in LDS)
-constexpr size_t kLdsBytes = 160 * 1024; // gfx950 LDS per workgroup
-constexpr int64_t kHistCapMax = 8192;   // fold histogram entries held in LDS
-constexpr int kCus = 256;
-constexpr int64_t kPartEntries = 1 << 21;  // per-workgroup fold partials: grid * entries <= this
 
 int ilog2(int64_t v) {
     int r = 0;
@@ -58,7 +54,6 @@ struct pond_plan {
     uint64_t* part_sum = nullptr;
     uint32_t* part_cnt = nullptr;
     int64_t hist_cap = 0;
-    int k3_grid_max = 0;
     uint64_t* status = nullptr;  // low 32 bits used
 
     // per-kernel timing (measurement only)
@@ -163,13 +158,6 @@ int64_t n_blocks_for(int64_t nsamp, int64_t nfft, int64_t hop) {
     return nsamp < nfft ? 0 : (nsamp - nfft) / hop + 1;
 }
 
-int k3_wg_per_cu(size_t lds_bytes) {
-    int w = (int)(kLdsBytes / (lds_bytes ? lds_bytes : 1));
-    if (w < 1) w = 1;
-    if (w > 4) w = 4;
-    return w;
-}
-
 }  // namespace
 
 extern "C" {
@@ -257,10 +245,7 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     }
     p->max_batch = max_batch;
 
-    const size_t k3_static = k3_static_lds(p->log2n2);
-    int64_t cap = (int64_t)((kLdsBytes - k3_static) / 12);
-    p->hist_cap = cap < kHistCapMax ? cap : kHistCapMax;
-    p->k3_grid_max = kCus * 4;
+    p->hist_cap = hist_capacity(p->log2n2);
 
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) {
@@ -542,14 +527,14 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         e = timed(0, nb, [&] { return launch_k1(p->precision, n2log, a1, stream); });
         if (e != hipSuccess) return fail(e);
 
-        K2Args a2;
+        K2Args a2{};
         a2.work = p->work;
         a2.nblocks = (int32_t)nb;
         a2.log2n2 = n2log;
         a2.tw1 = p->tw1;
         a2.table = p->table;
         a2.scale = k2_scale;
-        e = timed(1, nb, [&] { return launch_k2(p->precision, p->log2n1, a2, stream); });
+        e = timed(1, nb, [&] { return launch_k2(p->precision, kRowFull, p->log2n1, a2, stream); });
         if (e != hipSuccess) return fail(e);
 
         K3Args a3;
@@ -577,14 +562,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a3.acc_s0 = s_open;
         a3.status = reinterpret_cast<uint32_t*>(p->status);
         const size_t dyn = global_mode ? 0 : (size_t)entries * 12;
-        const int64_t items = nb * (n1 / 16);
-        int64_t grid = kCus * k3_wg_per_cu(k3_static_lds(n2log) + dyn);
-        if (grid > p->k3_grid_max) grid = p->k3_grid_max;
-        if (!global_mode && grid * entries > kPartEntries) grid = kPartEntries / entries;
-        const int64_t items8 = (items + 7) & ~int64_t(7);
-        if (grid > items8) grid = items8;
-        grid &= ~int64_t(7);
-        if (grid < 8) grid = 8;
+        const int grid = k3_grid(n2log, dyn, nb * (n1 / 16), entries, global_mode);
         e = timed(2, nb, [&] { return launch_k3(p->precision, n2log, a3, (int)grid, dyn, stream); });
         if (e != hipSuccess) return fail(e);
         if (!global_mode) {

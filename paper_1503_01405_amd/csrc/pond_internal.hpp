@@ -32,12 +32,18 @@ struct K1Args {
 
 // K2: four-step twiddle, forward row FFT (length n1), chirp, inverse row
 // FFT, conjugate twiddle.
+enum RowMode { kRowFull = 0, kRowFwd = 1, kRowInv = 2 };
+
 struct K2Args {
-    void* work;
+    void* work;             // rows, in place (kRowFull, kRowFwd)
+    const void* in;         // spectrum rows (kRowInv)
+    void* out;              // result rows (kRowInv)
     int32_t nblocks;
     int32_t log2n2;
     const float2* tw1;      // exp(-2 pi i t / n1), t < n1
-    const float4* table;    // [n2][n1]: four-step twiddle (x, y), inverse ISM response (z, w)
+    const float4* table;    // kRowFull: [n2][n1] four-step twiddle (x, y), inverse ISM response (z, w)
+    const float2* tw4;      // kRowFwd, kRowInv: [n2][n1] four-step twiddle
+    const float2* chirp;    // kRowInv: [n2][n1] inverse ISM response of one trial
     float scale;            // power-of-two scale applied on output
 };
 
@@ -72,7 +78,7 @@ struct K3Args {
 
 // Launchers; each returns the HIP error of the launch.
 hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s);
-hipError_t launch_k2(int prec, int log2n1, const K2Args& a, hipStream_t s);
+hipError_t launch_k2(int prec, int mode, int log2n1, const K2Args& a, hipStream_t s);
 hipError_t launch_k3(int prec, int log2n2, const K3Args& a, int grid, size_t dyn_lds, hipStream_t s);
 hipError_t launch_fold_reduce(const uint64_t* part_sum, const uint32_t* part_cnt, int nparts, int entries,
                               uint64_t* acc_sum, uint64_t* acc_cnt, int64_t acc_off, hipStream_t s);
@@ -81,6 +87,20 @@ hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins,
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
                                  hipStream_t s);
+hipError_t launch_k2_build_split_tables(float2* tw, float2* chirp, int log2n1, int log2n2, double chirp_a, double f0,
+                                        double df, hipStream_t s);
+
+hipError_t launch_fold_profiles(const uint64_t* acc_sum, const uint64_t* acc_cnt, int64_t n, float* profiles,
+                                hipStream_t s);
+
+// Workgroups of a K3 launch: enough to fill the chip at the occupancy the
+// LDS allows, at most one per item, a multiple of 8, and within the
+// partial-histogram budget.
+int k3_grid(int log2n2, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode);
+constexpr int64_t kPartEntries = 1 << 21;  // per-workgroup fold partials: grid * entries <= this
+constexpr int64_t kHistCapMax = 8192;      // fold histogram entries held in LDS
+constexpr size_t kLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
+int64_t hist_capacity(int log2n2);
 
 // Static LDS bytes of the K3 tile for a column length 2^log2n2.
 size_t k3_static_lds(int log2n2);

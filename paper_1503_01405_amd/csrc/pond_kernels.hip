@@ -157,7 +157,13 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 // indices on one XCD, so they run together and share the row's table entries
 // through that XCD's L2 (the table is then fetched from HBM about once per
 // launch).
-template <int LOG2N1, class T>
+//   MODE kRowFull: twiddle, forward FFT, chirp, inverse FFT, conjugate
+//                  twiddle, in place (float4 table: twiddle, chirp).
+//   MODE kRowFwd:  twiddle and forward FFT only, in place: leaves the block's
+//                  spectrum, row k2 holding bins k2 + n2 k1 (float2 twiddle table).
+//   MODE kRowInv:  spectrum (in) times one trial's chirp (float2 table),
+//                  inverse FFT, conjugate twiddle, to `out`.
+template <int LOG2N1, class T, int MODE>
 __global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k2_row(K2Args a) {
     using Sh = K2Shape<LOG2N1>;
@@ -186,26 +192,49 @@ k2_row(K2Args a) {
     // store).
     const int row0 = min(rg * Sh::ROWS, n2 - 1);
     const uint32_t toff = (uint32_t)(min(r, n2 - 1 - row0) << LOG2N1) + (uint32_t)j;
+    const int64_t rowbase = (((int64_t)b << a.log2n2) + row0) << LOG2N1;
     const float4* tab = a.table + ((int64_t)row0 << LOG2N1);
-    T* rows = reinterpret_cast<T*>(a.work) + ((((int64_t)b << a.log2n2) + row0) << LOG2N1);
+    const float2* tw4 = a.tw4 + ((int64_t)row0 << LOG2N1);
+    const float2* chirp = a.chirp + ((int64_t)row0 << LOG2N1);
+    T* rows = reinterpret_cast<T*>(a.work) + rowbase;
+    const T* src = MODE == kRowInv ? reinterpret_cast<const T*>(a.in) + rowbase : rows;
+    T* dst = MODE == kRowInv ? reinterpret_cast<T*>(a.out) + rowbase : rows;
 
     float2 v[16];
     uint32_t to = opaque(toff);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const float2 x = Elem<T>::load(at(rows, (to + TPV * e) * (uint32_t)sizeof(T)));
-        const float4 t = *at(tab, (to + TPV * e) * 16u);
-        v[e] = cmul(x, make_float2(t.x, t.y));
+        const float2 x = Elem<T>::load(at(src, (to + TPV * e) * (uint32_t)sizeof(T)));
+        if constexpr (MODE == kRowFull) {
+            const float4 t = *at(tab, (to + TPV * e) * 16u);
+            v[e] = cmul(x, make_float2(t.x, t.y));
+        } else if constexpr (MODE == kRowFwd) {
+            v[e] = cmul(x, *at(tw4, (to + TPV * e) * 8u));
+        } else {
+            v[e] = cmul(x, *at(chirp, (to + TPV * e) * 8u));
+        }
     }
-    fft_wg<LOG2N1, -1>(v, j, tb, ld, st);
-    // Re-read the table (from L2) rather than keep it live across the
-    // transforms: registers are the occupancy limit of this kernel.
-    asm volatile("" ::: "memory");
-    to = opaque(toff);
+    if constexpr (MODE != kRowInv) {
+        fft_wg<LOG2N1, -1>(v, j, tb, ld, st);
+    }
+    if constexpr (MODE == kRowFull) {
+        // Re-read the table (from L2) rather than keep it live across the
+        // transforms: registers are the occupancy limit of this kernel.
+        asm volatile("" ::: "memory");
+        to = opaque(toff);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const float4 t = *at(tab, (to + TPV * e) * 16u);
-        v[e] = cmul(v[e], make_float2(t.z, t.w));
+        for (int e = 0; e < 16; ++e) {
+            const float4 t = *at(tab, (to + TPV * e) * 16u);
+            v[e] = cmul(v[e], make_float2(t.z, t.w));
+        }
+    }
+    if constexpr (MODE == kRowFwd) {
+        if (valid) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+        }
+        return;
     }
     fft_wg<LOG2N1, +1>(v, j, tb, ld, st);
     asm volatile("" ::: "memory");
@@ -213,11 +242,44 @@ k2_row(K2Args a) {
     if (valid) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const float4 t = *at(tab, (to + TPV * e) * 16u);
-            Elem<T>::store(at(rows, (to + TPV * e) * (uint32_t)sizeof(T)),
-                           cscale(cmulc(v[e], make_float2(t.x, t.y)), a.scale));
+            float2 w;
+            if constexpr (MODE == kRowFull) {
+                const float4 t = *at(tab, (to + TPV * e) * 16u);
+                w = make_float2(t.x, t.y);
+            } else {
+                w = *at(tw4, (to + TPV * e) * 8u);
+            }
+            Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(cmulc(v[e], w), a.scale));
         }
     }
+}
+
+// Tables of the split middle pass: tw[i] = W_n^(k1 k2) for i = k2 n1 + k1;
+// per trial DM, chirp[i] = exp(-2 pi i turns_k), k = k2 + n2 k1, turns in
+// float64 reduced mod 1 (Sec. 3.7 / Eq. (4)).
+__global__ void __launch_bounds__(256) k2_build_split_tables(float2* __restrict__ tw, float2* __restrict__ chirp,
+                                                              int log2n1, int log2n2, double chirp_a, double f0,
+                                                              double df) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
+    const int64_t n = 1ll << log2n;
+    if (i >= n) return;
+    const int64_t k2 = i >> log2n1;
+    const int64_t k1 = i & ((1ll << log2n1) - 1);
+    if (tw) {
+        const int64_t r = (k1 * k2) & (n - 1);
+        double s, c;
+        sincospi(2.0 * (double)r / (double)n, &s, &c);
+        tw[i] = make_float2((float)c, (float)-s);
+    }
+    const int64_t k = k2 + (k1 << log2n2);
+    const int64_t kk = k < (n >> 1) ? k : k - n;
+    const double f = (double)kk * df;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double cs, cc;
+    sincospi(2.0 * frac, &cs, &cc);
+    chirp[i] = make_float2((float)cc, (float)-cs);
 }
 
 // ------------------------------------------------------------------- K3
@@ -479,6 +541,15 @@ __global__ void __launch_bounds__(256) fold_finalize(uint64_t* acc_sum, uint64_t
     }
 }
 
+// Mean power per (trial, bin): sum / count, 0 for an empty bin.
+__global__ void __launch_bounds__(256) fold_profiles(const uint64_t* acc_sum, const uint64_t* acc_cnt, int64_t n,
+                                                     float* profiles) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t c = acc_cnt[i];
+    profiles[i] = c ? (float)(((double)acc_sum[i] / kFoldScale) / (double)c) : 0.f;
+}
+
 __global__ void __launch_bounds__(256) zero_u64(uint64_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -514,34 +585,52 @@ hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s) {
     }
 }
 
-template <class T, int LOG2N1>
+template <class T, int MODE, int LOG2N1>
 static hipError_t k2_one(const K2Args& a, hipStream_t s) {
     using Sh = K2Shape<LOG2N1>;
     const int groups = ((1 << a.log2n2) + Sh::ROWS - 1) / Sh::ROWS * a.nblocks;
     const int grid = (groups + 7) & ~7;
-    hipLaunchKernelGGL((k2_row<LOG2N1, T>), dim3(grid), dim3(Sh::THREADS), 0, s, a);
+    hipLaunchKernelGGL((k2_row<LOG2N1, T, MODE>), dim3(grid), dim3(Sh::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-template <class T>
+template <class T, int MODE>
 static hipError_t k2_dispatch(int log2n1, const K2Args& a, hipStream_t s) {
     switch (log2n1) {
-        case 5: return k2_one<T, 5>(a, s);
-        case 6: return k2_one<T, 6>(a, s);
-        case 7: return k2_one<T, 7>(a, s);
-        case 8: return k2_one<T, 8>(a, s);
-        case 9: return k2_one<T, 9>(a, s);
-        case 10: return k2_one<T, 10>(a, s);
-        case 11: return k2_one<T, 11>(a, s);
-        case 12: return k2_one<T, 12>(a, s);
-        case 13: return k2_one<T, 13>(a, s);
-        case 14: return k2_one<T, 14>(a, s);
+        case 5: return k2_one<T, MODE, 5>(a, s);
+        case 6: return k2_one<T, MODE, 6>(a, s);
+        case 7: return k2_one<T, MODE, 7>(a, s);
+        case 8: return k2_one<T, MODE, 8>(a, s);
+        case 9: return k2_one<T, MODE, 9>(a, s);
+        case 10: return k2_one<T, MODE, 10>(a, s);
+        case 11: return k2_one<T, MODE, 11>(a, s);
+        case 12: return k2_one<T, MODE, 12>(a, s);
+        case 13: return k2_one<T, MODE, 13>(a, s);
+        case 14: return k2_one<T, MODE, 14>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_k2(int prec, int log2n1, const K2Args& a, hipStream_t s) {
-    return prec == kFp32 ? k2_dispatch<float2>(log2n1, a, s) : k2_dispatch<__half2>(log2n1, a, s);
+template <int MODE>
+static hipError_t k2_prec(int prec, int log2n1, const K2Args& a, hipStream_t s) {
+    return prec == kFp32 ? k2_dispatch<float2, MODE>(log2n1, a, s) : k2_dispatch<__half2, MODE>(log2n1, a, s);
+}
+
+hipError_t launch_k2(int prec, int mode, int log2n1, const K2Args& a, hipStream_t s) {
+    switch (mode) {
+        case kRowFull: return k2_prec<kRowFull>(prec, log2n1, a, s);
+        case kRowFwd: return k2_prec<kRowFwd>(prec, log2n1, a, s);
+        case kRowInv: return k2_prec<kRowInv>(prec, log2n1, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_k2_build_split_tables(float2* tw, float2* chirp, int log2n1, int log2n2, double chirp_a, double f0,
+                                        double df, hipStream_t s) {
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    hipLaunchKernelGGL(k2_build_split_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tw, chirp, log2n1,
+                       log2n2, chirp_a, f0, df);
+    return hipGetLastError();
 }
 
 template <class T, bool MFMA, int LOG2N2>
@@ -601,6 +690,32 @@ hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
+}
+
+hipError_t launch_fold_profiles(const uint64_t* acc_sum, const uint64_t* acc_cnt, int64_t n, float* profiles,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fold_profiles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, acc_sum, acc_cnt, n,
+                       profiles);
+    return hipGetLastError();
+}
+
+int64_t hist_capacity(int log2n2) {
+    const int64_t cap = (int64_t)((kLdsBytes - k3_static_lds(log2n2)) / 12);
+    return cap < kHistCapMax ? cap : kHistCapMax;
+}
+
+int k3_grid(int log2n2, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode) {
+    const size_t lds = k3_static_lds(log2n2) + dyn_lds;
+    int per_cu = (int)(kLdsBytes / lds);
+    per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+    int64_t grid = 256 * per_cu;
+    if (!global_mode && grid * entries > kPartEntries) grid = kPartEntries / entries;
+    const int64_t items8 = (items + 7) & ~int64_t(7);
+    if (grid > items8) grid = items8;
+    grid &= ~int64_t(7);
+    if (grid < 8) grid = 8;
+    return (int)grid;
 }
 
 size_t k3_static_lds(int log2n2) { return sizeof(float2) * 16 * ((size_t)1 << log2n2); }

@@ -1,0 +1,345 @@
+// DM-trial search: one stream dedispersed and folded at many trial DMs.
+//
+// Trials are grouped by FFT length (N_t = clamp(2 discard_t, nfft_min,
+// nfft_max), discard_t by the plan rule of the single-DM path); a group
+// shares one block grid with hop = N_t / 2, so each block's forward
+// transform (int8 unpack + column FFTs + twiddle + row FFTs) runs once per
+// group.  Each trial then multiplies the stored spectrum by its own inverse
+// ISM response (Sec. 3.7, Eq. (4)), inverts the row and column transforms,
+// detects and folds into its own integer accumulators.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pond.h"
+#include "pond_internal.hpp"
+
+using namespace pond;
+
+namespace {
+
+constexpr int kSearchMaxLog2N = 24;
+
+struct Group {
+    int64_t nfft = 0, hop = 0;
+    int log2n = 0, log2n1 = 0, log2n2 = 0;
+    int max_batch = 1;
+    std::vector<int> trials;
+    float2* tw1 = nullptr;    // exp(-2 pi i t / n1)
+    float2* tw2 = nullptr;    // exp(-2 pi i t / n2)
+    float2* tw4 = nullptr;    // [n2][n1] four-step twiddle
+    std::vector<float2*> chirp;  // per trial of the group, [n2][n1]
+    void* spec = nullptr;     // max_batch blocks of spectrum
+    void* out = nullptr;      // max_batch blocks of one trial's row-inverse output
+};
+
+std::vector<float2> stage_twiddles(int64_t n) {
+    std::vector<float2> w((size_t)n);
+    for (int64_t t = 0; t < n; ++t) {
+        const double a = 2.0 * M_PI * (double)t / (double)n;
+        w[(size_t)t] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    return w;
+}
+
+int ilog2(int64_t v) {
+    int r = 0;
+    while ((int64_t(1) << r) < v) ++r;
+    return r;
+}
+
+}  // namespace
+
+struct pond_search {
+    int device = 0;
+    double f0 = 0, bw = 0, period = 0, fs = 0, inv_pfs = 0;
+    int32_t nbins = 0, precision = 0, ntrials = 0;
+    size_t elem = 8;
+    std::vector<double> dm;
+    std::vector<int64_t> n_front;
+    std::vector<int> group_of;
+    std::vector<Group> groups;
+    uint64_t* acc_sum = nullptr;  // [ntrials][nbins]
+    uint64_t* acc_cnt = nullptr;
+    uint64_t* part_sum = nullptr;
+    uint32_t* part_cnt = nullptr;
+    uint64_t* status = nullptr;
+    bool sticky = false;
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+void free_search(pond_search* s) {
+    for (auto& g : s->groups) {
+        void* ptrs[] = {g.tw1, g.tw2, g.tw4, g.spec, g.out};
+        for (void* q : ptrs)
+            if (q) (void)hipFree(q);
+        for (float2* c : g.chirp)
+            if (c) (void)hipFree(c);
+    }
+    void* ptrs[] = {s->acc_sum, s->acc_cnt, s->part_sum, s->part_cnt, s->status};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+}
+
+// Plan geometry of the single-DM path (same expressions, float64).
+void trial_geometry(double f0, double bw, double dm, int64_t* n_front, int64_t* discard) {
+    const double fs = bw * 1e6;
+    const double k_dm = 1.0 / 2.41e-4;
+    const double f_lo = f0 - bw / 2, f_hi = f0 + bw / 2;
+    const double delta_lo = k_dm * dm * (1.0 / (f_lo * f_lo) - 1.0 / (f0 * f0));
+    const double delta_hi = k_dm * dm * (1.0 / (f0 * f0) - 1.0 / (f_hi * f_hi));
+    const int64_t nf = (int64_t)std::ceil(delta_hi * fs);
+    const int64_t s = nf + (int64_t)std::ceil(delta_lo * fs);
+    int64_t d = 0;
+    if (s > 0) {
+        d = 16;
+        while (d < s) d <<= 1;
+    }
+    *n_front = nf;
+    *discard = d;
+}
+
+}  // namespace
+
+extern "C" {
+
+pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms, int32_t ntrials, int32_t nbins,
+                                double period_s, int64_t nfft_min, int64_t nfft_max, int32_t precision) {
+    if (!dms || ntrials < 1 || nbins < 1 || nbins > 65536) return nullptr;
+    if (!std::isfinite(f0_mhz) || !std::isfinite(bw_mhz) || !std::isfinite(period_s)) return nullptr;
+    if (!(bw_mhz > 0) || !(f0_mhz - bw_mhz / 2 > 0)) return nullptr;
+    if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU) return nullptr;
+    if (nfft_min <= 0 || (nfft_min & (nfft_min - 1)) || nfft_max < nfft_min || (nfft_max & (nfft_max - 1)))
+        return nullptr;
+    if (ilog2(nfft_min) < 10 || ilog2(nfft_max) > kSearchMaxLog2N) return nullptr;
+    const double fs = bw_mhz * 1e6;
+    if (!(period_s > 0) || !(period_s * fs >= 1.0)) return nullptr;
+    for (int t = 0; t < ntrials; ++t)
+        if (!std::isfinite(dms[t]) || !(dms[t] >= 0) || dms[t] > 1e6) return nullptr;
+
+    pond_search* s = new (std::nothrow) pond_search();
+    if (!s) return nullptr;
+    s->f0 = f0_mhz;
+    s->bw = bw_mhz;
+    s->period = period_s;
+    s->fs = fs;
+    s->inv_pfs = 1.0 / (period_s * fs);
+    s->nbins = nbins;
+    s->precision = precision;
+    s->ntrials = ntrials;
+    s->elem = precision == POND_FP32 ? 8 : 4;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return nullptr;
+    }
+    // Trial geometry and grouping by FFT length.
+    s->dm.assign(dms, dms + ntrials);
+    s->n_front.resize(ntrials);
+    s->group_of.resize(ntrials);
+    for (int t = 0; t < ntrials; ++t) {
+        int64_t nf, d;
+        trial_geometry(f0_mhz, bw_mhz, dms[t], &nf, &d);
+        if (d > nfft_max / 2) {
+            delete s;
+            return nullptr;
+        }
+        int64_t n = 2 * d;
+        n = n < nfft_min ? nfft_min : (n > nfft_max ? nfft_max : n);
+        s->n_front[t] = nf;
+        int gi = -1;
+        for (size_t i = 0; i < s->groups.size(); ++i)
+            if (s->groups[i].nfft == n) gi = (int)i;
+        if (gi < 0) {
+            Group g;
+            g.nfft = n;
+            g.hop = n / 2;
+            g.log2n = ilog2(n);
+            g.log2n2 = g.log2n / 2 < 10 ? g.log2n / 2 : 10;
+            g.log2n1 = g.log2n - g.log2n2;
+            int64_t b = ((int64_t)1 << 28) / (n * (int64_t)s->elem);
+            g.max_batch = (int)(b < 1 ? 1 : (b > 16 ? 16 : b));
+            s->groups.push_back(g);
+            gi = (int)s->groups.size() - 1;
+        }
+        s->group_of[t] = gi;
+        s->groups[gi].trials.push_back(t);
+    }
+
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    for (auto& g : s->groups) {
+        const int64_t n1 = (int64_t)1 << g.log2n1, n2 = (int64_t)1 << g.log2n2;
+        const std::vector<float2> t1 = stage_twiddles(n1), t2 = stage_twiddles(n2);
+        chk(hipMalloc(reinterpret_cast<void**>(&g.tw1), n1 * sizeof(float2)));
+        chk(hipMalloc(reinterpret_cast<void**>(&g.tw2), n2 * sizeof(float2)));
+        if (e == hipSuccess) chk(hipMemcpy(g.tw1, t1.data(), n1 * sizeof(float2), hipMemcpyHostToDevice));
+        if (e == hipSuccess) chk(hipMemcpy(g.tw2, t2.data(), n2 * sizeof(float2), hipMemcpyHostToDevice));
+        chk(hipMalloc(reinterpret_cast<void**>(&g.tw4), g.nfft * sizeof(float2)));
+        chk(hipMalloc(&g.spec, (size_t)g.max_batch * g.nfft * s->elem));
+        chk(hipMalloc(&g.out, (size_t)g.max_batch * g.nfft * s->elem));
+        g.chirp.assign(g.trials.size(), nullptr);
+        for (size_t i = 0; i < g.trials.size() && e == hipSuccess; ++i) {
+            chk(hipMalloc(reinterpret_cast<void**>(&g.chirp[i]), g.nfft * sizeof(float2)));
+            const double dm = s->dm[g.trials[i]];
+            if (e == hipSuccess)
+                chk(launch_k2_build_split_tables(i == 0 ? g.tw4 : nullptr, g.chirp[i], g.log2n1, g.log2n2,
+                                                 dm / (2.41e-10 * f0_mhz * f0_mhz), f0_mhz,
+                                                 bw_mhz / (double)g.nfft, nullptr));
+        }
+    }
+    chk(hipMalloc(reinterpret_cast<void**>(&s->acc_sum), (size_t)ntrials * nbins * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&s->acc_cnt), (size_t)ntrials * nbins * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&s->part_sum), (size_t)kPartEntries * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&s->part_cnt), (size_t)kPartEntries * 4));
+    chk(hipMalloc(reinterpret_cast<void**>(&s->status), 8));
+    if (e == hipSuccess) chk(hipMemset(s->status, 0, 8));
+    if (e == hipSuccess) chk(hipDeviceSynchronize());
+    if (e != hipSuccess) {
+        free_search(s);
+        delete s;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return s;
+}
+
+int32_t pond_search_trial(const pond_search* s, int32_t t, int64_t* nfft, int64_t* n_front, int64_t* hop) {
+    if (!s || t < 0 || t >= s->ntrials) return POND_EINVAL;
+    const Group& g = s->groups[s->group_of[t]];
+    if (nfft) *nfft = g.nfft;
+    if (n_front) *n_front = s->n_front[t];
+    if (hop) *hop = g.hop;
+    return POND_OK;
+}
+
+int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* profiles, void* stream_ptr) {
+    if (!s) return POND_EINVAL;
+    if (s->sticky) return POND_EDEVICE;
+    if (nsamp < 0 || (nsamp > 0 && (!iq || (reinterpret_cast<uintptr_t>(iq) & 1u))) || !profiles)
+        return POND_EINVAL;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return POND_EDEVICE;
+    if (cur != s->device && hipSetDevice(s->device) != hipSuccess) return POND_EDEVICE;
+    hipError_t e = hipSuccess;
+    auto done = [&](int32_t r) {
+        if (cur != s->device) (void)hipSetDevice(cur);
+        return r;
+    };
+    auto fail = [&]() {
+        (void)hipGetLastError();
+        s->sticky = true;
+        return done(POND_EDEVICE);
+    };
+    const int32_t nbins = s->nbins;
+    e = launch_zero_u64(s->acc_sum, (int64_t)s->ntrials * nbins, stream);
+    if (e == hipSuccess) e = launch_zero_u64(s->acc_cnt, (int64_t)s->ntrials * nbins, stream);
+    if (e != hipSuccess) return fail();
+    const bool global_mode_all = false;
+    (void)global_mode_all;
+
+    for (auto& g : s->groups) {
+        const int64_t nb_total = nsamp < g.nfft ? 0 : (nsamp - g.nfft) / g.hop + 1;
+        const int64_t n1 = (int64_t)1 << g.log2n1;
+        const int64_t cap = hist_capacity(g.log2n2);
+        const bool global_mode = nbins > cap;
+        for (int64_t b = 0; b < nb_total; b += g.max_batch) {
+            const int nb = (int)(nb_total - b < g.max_batch ? nb_total - b : g.max_batch);
+            K1Args a1{};
+            a1.tail = iq;
+            a1.tail_start = 0;
+            a1.in = iq;
+            a1.in_start = 0;
+            a1.hop = g.hop;
+            a1.block0 = b;
+            a1.nblocks = nb;
+            a1.log2n1 = g.log2n1;
+            a1.work = g.spec;
+            a1.tw2 = g.tw2;
+            a1.scale = std::ldexp(1.0f, -g.log2n2);
+            e = launch_k1(s->precision, g.log2n2, a1, stream);
+            if (e != hipSuccess) return fail();
+            K2Args f{};
+            f.work = g.spec;
+            f.nblocks = nb;
+            f.log2n2 = g.log2n2;
+            f.tw1 = g.tw1;
+            f.tw4 = g.tw4;
+            f.scale = std::ldexp(1.0f, -g.log2n1);
+            e = launch_k2(s->precision, kRowFwd, g.log2n1, f, stream);
+            if (e != hipSuccess) return fail();
+            for (size_t i = 0; i < g.trials.size(); ++i) {
+                const int t = g.trials[i];
+                K2Args v{};
+                v.in = g.spec;
+                v.out = g.out;
+                v.nblocks = nb;
+                v.log2n2 = g.log2n2;
+                v.tw1 = g.tw1;
+                v.tw4 = g.tw4;
+                v.chirp = g.chirp[i];
+                v.scale = 1.0f;
+                e = launch_k2(s->precision, kRowInv, g.log2n1, v, stream);
+                if (e != hipSuccess) return fail();
+                K3Args a3{};
+                a3.work = g.out;
+                a3.nblocks = nb;
+                a3.log2n1 = g.log2n1;
+                a3.hop = g.hop;
+                a3.n_front = s->n_front[t];
+                a3.block0 = b;
+                a3.tw2 = g.tw2;
+                a3.scale = 1.0f;
+                a3.series = nullptr;
+                a3.series_base = 0;
+                a3.decim = 16;
+                a3.nbins = nbins;
+                a3.inv_pfs = s->inv_pfs;
+                a3.subint = 0;
+                a3.s_base = 0;
+                a3.entries = nbins;
+                a3.global_mode = global_mode ? 1 : 0;
+                a3.part_sum = s->part_sum;
+                a3.part_cnt = s->part_cnt;
+                a3.acc_sum = s->acc_sum + (int64_t)t * nbins;
+                a3.acc_cnt = s->acc_cnt + (int64_t)t * nbins;
+                a3.acc_s0 = 0;
+                a3.status = reinterpret_cast<uint32_t*>(s->status);
+                const size_t dyn = global_mode ? 0 : (size_t)nbins * 12;
+                const int grid = k3_grid(g.log2n2, dyn, (int64_t)nb * (n1 / 16), nbins, global_mode);
+                e = launch_k3(s->precision, g.log2n2, a3, grid, dyn, stream);
+                if (e != hipSuccess) return fail();
+                if (!global_mode) {
+                    e = launch_fold_reduce(s->part_sum, s->part_cnt, grid, nbins, a3.acc_sum, a3.acc_cnt, 0, stream);
+                    if (e != hipSuccess) return fail();
+                }
+            }
+        }
+    }
+    e = launch_fold_profiles(s->acc_sum, s->acc_cnt, (int64_t)s->ntrials * nbins, profiles, stream);
+    if (e != hipSuccess) return fail();
+    s->last_stream = stream;
+    return done(POND_OK);
+}
+
+void pond_search_destroy(pond_search* s) {
+    if (!s) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != s->device) (void)hipSetDevice(s->device);
+    if (s->last_stream) (void)hipStreamSynchronize(s->last_stream);
+    (void)hipDeviceSynchronize();
+    free_search(s);
+    if (cur >= 0 && cur != s->device) (void)hipSetDevice(cur);
+    delete s;
+}
+
+}  // extern "C"

@@ -30,6 +30,7 @@ EXPORTS = (
     "pond_dedisperse_fold", "pond_dedisperse_series", "pond_plan_query",
     "pond_plan_expect", "pond_plan_destroy", "pond_strerror",
     "pond_plan_set_timing", "pond_plan_kernel_times",
+    "pond_search_create", "pond_search_run", "pond_search_trial", "pond_search_destroy",
 )
 KERNEL_NAMES = ("k1_unpack_colfft", "k2_row", "k3_colinv_detect_fold", "fold_reduce", "fold_finalize")
 
@@ -87,6 +88,14 @@ def _load():
     lib.pond_plan_set_timing.restype = i32
     lib.pond_plan_kernel_times.argtypes = [P, ctypes.POINTER(pond_kernel_times)]
     lib.pond_plan_kernel_times.restype = i32
+    lib.pond_search_create.argtypes = [dbl, dbl, ctypes.POINTER(dbl), i32, i32, dbl, i64, i64, i32]
+    lib.pond_search_create.restype = P
+    lib.pond_search_run.argtypes = [P, P, i64, P, P]
+    lib.pond_search_run.restype = i32
+    lib.pond_search_trial.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.pond_search_trial.restype = i32
+    lib.pond_search_destroy.argtypes = [P]
+    lib.pond_search_destroy.restype = None
     lib.pond_strerror.argtypes = [i64]
     lib.pond_strerror.restype = ctypes.c_char_p
     return lib
@@ -176,6 +185,32 @@ def pond_plan_kernel_times(plan):
     if r != POND_OK:
         raise PondError(r, "pond_plan_kernel_times")
     return {KERNEL_NAMES[i]: (t.ms[i], t.launches[i], t.blocks[i]) for i in range(5)}
+
+
+def pond_search_create(f0_mhz, bw_mhz, dms, nbins, period_s, nfft_min=1 << 20, nfft_max=1 << 23,
+                       precision=POND_FP32):
+    arr = (ctypes.c_double * len(dms))(*[float(d) for d in dms])
+    h = _lib.pond_search_create(float(f0_mhz), float(bw_mhz), arr, len(dms), int(nbins), float(period_s),
+                                int(nfft_min), int(nfft_max), int(precision))
+    if not h:
+        raise PondError(POND_EINVAL, "pond_search_create")
+    return h
+
+
+def pond_search_run(search, iq, nsamp, profiles, stream=None):
+    return _lib.pond_search_run(search, _ptr(iq), int(nsamp), _ptr(profiles), _stream(stream))
+
+
+def pond_search_trial(search, t):
+    n, f, h = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    r = _lib.pond_search_trial(search, int(t), ctypes.byref(n), ctypes.byref(f), ctypes.byref(h))
+    if r != POND_OK:
+        raise PondError(r, "pond_search_trial")
+    return n.value, f.value, h.value
+
+
+def pond_search_destroy(search):
+    _lib.pond_search_destroy(search)
 
 
 # ------------------------------------------------------- convenience class

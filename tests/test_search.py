@@ -1,0 +1,84 @@
+"""DM-trial search: grouping rule, oracle behaviour on a dispersed pulse
+(CPU), GPU parity with the oracle per trial, and the S/N-vs-DM peak of the
+batched search on the GPU."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_helpers import BW, F0, dispersed_pulsar_stream, profile_rel_l2
+
+TRIALS_128 = np.arange(128) * 0.5
+
+
+def test_search_groups_of_the_128_trial_workload():
+    """N_t = clamp(2 discard_t, 2^20, 2^23): four length groups, DM 0-8.5,
+    9-17, 17.5-34 and 34.5-63.5, each with hop = N/2."""
+    geo = O.search_geometry(F0, BW, TRIALS_128)
+    by_n = {}
+    for t in geo:
+        by_n.setdefault(t["nfft"], []).append(t["dm"])
+        assert t["hop"] == t["nfft"] // 2
+        g = O.plan_geometry(F0, BW, t["dm"], t["nfft"])
+        assert g["discard"] <= t["hop"] and t["n_front"] == g["n_front"]
+    assert sorted(by_n) == [1 << 20, 1 << 21, 1 << 22, 1 << 23]
+    assert (min(by_n[1 << 20]), max(by_n[1 << 20])) == (0.0, 8.5)
+    assert (min(by_n[1 << 21]), max(by_n[1 << 21])) == (9.0, 17.0)
+    assert (min(by_n[1 << 22]), max(by_n[1 << 22])) == (17.5, 34.0)
+    assert (min(by_n[1 << 23]), max(by_n[1 << 23])) == (34.5, 63.5)
+
+
+def test_oracle_search_snr_peaks_at_true_dm():
+    """A pulse dispersed at DM 2.0 is sharpest when folded at DM 2.0."""
+    iq = dispersed_pulsar_stream(4, 2_000_000, 2.0, period=0.02)
+    dms = np.arange(1.5, 2.51, 0.25)
+    profs, geo = O.search(iq, F0, BW, dms, 256, 0.02, nfft_min=1 << 16, nfft_max=1 << 20,
+                          workers=8)
+    snr = [O.profile_snr(p) for p in profs]
+    assert dms[int(np.argmax(snr))] == 2.0, snr
+
+
+def _gpu_search(iq, dms, nbins, period, nmin, nmax, precision):
+    import torch
+    import paper_1503_01405_amd as P
+    x = torch.from_numpy(iq).to("cuda")
+    prec = {"fp32": P.POND_FP32, "mixed": P.POND_MIXED, "mixed_valu": P.POND_MIXED_VALU}[precision]
+    h = P.pond_search_create(F0, BW, dms, nbins, period, nmin, nmax, prec)
+    try:
+        out = torch.zeros((len(dms), nbins), device="cuda")
+        assert P.pond_search_run(h, x, iq.size // 2, out) == P.POND_OK
+        torch.cuda.synchronize()
+        geo = [P.pond_search_trial(h, t) for t in range(len(dms))]
+        return out.cpu().numpy(), geo
+    finally:
+        P.pond_search_destroy(h)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp32", "mixed", "mixed_valu"])
+def test_gpu_search_parity(precision):
+    dms = [0.0, 0.4, 1.1, 2.5, 3.0, 6.0]
+    nbins, period, nmin, nmax = 128, 3.3e-3, 1 << 14, 1 << 20
+    print(f"case: search parity {precision} dms={dms}", flush=True)
+    iq = synth.white_stream_int8(31, 1_500_001)
+    want, geo = O.search(iq, F0, BW, dms, nbins, period, nfft_min=nmin, nfft_max=nmax, workers=8)
+    got, ggeo = _gpu_search(iq, dms, nbins, period, nmin, nmax, precision)
+    assert [(t["nfft"], t["n_front"], t["hop"]) for t in geo] == ggeo
+    err = profile_rel_l2(got, want)
+    print(f"{precision}: max per-trial profile rel-L2 {err:.3e}")
+    assert err <= (1e-6 if precision == "fp32" else 1e-4)
+
+
+@pytest.mark.gpu
+def test_gpu_search_finds_dm_37_2():
+    """The batched-search workload's structure: a pulse dispersed at DM 37.2,
+    trials every 0.5 with FFT lengths by smear (2^23 here); the S/N peaks at
+    the trial nearest 37.2."""
+    print("case: search S/N peak DM 37.2", flush=True)
+    iq = dispersed_pulsar_stream(9, 32_000_000, 37.2)
+    dms = list(np.arange(35.0, 39.51, 0.5))
+    got, _ = _gpu_search(iq, dms, 512, synth.PERIOD_S, 1 << 20, 1 << 23, "mixed_valu")
+    snr = [O.profile_snr(p) for p in got]
+    print("S/N:", [f"{d}:{s:.1f}" for d, s in zip(dms, snr)])
+    assert dms[int(np.argmax(snr))] in (37.0, 37.5)
+    assert max(snr) > 1.5 * snr[0]
