@@ -56,6 +56,7 @@ typedef struct pond_plan pond_plan;
 #define POND_EINVAL   (-1)  /* bad argument or call sequence; plan state untouched   */
 #define POND_ENOMEM   (-2)  /* device allocation failed; plan state untouched        */
 #define POND_EDEVICE  (-3)  /* HIP runtime error; sticky: only destroy is valid after */
+#define POND_EBUSY    (-4)  /* server: the stream does not fit the budget right now  */
 
 /* Precision forms. */
 #define POND_FP32   0  /* float32 storage and arithmetic                                   */
@@ -229,6 +230,87 @@ int32_t pond_search_trial(const pond_search* s, int32_t t, int64_t* nfft, int64_
 
 /* Destroy a search (NULL-safe); waits for its pending work. */
 void pond_search_destroy(pond_search* s);
+
+/*
+ * Real-time serving of many streams on one device (continuous batching).
+ *
+ * A server admits streams, each a plan of its own with the usual geometry,
+ * against a device-memory budget.  An admitted stream keeps its overlap
+ * tail and fold accumulators on the device between blocks.  Blocks of int8
+ * samples arrive in HOST memory and are submitted as they arrive.  A block
+ * is dispatched at once if its stream has fewer than two blocks on the
+ * device: copy to the device, dedispersion + fold (Sec. 3.7), copy of the
+ * completed profiles back, on the stream's own non-blocking HIP stream.
+ * Otherwise it waits in the stream's queue until poll() finds a slot free.
+ * Blocks of different streams thus overlap on the device, and each stream's
+ * blocks run in order, so its results are those of the same blocks passed
+ * to pond_dedisperse_fold one after another on a plan of its own.
+ *
+ * The server is single-threaded: call it from one host thread.  Host block
+ * memory must stay valid and unmodified until poll() has reported that
+ * block; pinned memory (hipHostMalloc) makes the copy asynchronous,
+ * pageable memory makes the submitting call wait for the copy.
+ */
+typedef struct pond_server pond_server;
+
+typedef struct pond_stream_desc {
+    double  f0_mhz, bw_mhz, dm, period_s;  /* as pond_plan_create                  */
+    int64_t nfft;                          /* as pond_plan_create                  */
+    int64_t subint_nsamp;                  /* S of the stream (0 = one open-ended)  */
+    int64_t max_block_nsamp;               /* largest block the stream will submit */
+    int32_t nbins;
+    int32_t precision;                     /* POND_FP32 / POND_MIXED / POND_MIXED_VALU */
+} pond_stream_desc;
+
+typedef struct pond_completion {
+    int64_t ticket;       /* as returned by pond_server_submit                        */
+    int32_t stream;       /* stream id                                                */
+    int32_t status;       /* POND_OK or the error that ended the stream               */
+    int64_t n_profiles;   /* sub-integrations the block completed                     */
+    double  latency_us;   /* host clock: submission to completion seen by the server  */
+    double  device_us;    /* device time from the block's copy-in to its copy-out     */
+} pond_completion;
+
+/* A server on the current device with a budget in bytes of device memory
+   and a cap on open streams.  NULL on bad arguments. */
+pond_server* pond_server_create(int64_t hbm_budget_bytes, int32_t max_streams);
+
+/* Device bytes a stream with this description holds while open (default
+   blocks per launch), or POND_EINVAL. */
+int64_t pond_server_stream_bytes(const pond_stream_desc* d);
+
+/* Admit a stream: returns its id (>= 0), POND_EBUSY if it does not fit the
+   budget (with fewer blocks per launch tried first) or the stream cap now,
+   POND_EINVAL for an invalid description, POND_ENOMEM / POND_EDEVICE. */
+int32_t pond_server_open(pond_server* s, const pond_stream_desc* d);
+
+/* Submit the stream's next block (host_iq: 2*nsamp int8, 0 < nsamp <=
+   max_block_nsamp).  Returns a ticket (>= 0) or an error. */
+int64_t pond_server_submit(pond_server* s, int32_t stream, const int8_t* host_iq, int64_t nsamp);
+
+/* Report completed blocks (up to max_out, in completion order per stream)
+   and dispatch queued blocks into freed slots.  With wait != 0, waits until
+   at least one block completes or nothing is on the device.  Returns the
+   number of completions written, or POND_EINVAL. */
+int32_t pond_server_poll(pond_server* s, pond_completion* out, int32_t max_out, int32_t wait);
+
+/* Move up to max_profiles of the stream's completed profiles (oldest
+   first, nbins float32 each) to host_out and drop them from the server;
+   valid before and after close.  Returns the number moved. */
+int64_t pond_server_take_profiles(pond_server* s, int32_t stream, float* host_out, int64_t max_profiles);
+
+/* End a stream: run its queued blocks, append the open sub-integration as
+   its last profile, free its device memory and return it to the budget.
+   Completions seen meanwhile are reported by the next poll().  Returns
+   POND_OK or the error that ended the stream. */
+int32_t pond_server_close(pond_server* s, int32_t stream);
+
+/* Budget in use, budget, open streams and blocks queued or on the device. */
+int32_t pond_server_query(const pond_server* s, int64_t* used_bytes, int64_t* budget_bytes,
+                          int32_t* open_streams, int64_t* queued_blocks);
+
+/* Destroy a server (NULL-safe): waits for and frees every open stream. */
+void pond_server_destroy(pond_server* s);
 
 /* Static text for a return code. */
 const char* pond_strerror(int64_t code);

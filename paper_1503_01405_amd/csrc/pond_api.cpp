@@ -154,11 +154,39 @@ hipError_t upload(T** dst, const std::vector<T>& v) {
     return hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
+int default_max_batch(int64_t nfft, int32_t precision, int32_t max_batch) {
+    if (max_batch > 0) return max_batch;
+    const int64_t elem = precision == POND_FP32 ? 8 : 4;
+    const int64_t b = ((int64_t)1 << 29) / (nfft * elem);
+    return (int)(b < 1 ? 1 : (b > 16 ? 16 : b));
+}
+
 int64_t n_blocks_for(int64_t nsamp, int64_t nfft, int64_t hop) {
     return nsamp < nfft ? 0 : (nsamp - nfft) / hop + 1;
 }
 
 }  // namespace
+
+namespace pond {
+
+// Device bytes a plan allocates in pond_plan_create_ex (the accumulator
+// ring counted at its initial 4 sub-integrations; it grows only for calls
+// that span more).
+int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t max_batch) {
+    const int log2n = ilog2(nfft);
+    const int log2n2 = log2n / 2 < kMaxLog2N2 ? log2n / 2 : kMaxLog2N2;
+    const int64_t n1 = (int64_t)1 << (log2n - log2n2), n2 = (int64_t)1 << log2n2;
+    const int64_t elem = precision == POND_FP32 ? 8 : 4;
+    const int64_t mb = default_max_batch(nfft, precision, max_batch);
+    return mb * nfft * elem + 2 * nfft * 2 + (n1 + n2) * 8 + nfft * 16 + 2 * 4 * (int64_t)nbins * 8 +
+           kPartEntries * 12 + 8;
+}
+
+int plan_max_batch(int64_t nfft, int32_t precision, int32_t max_batch) {
+    return default_max_batch(nfft, precision, max_batch);
+}
+
+}  // namespace pond
 
 extern "C" {
 
@@ -170,6 +198,7 @@ const char* pond_strerror(int64_t code) {
         case POND_EINVAL: return "invalid argument or call sequence";
         case POND_ENOMEM: return "device allocation failed";
         case POND_EDEVICE: return "HIP runtime error (plan unusable)";
+        case POND_EBUSY: return "does not fit the device-memory budget now";
         default: return code > 0 ? "ok" : "unknown error";
     }
 }
@@ -239,11 +268,7 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     p->nbins = nbins;
     p->precision = precision;
     p->elem = precision == POND_FP32 ? 8 : 4;
-    if (max_batch <= 0) {
-        int64_t b = ((int64_t)1 << 29) / (nfft * (int64_t)p->elem);
-        max_batch = (int)(b < 1 ? 1 : (b > 16 ? 16 : b));
-    }
-    p->max_batch = max_batch;
+    p->max_batch = max_batch = default_max_batch(nfft, precision, max_batch);
 
     p->hist_cap = hist_capacity(p->log2n2);
 
@@ -269,7 +294,8 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     if (e == hipSuccess) chk(hipMemset(p->acc_sum, 0, (size_t)p->acc_slots * nbins * 8));
     if (e == hipSuccess) chk(hipMemset(p->acc_cnt, 0, (size_t)p->acc_slots * nbins * 8));
     if (e == hipSuccess) chk(hipMemset(p->status, 0, 8));
-    if (e == hipSuccess) chk(hipDeviceSynchronize());
+    // The set-up work ran on the null stream; other streams' work is not waited for.
+    if (e == hipSuccess) chk(hipStreamSynchronize(nullptr));
     if (e != hipSuccess) {
         g_create_status = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? POND_ENOMEM : POND_EDEVICE;
         free_plan_memory(p);
@@ -290,8 +316,9 @@ void pond_plan_destroy(pond_plan* p) {
     if (!p) return;
     {
         DeviceGuard g(p->device);
-        if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
-        (void)hipDeviceSynchronize();
+        // Calls on a plan are ordered on the device, so its last stream
+        // having passed the last call means all of its work is done.
+        (void)hipStreamSynchronize(p->last_stream);
         free_plan_memory(p);
     }
     delete p;

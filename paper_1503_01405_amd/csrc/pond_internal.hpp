@@ -102,6 +102,11 @@ constexpr int64_t kHistCapMax = 8192;      // fold histogram entries held in LDS
 constexpr size_t kLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
 int64_t hist_capacity(int log2n2);
 
+// Device bytes pond_plan_create_ex allocates for these arguments, and the
+// blocks per launch it picks (max_batch <= 0: the default).
+int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t max_batch);
+int plan_max_batch(int64_t nfft, int32_t precision, int32_t max_batch);
+
 // Static LDS bytes of the K3 tile for a column length 2^log2n2.
 size_t k3_static_lds(int log2n2);
 // Threads per workgroup of each kernel.

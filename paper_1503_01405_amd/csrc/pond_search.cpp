@@ -201,7 +201,7 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
     chk(hipMalloc(reinterpret_cast<void**>(&s->part_cnt), (size_t)kPartEntries * 4));
     chk(hipMalloc(reinterpret_cast<void**>(&s->status), 8));
     if (e == hipSuccess) chk(hipMemset(s->status, 0, 8));
-    if (e == hipSuccess) chk(hipDeviceSynchronize());
+    if (e == hipSuccess) chk(hipStreamSynchronize(nullptr));
     if (e != hipSuccess) {
         free_search(s);
         delete s;
@@ -335,8 +335,7 @@ void pond_search_destroy(pond_search* s) {
     int cur = -1;
     (void)hipGetDevice(&cur);
     if (cur != s->device) (void)hipSetDevice(s->device);
-    if (s->last_stream) (void)hipStreamSynchronize(s->last_stream);
-    (void)hipDeviceSynchronize();
+    (void)hipStreamSynchronize(s->last_stream);
     free_search(s);
     if (cur >= 0 && cur != s->device) (void)hipSetDevice(cur);
     delete s;

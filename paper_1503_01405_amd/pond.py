@@ -17,6 +17,7 @@ POND_OK = 0
 POND_EINVAL = -1
 POND_ENOMEM = -2
 POND_EDEVICE = -3
+POND_EBUSY = -4
 
 POND_FP32 = 0
 POND_MIXED = 1
@@ -31,6 +32,9 @@ EXPORTS = (
     "pond_plan_expect", "pond_plan_destroy", "pond_strerror",
     "pond_plan_set_timing", "pond_plan_kernel_times",
     "pond_search_create", "pond_search_run", "pond_search_trial", "pond_search_destroy",
+    "pond_server_create", "pond_server_stream_bytes", "pond_server_open", "pond_server_submit",
+    "pond_server_poll", "pond_server_take_profiles", "pond_server_close", "pond_server_query",
+    "pond_server_destroy",
 )
 KERNEL_NAMES = ("k1_unpack_colfft", "k2_row", "k3_colinv_detect_fold", "fold_reduce", "fold_finalize")
 
@@ -61,9 +65,29 @@ class pond_kernel_times(ctypes.Structure):
                 ("blocks", ctypes.c_int64 * 5)]
 
 
+class pond_stream_desc(ctypes.Structure):
+    _fields_ = [
+        ("f0_mhz", ctypes.c_double), ("bw_mhz", ctypes.c_double), ("dm", ctypes.c_double),
+        ("period_s", ctypes.c_double), ("nfft", ctypes.c_int64), ("subint_nsamp", ctypes.c_int64),
+        ("max_block_nsamp", ctypes.c_int64), ("nbins", ctypes.c_int32), ("precision", ctypes.c_int32),
+    ]
+
+
+class pond_completion(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_int64), ("stream", ctypes.c_int32), ("status", ctypes.c_int32),
+        ("n_profiles", ctypes.c_int64), ("latency_us", ctypes.c_double), ("device_us", ctypes.c_double),
+    ]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python paper_1503_01405_amd/build.py")
+    # torch first: its HIP runtime (soname libamdhip64.so.7) then satisfies
+    # the library's dependency, so device pointers, streams and graphs of
+    # both live in ONE runtime.  Loaded the other way round, the process
+    # would hold two HIP runtimes and torch would find no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
@@ -96,6 +120,25 @@ def _load():
     lib.pond_search_trial.restype = i32
     lib.pond_search_destroy.argtypes = [P]
     lib.pond_search_destroy.restype = None
+    lib.pond_server_create.argtypes = [i64, i32]
+    lib.pond_server_create.restype = P
+    lib.pond_server_stream_bytes.argtypes = [ctypes.POINTER(pond_stream_desc)]
+    lib.pond_server_stream_bytes.restype = i64
+    lib.pond_server_open.argtypes = [P, ctypes.POINTER(pond_stream_desc)]
+    lib.pond_server_open.restype = i32
+    lib.pond_server_submit.argtypes = [P, i32, P, i64]
+    lib.pond_server_submit.restype = i64
+    lib.pond_server_poll.argtypes = [P, ctypes.POINTER(pond_completion), i32, i32]
+    lib.pond_server_poll.restype = i32
+    lib.pond_server_take_profiles.argtypes = [P, i32, P, i64]
+    lib.pond_server_take_profiles.restype = i64
+    lib.pond_server_close.argtypes = [P, i32]
+    lib.pond_server_close.restype = i32
+    lib.pond_server_query.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i64)]
+    lib.pond_server_query.restype = i32
+    lib.pond_server_destroy.argtypes = [P]
+    lib.pond_server_destroy.restype = None
     lib.pond_strerror.argtypes = [i64]
     lib.pond_strerror.restype = ctypes.c_char_p
     return lib
@@ -211,6 +254,73 @@ def pond_search_trial(search, t):
 
 def pond_search_destroy(search):
     _lib.pond_search_destroy(search)
+
+
+def _desc(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, subint_nsamp, max_block_nsamp, precision):
+    prec = {"fp32": POND_FP32, "mixed": POND_MIXED, "mixed_valu": POND_MIXED_VALU}.get(precision, precision)
+    return pond_stream_desc(float(f0_mhz), float(bw_mhz), float(dm), float(period_s), int(nfft),
+                            int(subint_nsamp), int(max_block_nsamp), int(nbins), int(prec))
+
+
+def pond_server_create(hbm_budget_bytes, max_streams=64):
+    h = _lib.pond_server_create(int(hbm_budget_bytes), int(max_streams))
+    if not h:
+        raise PondError(POND_EINVAL, "pond_server_create")
+    return h
+
+
+def pond_server_stream_bytes(desc):
+    return _lib.pond_server_stream_bytes(ctypes.byref(desc))
+
+
+def pond_server_open(server, desc):
+    return _lib.pond_server_open(server, ctypes.byref(desc))
+
+
+def pond_server_submit(server, stream, host_iq, nsamp):
+    """host_iq: a CPU tensor or numpy int8 array (2*nsamp values) that stays
+    alive and unmodified until the block is reported by poll."""
+    ptr = host_iq.data_ptr() if hasattr(host_iq, "data_ptr") else host_iq.ctypes.data
+    return _lib.pond_server_submit(server, int(stream), ptr, int(nsamp))
+
+
+def pond_server_poll(server, max_out=64, wait=False):
+    buf = (pond_completion * max_out)()
+    n = _lib.pond_server_poll(server, buf, int(max_out), 1 if wait else 0)
+    if n < 0:
+        raise PondError(n, "pond_server_poll")
+    return [dict(ticket=c.ticket, stream=c.stream, status=c.status, n_profiles=c.n_profiles,
+                 latency_us=c.latency_us, device_us=c.device_us) for c in buf[:n]]
+
+
+def pond_server_take_profiles(server, stream, nbins, max_profiles=1 << 20):
+    import numpy as np
+    out = np.empty((0, nbins), dtype=np.float32)
+    while True:
+        chunk = np.empty((4096, nbins), dtype=np.float32)
+        n = _lib.pond_server_take_profiles(server, int(stream), chunk.ctypes.data, 4096)
+        if n < 0:
+            raise PondError(n, "pond_server_take_profiles")
+        out = np.concatenate([out, chunk[:n]])
+        if n < 4096 or out.shape[0] >= max_profiles:
+            return out
+
+
+def pond_server_close(server, stream):
+    return _lib.pond_server_close(server, int(stream))
+
+
+def pond_server_query(server):
+    u, b, q = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    o = ctypes.c_int32(0)
+    r = _lib.pond_server_query(server, ctypes.byref(u), ctypes.byref(b), ctypes.byref(o), ctypes.byref(q))
+    if r != POND_OK:
+        raise PondError(r, "pond_server_query")
+    return dict(used_bytes=u.value, budget_bytes=b.value, open_streams=o.value, queued_blocks=q.value)
+
+
+def pond_server_destroy(server):
+    _lib.pond_server_destroy(server)
 
 
 # ------------------------------------------------------- convenience class

@@ -58,3 +58,18 @@ def test_null_plan_calls():
     assert lib.pond_plan_expect(None, 0, 0, None, None) == B.POND_EINVAL
     lib.pond_plan_destroy(None)
     assert lib.pond_strerror(B.POND_EDEVICE)
+
+
+def test_library_shares_torchs_hip_runtime():
+    """The binding loads torch before libpond.so, so the library's HIP
+    runtime dependency resolves to the copy torch already loaded (a second
+    runtime in the process would not see torch's device state)."""
+    import subprocess
+    import sys
+    code = ("import paper_1503_01405_amd, torch, os\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "paths = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})\n"
+            "print(len(paths)); print(paths)\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.splitlines()[0] == "1", out.stdout
