@@ -198,7 +198,7 @@ def search_bytes(geo_groups, nsamp, elem):
 def run_search(precision, x, dms, steps, warmup):
     import torch
     import paper_1503_01405_amd as P
-    prec = {"fp32": P.POND_FP32, "mixed": P.POND_MIXED, "mixed_valu": P.POND_MIXED_VALU}[precision]
+    prec = P.FORMS[precision]
     h = P.pond_search_create(F0, BW, dms, SEARCH_NBINS, PERIOD, 1 << 20, 1 << 23, prec)
     nsamp = x.numel() // 2
     out = torch.empty((len(dms), SEARCH_NBINS), dtype=torch.float32, device=x.device)
@@ -278,6 +278,7 @@ def main_search(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(h["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"mixed": "f16 (matrix-core DFT) / f32 accumulate", "mixed_valu": "f16-storage/f32",
+                  "half": "f16 (packed VALU) / f32 detect+fold",
                   "fp32": "f32"}[head],
         "data": "synthetic",
         "config": {"workload": "10 s 16 Msps int8 I/Q at 326.5 MHz, 128 DM trials 0-63.5 step 0.5, "
@@ -346,7 +347,7 @@ def main_serve(args):
     import synth
 
     form = [f for f in args.forms.split(",") if f and f != "fp32"] or ["fp32"]
-    form = form[0] if "mixed_valu" not in form else "mixed_valu"
+    form = "half" if "half" in form else form[0]
     torch.cuda.init()
     streams = serve_streams()
     pool = []
@@ -424,6 +425,7 @@ def main_serve(args):
         "steps": nblk, "warmup": 0, "ms_per_step": round(wall * 1e3 / nblk, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": {"mixed": "f16 (matrix-core DFT) / f32 accumulate", "mixed_valu": "f16-storage/f32",
+                  "half": "f16 (packed VALU) / f32 detect+fold",
                   "fp32": "f32"}[form],
         "data": "synthetic",
         "config": {"workload": "16 streams, DM log-uniform 0.5-200, P uniform 2 ms-2 s, nfft 2^16-2^24 by smear, "
@@ -447,7 +449,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="fp32,mixed_valu,mixed")
+    ap.add_argument("--forms", default="fp32,mixed_valu,mixed,half")
     ap.add_argument("--cpu-blocks", type=int, default=16)
     ap.add_argument("--graph", action="store_true",
                     help="also time the step captured once into a HIP graph and replayed")
@@ -542,6 +544,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"mixed": "f16 (matrix-core DFT) / f32 accumulate", "mixed_valu": "f16-storage/f32",
+                  "half": "f16 (packed VALU) / f32 detect+fold",
                   "fp32": "f32"}[head],
         "data": "synthetic",
         "config": {"workload": "60 s 16 Msps int8 I/Q at 326.5 MHz, DM 50, nfft 2^23 (2^22 discarded), "

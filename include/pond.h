@@ -66,6 +66,10 @@ typedef struct pond_plan pond_plan;
                           scaling); chirp and fold phases stay float64                      */
 #define POND_MIXED_VALU 2  /* float16 storage between passes, every butterfly in float32
                               vector arithmetic                                            */
+#define POND_HALF   3  /* float16 storage and packed float16 vector arithmetic (two halves per
+                          instruction) for every butterfly, twiddle and the chirp multiply;
+                          forward transforms normalised stage by stage; detection and fold
+                          in float32 from the float16 pair; chirp and fold phases float64  */
 
 /* Status bits reported by pond_plan_query().status (sticky until flush). */
 #define POND_STATUS_NONFINITE  1u  /* a detected power was inf or NaN (fp16 overflow)        */
@@ -86,7 +90,7 @@ typedef struct pond_info {
     double  delta_hi_s;    /* advance of band top relative to f0                   */
     double  inv_pfs;       /* 1 / (period_s * fs_hz)                               */
     int32_t nbins;
-    int32_t precision;     /* POND_FP32, POND_MIXED or POND_MIXED_VALU             */
+    int32_t precision;     /* POND_FP32, POND_MIXED, POND_MIXED_VALU or POND_HALF  */
     uint32_t status;       /* POND_STATUS_* bits (read synchronously)              */
     int32_t reserved;
 } pond_info;
@@ -110,8 +114,8 @@ pond_plan* pond_plan_create(double f0_mhz, double bw_mhz, double dm,
                             int64_t nfft, int32_t nbins, double period_s);
 
 /*
- * As pond_plan_create with a precision form (POND_FP32, POND_MIXED or
- * POND_MIXED_VALU) and a cap on overlap-save blocks per launch (max_batch
+ * As pond_plan_create with a precision form (POND_FP32, POND_MIXED,
+ * POND_MIXED_VALU or POND_HALF) and a cap on overlap-save blocks per launch (max_batch
  * <= 0 picks a default).
  */
 pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm,
@@ -259,7 +263,7 @@ typedef struct pond_stream_desc {
     int64_t subint_nsamp;                  /* S of the stream (0 = one open-ended)  */
     int64_t max_block_nsamp;               /* largest block the stream will submit */
     int32_t nbins;
-    int32_t precision;                     /* POND_FP32 / POND_MIXED / POND_MIXED_VALU */
+    int32_t precision;                     /* POND_FP32 / POND_MIXED / POND_MIXED_VALU / POND_HALF */
 } pond_stream_desc;
 
 typedef struct pond_completion {

@@ -4,7 +4,7 @@ baseband voltages (the pulsar mode of PONDER, arXiv:1503.01405).
 The compute path lives in libpond.so (HIP kernels for gfx950 behind the C
 ABI of include/pond.h); this package is its ctypes binding.
 """
-from .pond import (POND_EBUSY, POND_EDEVICE, POND_EINVAL, POND_ENOMEM, POND_FP32, POND_MIXED, POND_MIXED_VALU,  # noqa: F401
+from .pond import (POND_EBUSY, POND_EDEVICE, POND_EINVAL, POND_ENOMEM, FORMS, POND_FP32, POND_HALF, POND_MIXED, POND_MIXED_VALU,  # noqa: F401
                    POND_OK, POND_STATUS_NONFINITE, POND_STATUS_RANGE, Plan, PondError,
                    pond_dedisperse_fold, pond_dedisperse_series, pond_plan_create,
                    pond_plan_destroy, pond_plan_expect, pond_plan_kernel_times,

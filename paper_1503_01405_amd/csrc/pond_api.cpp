@@ -47,7 +47,9 @@ struct pond_plan {
     int64_t tail_start = 0;
     float2* tw1 = nullptr;
     float2* tw2 = nullptr;
-    float4* table = nullptr;
+    float4* table = nullptr;    // float32 forms
+    void* htable = nullptr;     // packed float16 form (8 bytes per entry)
+    float pscale = 1.0f;        // detected-power scale applied in K3
     uint64_t* acc_sum = nullptr;
     uint64_t* acc_cnt = nullptr;
     int64_t acc_slots = 0;
@@ -130,7 +132,7 @@ void free_plan_memory(pond_plan* p) {
     p->marks.clear();
     for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     p->event_pool.clear();
-    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->table,
+    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->table, p->htable,
                     p->acc_sum, p->acc_cnt, p->part_sum, p->part_cnt, p->status};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -169,6 +171,93 @@ int64_t n_blocks_for(int64_t nsamp, int64_t nfft, int64_t hop) {
 
 namespace pond {
 
+namespace {
+float2 h_cmul(float2 a, float2 b) {
+    return make_float2(std::fma(a.x, b.x, -(a.y * b.y)), std::fma(a.x, b.y, a.y * b.x));
+}
+// The device's float32 power tree (powers<R>) and W16 products (mul_w16,
+// forward direction), replicated in the same float32 operations.
+void h_powers(float2 w, int R, float2* p) {
+    p[0] = make_float2(1.f, 0.f);
+    if (R > 1) p[1] = w;
+    if (R > 2) p[2] = h_cmul(w, w);
+    if (R > 3) p[3] = h_cmul(p[2], w);
+    if (R > 4) {
+        p[4] = h_cmul(p[2], p[2]);
+        p[5] = h_cmul(p[4], w);
+        p[6] = h_cmul(p[4], p[2]);
+        p[7] = h_cmul(p[4], p[3]);
+    }
+    if (R > 8) {
+        p[8] = h_cmul(p[4], p[4]);
+        for (int q = 9; q < 16; ++q) p[q] = h_cmul(p[8], p[q - 8]);
+    }
+}
+float2 h_mul_w16(int u, float2 a) {
+    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+    auto cs = [&](float c, float s) { return make_float2(std::fma(a.x, c, a.y * s), std::fma(a.y, c, -(a.x * s))); };
+    switch (u & 15) {
+        case 0: return a;
+        case 4: return make_float2(a.y, -a.x);
+        case 8: return make_float2(-a.x, -a.y);
+        case 12: return make_float2(-a.y, a.x);
+        case 2: return make_float2((a.x + a.y) * h, (a.y - a.x) * h);
+        case 6: return make_float2((a.y - a.x) * h, -(a.x + a.y) * h);
+        case 10: return make_float2(-(a.x + a.y) * h, (a.x - a.y) * h);
+        case 14: return make_float2((a.x - a.y) * h, (a.x + a.y) * h);
+        case 1: return cs(c1, s1);
+        case 3: return cs(s1, c1);
+        case 5: return cs(-s1, c1);
+        case 7: return cs(-c1, s1);
+        case 9: return cs(-c1, -s1);
+        case 11: return cs(-s1, -c1);
+        case 13: return cs(s1, -c1);
+        default: return cs(c1, -s1);
+    }
+}
+double h_f16sq(float2 v) {
+    const double x = (double)(_Float16)v.x, y = (double)(_Float16)v.y;
+    return x * x + y * y;
+}
+}  // namespace
+
+// Mean power gain of the float16 stage twiddles of a length-2^log2l
+// transform in the packed-float16 form: each stage multiplies its inputs by
+// float16 roundings of exact powers, and the mean of |w|^2 over a stage's
+// fixed set of twiddles is not exactly 1 (a few 1e-5); for white input a
+// stage scales the mean power by that mean.  Summed over the stages.
+double half_twiddle_gain(int log2l) {
+    const int64_t L = (int64_t)1 << log2l;
+    const std::vector<float2> tw = twiddles(L, L, 1);
+    const int full = log2l / 4, rem = 1 << (log2l % 4);
+    const int nst = full + (rem > 1 ? 1 : 0);
+    double total = 0;
+    int64_t ns = 1;
+    for (int st = 0; st < nst; ++st) {
+        const int R = st < full ? 16 : rem;
+        if (ns > 1) {
+            double acc = 0;
+            int64_t cnt = 0;
+            float2 p[16];
+            if (R == 16) {
+                for (int64_t k = 0; k < ns; ++k) {
+                    h_powers(tw[(size_t)(k * (L / (16 * ns)))], 16, p);
+                    for (int q = 0; q < 16; ++q, ++cnt) acc += h_f16sq(p[q]);
+                }
+            } else {
+                for (int64_t j = 0; j < L / 16; ++j)
+                    for (int u = 0; u < 16 / R; ++u) {
+                        h_powers(h_mul_w16(u, tw[(size_t)j]), R, p);
+                        for (int q = 0; q < R; ++q, ++cnt) acc += h_f16sq(p[q]);
+                    }
+            }
+            total += acc / (double)cnt - 1.0;
+        }
+        ns *= R;
+    }
+    return total;
+}
+
 // Device bytes a plan allocates in pond_plan_create_ex (the accumulator
 // ring counted at its initial 4 sub-integrations; it grows only for calls
 // that span more).
@@ -178,7 +267,8 @@ int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t m
     const int64_t n1 = (int64_t)1 << (log2n - log2n2), n2 = (int64_t)1 << log2n2;
     const int64_t elem = precision == POND_FP32 ? 8 : 4;
     const int64_t mb = default_max_batch(nfft, precision, max_batch);
-    return mb * nfft * elem + 2 * nfft * 2 + (n1 + n2) * 8 + nfft * 16 + 2 * 4 * (int64_t)nbins * 8 +
+    const int64_t table = precision == POND_HALF ? 8 : 16;
+    return mb * nfft * elem + 2 * nfft * 2 + (n1 + n2) * 8 + nfft * table + 2 * 4 * (int64_t)nbins * 8 +
            kPartEntries * 12 + 8;
 }
 
@@ -213,7 +303,8 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     const int log2n = ilog2(nfft);
     if (log2n < kMinLog2N || log2n > kMaxLog2N) return nullptr;
     if (nbins < 1 || nbins > 65536) return nullptr;
-    if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU) return nullptr;
+    if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU && precision != POND_HALF)
+        return nullptr;
     const double fs = bw_mhz * 1e6;
     if (!(period_s > 0) || !(period_s * fs >= 1.0)) return nullptr;
 
@@ -271,6 +362,11 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     p->max_batch = max_batch = default_max_batch(nfft, precision, max_batch);
 
     p->hist_cap = hist_capacity(p->log2n2);
+    // Packed float16: the middle pass leaves 1/16 of the value (its twiddle
+    // table carries the first stage's 1/16), so power x 256, divided by the
+    // gain of the float16 stage twiddles of the four transforms.
+    if (precision == POND_HALF)
+        p->pscale = (float)(256.0 / (1.0 + 2.0 * half_twiddle_gain(p->log2n2) + 2.0 * half_twiddle_gain(p->log2n1)));
 
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) {
@@ -282,9 +378,15 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     const int64_t n1 = (int64_t)1 << p->log2n1, n2 = (int64_t)1 << p->log2n2;
     if (e == hipSuccess) chk(upload(&p->tw1, twiddles(n1, n1, 1)));
     if (e == hipSuccess) chk(upload(&p->tw2, twiddles(n2, n2, 1)));
-    chk(hipMalloc(reinterpret_cast<void**>(&p->table), (size_t)nfft * sizeof(float4)));
-    if (e == hipSuccess)
-        chk(launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, nullptr));
+    if (precision == POND_HALF) {
+        chk(hipMalloc(&p->htable, (size_t)nfft * 8));
+        if (e == hipSuccess)
+            chk(launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, nullptr));
+    } else {
+        chk(hipMalloc(reinterpret_cast<void**>(&p->table), (size_t)nfft * sizeof(float4)));
+        if (e == hipSuccess)
+            chk(launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, nullptr));
+    }
     p->acc_slots = 4;
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_sum), (size_t)p->acc_slots * nbins * 8));
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_cnt), (size_t)p->acc_slots * nbins * 8));
@@ -560,6 +662,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a2.log2n2 = n2log;
         a2.tw1 = p->tw1;
         a2.table = p->table;
+        a2.htable = p->htable;
         a2.scale = k2_scale;
         e = timed(1, nb, [&] { return launch_k2(p->precision, kRowFull, p->log2n1, a2, stream); });
         if (e != hipSuccess) return fail(e);
@@ -573,6 +676,9 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a3.block0 = b;
         a3.tw2 = p->tw2;
         a3.scale = k3_scale;
+        // The packed-float16 middle pass leaves 1/16 of the value (its
+        // twiddle table carries the first stage's 1/16): power x 256.
+        a3.pscale = p->pscale;
         a3.series = want_series ? series : nullptr;
         a3.series_base = m_before / decim;
         a3.decim = decim;

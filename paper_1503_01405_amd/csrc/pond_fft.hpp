@@ -14,11 +14,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 namespace pond {
 
 // ---------------------------------------------------------------- complex
+// Two value types carry a complex number: float2 (float32 arithmetic) and
+// h2, a pair of float16 that the packed instructions (v_pk_add_f16,
+// v_pk_mul_f16, v_pk_fma_f16) process in one operation -- swaps and sign
+// changes of halves fold into their op_sel / neg modifiers.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
@@ -30,25 +37,94 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
     return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
+
+__device__ __forceinline__ h2 cadd(h2 a, h2 b) { return a + b; }
+__device__ __forceinline__ h2 csub(h2 a, h2 b) { return a - b; }
+__device__ __forceinline__ h2 cscale(h2 a, _Float16 s) { return a * s; }
+__device__ __forceinline__ h2 cmul(h2 a, h2 b) {
+    const h2 m = {-b.y, b.y};
+    return __builtin_elementwise_fma(a.yx, m, a * b.xx);
+}
+__device__ __forceinline__ h2 cmulc(h2 a, h2 b) {
+    const h2 m = {b.y, -b.y};
+    return __builtin_elementwise_fma(a.yx, m, a * b.xx);
+}
+
+__device__ __forceinline__ float2 cneg(float2 a) { return make_float2(-a.x, -a.y); }
+__device__ __forceinline__ h2 cneg(h2 a) { return -a; }
+
+__device__ __forceinline__ h2 to_h2(float2 a) {
+    const h2 r = {(_Float16)a.x, (_Float16)a.y};
+    return r;
+}
+__device__ __forceinline__ float2 to_f2(h2 a) { return make_float2((float)a.x, (float)a.y); }
+
+template <class V>
+__device__ __forceinline__ V cone();
+template <>
+__device__ __forceinline__ float2 cone<float2>() { return make_float2(1.f, 0.f); }
+template <>
+__device__ __forceinline__ h2 cone<h2>() {
+    const h2 r = {(_Float16)1.f, (_Float16)0.f};
+    return r;
+}
+
+// Constants of the in-register DFTs.  cos(pi/8), sin(pi/8) and 1/sqrt(2)
+// in float32; for float16 the cos/sin pair is chosen among neighbouring
+// float16 values so that c^2 + s^2 = 1 + 4e-6 (the nearest values would
+// lose 1.8e-4 of power per use), and products by 1/sqrt(2) are formed in
+// float32 and rounded once (the nearest float16 constant would lose 2.1e-4
+// of power per use).  Folded profiles are means of power, so such a fixed
+// gain would not average out.
+constexpr float kC8 = 0.92387953251128675613f, kS8 = 0.38268343236508977173f;
+constexpr float kRs2 = 0.70710678118654752440f;
+constexpr float kC8h = 0.923828125f, kS8h = 0.3828125f;  // float16-exact
+
 // a * exp(DIR * i pi / 2): DIR = -1 multiplies by -i, DIR = +1 by +i
 template <int DIR>
 __device__ __forceinline__ float2 mul_i(float2 a) {
     if constexpr (DIR < 0) return make_float2(a.y, -a.x);
     else return make_float2(-a.y, a.x);
 }
+template <int DIR>
+__device__ __forceinline__ h2 mul_i(h2 a) {
+    if constexpr (DIR < 0) {
+        const h2 r = {a.y, -a.x};
+        return r;
+    } else {
+        const h2 r = {-a.y, a.x};
+        return r;
+    }
+}
 // a * exp(DIR * i pi / 4)
 template <int DIR>
 __device__ __forceinline__ float2 mul_w8(float2 a) {
-    constexpr float h = 0.70710678118654752440f;
+    constexpr float h = kRs2;
     if constexpr (DIR < 0) return make_float2((a.x + a.y) * h, (a.y - a.x) * h);
     else return make_float2((a.x - a.y) * h, (a.x + a.y) * h);
+}
+// t * c for a float32 constant c, each half rounded once from the float32
+// product (v_fma_mix*_f16): 1/sqrt(2) itself is not a float16 value.
+__device__ __forceinline__ h2 scale_f32(h2 t, float c) {
+    const h2 r = {(_Float16)fmaf((float)t.x, c, 0.0f), (_Float16)fmaf((float)t.y, c, 0.0f)};
+    return r;
+}
+template <int DIR>
+__device__ __forceinline__ h2 mul_w8(h2 a) {
+    const h2 t = a + mul_i<DIR>(a);  // DIR < 0: (x + y, y - x); DIR > 0: (x - y, x + y)
+    return scale_f32(t, kRs2);
 }
 // a * exp(DIR * 3 i pi / 4)
 template <int DIR>
 __device__ __forceinline__ float2 mul_w8_3(float2 a) {
-    constexpr float h = 0.70710678118654752440f;
+    constexpr float h = kRs2;
     if constexpr (DIR < 0) return make_float2((a.y - a.x) * h, -(a.x + a.y) * h);
     else return make_float2(-(a.x + a.y) * h, (a.x - a.y) * h);
+}
+template <int DIR>
+__device__ __forceinline__ h2 mul_w8_3(h2 a) {
+    const h2 t = a + mul_i<-DIR>(a);  // DIR < 0: (x - y, x + y); DIR > 0: (x + y, y - x)
+    return scale_f32(t, -kRs2);
 }
 // a * (c + DIR*i*s) for a constant point on the unit circle
 template <int DIR>
@@ -56,53 +132,69 @@ __device__ __forceinline__ float2 mul_cs(float2 a, float c, float s) {
     if constexpr (DIR < 0) return make_float2(fmaf(a.x, c, a.y * s), fmaf(a.y, c, -(a.x * s)));
     else return make_float2(fmaf(a.x, c, -(a.y * s)), fmaf(a.y, c, a.x * s));
 }
+template <int DIR>
+__device__ __forceinline__ h2 mul_cs(h2 a, float c, float s) {
+    const _Float16 ch = (_Float16)c, sh = (_Float16)s;
+    const h2 m = DIR < 0 ? h2{sh, -sh} : h2{-sh, sh};
+    return __builtin_elementwise_fma(a.yx, m, a * ch);
+}
+template <class V>
+struct DftConst;
+template <>
+struct DftConst<float2> {
+    static constexpr float c8 = kC8, s8 = kS8;
+};
+template <>
+struct DftConst<h2> {
+    static constexpr float c8 = kC8h, s8 = kS8h;
+};
 
 // --------------------------------------------------------- small DFTs
 // In-place DFT of R values, natural order in and out:
 //   V[s] = sum_q v[q] exp(DIR * 2 pi i q s / R)   (DIR = -1 forward)
-template <int DIR>
-__device__ __forceinline__ void dft2(float2& a, float2& b) {
-    float2 t = a;
+template <int DIR, class V>
+__device__ __forceinline__ void dft2(V& a, V& b) {
+    V t = a;
     a = cadd(t, b);
     b = csub(t, b);
 }
 
-template <int DIR>
-__device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
-    float2 a0 = cadd(v0, v2), a1 = csub(v0, v2);
-    float2 a2 = cadd(v1, v3), a3 = mul_i<DIR>(csub(v1, v3));
+template <int DIR, class V>
+__device__ __forceinline__ void dft4(V& v0, V& v1, V& v2, V& v3) {
+    V a0 = cadd(v0, v2), a1 = csub(v0, v2);
+    V a2 = cadd(v1, v3), a3 = mul_i<DIR>(csub(v1, v3));
     v0 = cadd(a0, a2);
     v2 = csub(a0, a2);
     v1 = cadd(a1, a3);
     v3 = csub(a1, a3);
 }
 
-template <int R, int DIR>
+template <int R, int DIR, class V>
 struct Dft;
 
-template <int DIR>
-struct Dft<2, DIR> {
-    __device__ __forceinline__ static void run(float2* v) { dft2<DIR>(v[0], v[1]); }
+template <int DIR, class V>
+struct Dft<2, DIR, V> {
+    __device__ __forceinline__ static void run(V* v) { dft2<DIR>(v[0], v[1]); }
 };
 
-template <int DIR>
-struct Dft<4, DIR> {
-    __device__ __forceinline__ static void run(float2* v) { dft4<DIR>(v[0], v[1], v[2], v[3]); }
+template <int DIR, class V>
+struct Dft<4, DIR, V> {
+    __device__ __forceinline__ static void run(V* v) { dft4<DIR>(v[0], v[1], v[2], v[3]); }
 };
 
 // 8 = 2 x 4: two 4-point DFTs on the even/odd subsequences, twiddle, 2-point.
-template <int DIR>
-struct Dft<8, DIR> {
-    __device__ __forceinline__ static void run(float2* v) {
+template <int DIR, class V>
+struct Dft<8, DIR, V> {
+    __device__ __forceinline__ static void run(V* v) {
         dft4<DIR>(v[0], v[2], v[4], v[6]);
         dft4<DIR>(v[1], v[3], v[5], v[7]);
         v[3] = mul_w8<DIR>(v[3]);
         v[5] = mul_i<DIR>(v[5]);
         v[7] = mul_w8_3<DIR>(v[7]);
-        float2 o[8];
+        V o[8];
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) {
-            float2 a = v[2 * sb], b = v[2 * sb + 1];
+            V a = v[2 * sb], b = v[2 * sb + 1];
             o[sb] = cadd(a, b);
             o[sb + 4] = csub(a, b);
         }
@@ -112,11 +204,11 @@ struct Dft<8, DIR> {
 };
 
 // 16 = 4 x 4: q = qa + 4 qb, s = sb + 4 sa.
-template <int DIR>
-struct Dft<16, DIR> {
-    __device__ __forceinline__ static void run(float2* v) {
-        constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
-        constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
+template <int DIR, class V>
+struct Dft<16, DIR, V> {
+    __device__ __forceinline__ static void run(V* v) {
+        constexpr float c1 = DftConst<V>::c8;  // cos(pi/8)
+        constexpr float s1 = DftConst<V>::s8;  // sin(pi/8)
 #pragma unroll
         for (int qa = 0; qa < 4; ++qa) dft4<DIR>(v[qa], v[qa + 4], v[qa + 8], v[qa + 12]);
         // twiddle T[qa][sb] (stored at v[qa + 4 sb]) by W16^(qa sb)
@@ -129,10 +221,10 @@ struct Dft<16, DIR> {
         v[3 + 4 * 1] = mul_cs<DIR>(v[3 + 4 * 1], s1, c1);   // W^3
         v[3 + 4 * 2] = mul_w8_3<DIR>(v[3 + 4 * 2]);         // W^6
         v[3 + 4 * 3] = mul_cs<DIR>(v[3 + 4 * 3], -c1, -s1); // W^9
-        float2 o[16];
+        V o[16];
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) {
-            float2 a0 = v[0 + 4 * sb], a1 = v[1 + 4 * sb], a2 = v[2 + 4 * sb], a3 = v[3 + 4 * sb];
+            V a0 = v[0 + 4 * sb], a1 = v[1 + 4 * sb], a2 = v[2 + 4 * sb], a3 = v[3 + 4 * sb];
             dft4<DIR>(a0, a1, a2, a3);
             o[sb + 0] = a0;
             o[sb + 4] = a1;
@@ -153,6 +245,12 @@ struct Sched {
     static constexpr int kStages = kFull + (kRem > 1 ? 1 : 0);
     static constexpr int radix(int s) { return s < kFull ? 16 : kRem; }
     static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * radix(s - 1); }
+    // float16 forward transforms scale the input of every even stage by
+    // 1/16 (stage 0 by the caller), so that no value exceeds 16x the input
+    // bound between scalings; the rest of the 1/L normalisation is left
+    // to the caller: 2^-kHalfRem.
+    static constexpr int kHalfScaled = 4 * ((kStages + 1) / 2);
+    static constexpr int kHalfRem = LOG2L - kHalfScaled;
 };
 
 template <int N, class F, int... I>
@@ -165,21 +263,34 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // ------------------------------------------------------------ twiddles
-// exp(-2 pi i u / 16) for a compile-time u.
-template <int U>
-__device__ __forceinline__ float2 w16() {
-    constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
-    constexpr float h = 0.70710678118654752440f;
-    constexpr float cs[16][2] = {{1.f, 0.f},  {c1, -s1},  {h, -h},   {s1, -c1},  {0.f, -1.f}, {-s1, -c1},
-                                 {-h, -h},    {-c1, -s1}, {-1.f, 0.f}, {-c1, s1}, {-h, h},     {-s1, c1},
-                                 {0.f, 1.f},  {s1, c1},   {h, h},    {c1, s1}};
-    return make_float2(cs[U & 15][0], cs[U & 15][1]);
+// a * exp(-2 pi i u / 16) for a compile-time u (DIR-independent: the
+// twiddle bases are always the forward ones).
+template <int U, class V>
+__device__ __forceinline__ V mul_w16(V a) {
+    constexpr int u = U & 15;
+    constexpr float c1 = DftConst<V>::c8, s1 = DftConst<V>::s8;
+    if constexpr (u == 0) return a;
+    else if constexpr (u == 4) return mul_i<-1>(a);
+    else if constexpr (u == 8) return cneg(a);
+    else if constexpr (u == 12) return mul_i<+1>(a);
+    else if constexpr (u == 2) return mul_w8<-1>(a);
+    else if constexpr (u == 6) return mul_w8_3<-1>(a);
+    else if constexpr (u == 10) return mul_w8_3<+1>(a);
+    else if constexpr (u == 14) return mul_w8<+1>(a);
+    else if constexpr (u == 1) return mul_cs<-1>(a, c1, s1);
+    else if constexpr (u == 3) return mul_cs<-1>(a, s1, c1);
+    else if constexpr (u == 5) return mul_cs<-1>(a, -s1, c1);
+    else if constexpr (u == 7) return mul_cs<-1>(a, -c1, s1);
+    else if constexpr (u == 9) return mul_cs<-1>(a, -c1, -s1);
+    else if constexpr (u == 11) return mul_cs<-1>(a, -s1, -c1);
+    else if constexpr (u == 13) return mul_cs<-1>(a, s1, -c1);
+    else return mul_cs<-1>(a, c1, -s1);
 }
 
 // p[q] = w^q for q = 1..R-1 (p[0] unused), products at most four deep.
-template <int R>
-__device__ __forceinline__ void powers(float2 w, float2 (&p)[R]) {
-    p[0] = make_float2(1.f, 0.f);
+template <int R, class V>
+__device__ __forceinline__ void powers(V w, V (&p)[R]) {
+    p[0] = cone<V>();
     if constexpr (R > 1) p[1] = w;
     if constexpr (R > 2) p[2] = cmul(w, w);
     if constexpr (R > 3) p[3] = cmul(p[2], w);
@@ -202,9 +313,9 @@ __device__ __forceinline__ void powers(float2 w, float2 (&p)[R]) {
 //     (one butterfly per thread; its twiddles are the powers of the base);
 //   final stage of radix R < 16 (NS = L / R): exp(-2 pi i j / L); butterfly
 //     u of the thread has base exp(-2 pi i (j + u L/16) / L) = base * W16^u.
-template <int LOG2L>
+template <int LOG2L, class V = float2>
 struct StageBases {
-    float2 b[Sched<LOG2L>::kStages];
+    V b[Sched<LOG2L>::kStages];
     __device__ __forceinline__ void load(int j, const float2* __restrict__ tw) {
         using S = Sched<LOG2L>;
         constexpr int L = 1 << LOG2L;
@@ -212,81 +323,198 @@ struct StageBases {
             constexpr int s = decltype(si)::value;
             constexpr int NS = S::ns(s);
             constexpr int R = S::radix(s);
+            float2 x = make_float2(1.f, 0.f);
             if constexpr (NS > 1) {
-                if constexpr (R == 16) b[s] = tw[(j & (NS - 1)) * (L / (16 * NS))];
-                else b[s] = tw[j];
-            } else {
-                b[s] = make_float2(1.f, 0.f);
+                if constexpr (R == 16) x = tw[(j & (NS - 1)) * (L / (16 * NS))];
+                else x = tw[j];
             }
+            b[s] = x;
         });
     }
 };
 
+// The packed-float16 transforms use the float32 stage bases.
+template <int LOG2L>
+struct StageBases<LOG2L, h2> : StageBases<LOG2L, float2> {};
+
+// LDS layouts of a transform's vector (the position of an element is its
+// index in the vector).  put<D>(p0, x) / get<D>(p0) access position p0 + D
+// for a compile-time D, so that D's part of the address is an immediate.
+// Columns interleaved by 16 (K1/K3 tiles): index = pos * 16 (from the
+// column's base).
+template <class V>
+struct ColLds {
+    V* base;
+    template <int D, bool AL = false>
+    __device__ __forceinline__ void put(int p0, V x) const { base[(p0 + D) * 16] = x; }
+    template <int D>
+    __device__ __forceinline__ V get(int p0) const { return base[(p0 + D) * 16]; }
+};
+// One row with a pad slot per 16 values (K2): index = pos + pos / 16.  The
+// split p0 + D -> (p0 + p0/16) + (D + D/16) holds when D is a multiple of 16,
+// or when p0 is (AL) and D < 16.
+template <class V>
+struct PadLds {
+    V* base;
+    template <int D, bool AL = false>
+    __device__ __forceinline__ V* addr(int p0) const {
+        if constexpr (D % 16 == 0 || AL) {
+            const uint32_t u = (uint32_t)p0;
+            return base + (u + (u >> 4)) + (D + D / 16);
+        } else {
+            const uint32_t u = (uint32_t)(p0 + D);
+            return base + (u + (u >> 4));
+        }
+    }
+    template <int D, bool AL = false>
+    __device__ __forceinline__ void put(int p0, V x) const { *addr<D, AL>(p0) = x; }
+    template <int D>
+    __device__ __forceinline__ V get(int p0) const { return *addr<D>(p0); }
+};
+// For a last stage, whose outputs stay in registers.
+template <class V>
+struct NoLds {
+    template <int D, bool AL = false>
+    __device__ __forceinline__ void put(int, V) const {}
+    template <int D>
+    __device__ __forceinline__ V get(int) const { return V{}; }
+};
+
+// All float16 twiddles thread j needs for stage s of a length-2^LOG2L
+// transform: 16 values (R = 16: its one butterfly; R < 16: R per butterfly
+// u at u*R).  The powers of the stage's float32 base are formed in float32
+// and each rounded once to float16 (raising a rounded float16 base to
+// powers up to 15 would multiply its magnitude error, and the few distinct
+// bases of a stage would leave that error as a gain bias).
+template <int LOG2L, int s>
+__device__ __forceinline__ void stage_tw_h(float2 base, h2 (&t)[16]) {
+    using S = Sched<LOG2L>;
+    constexpr int R = S::radix(s);
+    if constexpr (R == 16) {
+        float2 p[16];
+        powers<16>(base, p);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t[q] = to_h2(p[q]);
+    } else {
+        static_for<16 / R>([&](auto ui) {
+            constexpr int u = decltype(ui)::value;
+            float2 p[R];
+            powers<R>(mul_w16<u>(base), p);
+#pragma unroll
+            for (int q = 0; q < R; ++q) t[u * R + q] = to_h2(p[q]);
+        });
+    }
+}
+
 // One Stockham stage of radix R on the 16 values of thread j.  Butterfly u
 // (index jp = j + TPV u, k = jp mod NS) reads positions jp + q L/R, which
 // are registers u + q BF, twiddles input q by W_{NS R}^(q k), and writes
-// output q to position (jp - k) R + k + q NS.
-template <int L, int R, int NS, int DIR, bool LAST, class Store>
-__device__ __forceinline__ void stockham_stage(float2 (&v)[16], int j, float2 base, Store&& st) {
+// output q to position (jp - k) R + k + q NS.  With SCALE_IN the inputs
+// are first multiplied by 1/16 (float16 forward transforms).
+template <int L, int R, int NS, int DIR, bool LAST, bool SCALE_IN = false, class V, class Lds>
+__device__ __forceinline__ void stockham_stage(V (&v)[16], int j, V base, const Lds& st,
+                                               const h2* htw = nullptr) {
+    // htw (float16 only): the stage's 16 twiddles of this thread (stage_tw_h).
+    constexpr bool HALF = std::is_same<V, h2>::value;
     // Opaque to the optimiser: the twiddle powers and LDS addresses of a
     // stage are recomputed at each use instead of being shared between the
     // forward and inverse transforms (or hoisted out of loops) and held in
     // registers, which costs occupancy.
-    asm volatile("" : "+v"(base.x), "+v"(base.y), "+v"(j));
+    if constexpr (std::is_same<V, h2>::value) {
+        asm volatile("" : "+v"(base), "+v"(j));
+    } else {
+        asm volatile("" : "+v"(base.x), "+v"(base.y), "+v"(j));
+    }
     constexpr int BF = 16 / R;
     constexpr int TPV = L / 16;
-    float2 pw[R];
-    if constexpr (NS > 1 && R == 16) powers<R>(base, pw);
+    V pw[R];
+    if constexpr (NS > 1 && R == 16) {
+        if constexpr (HALF) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) pw[q] = htw[q];
+        } else {
+            powers<R>(base, pw);
+        }
+    }
     static_for<BF>([&](auto ui) {
         constexpr int u = decltype(ui)::value;
         const int jp = j + TPV * u;
         const int k = jp & (NS - 1);
-        float2 w[R];
+        V w[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) w[q] = v[u + q * BF];
+        if constexpr (SCALE_IN) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) w[q] = cscale(w[q], (_Float16)0.0625f);
+        }
         if constexpr (NS > 1) {
             if constexpr (R < 16) {
-                const float2 bu = u == 0 ? base : cmul(base, w16<u>());
-                powers<R>(bu, pw);
+                if constexpr (HALF) {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) pw[q] = htw[u * R + q];
+                } else {
+                    const V bu = mul_w16<u>(base);
+                    powers<R>(bu, pw);
+                }
             }
 #pragma unroll
             for (int q = 1; q < R; ++q) w[q] = DIR < 0 ? cmul(w[q], pw[q]) : cmulc(w[q], pw[q]);
         }
-        Dft<R, DIR>::run(w);
+        Dft<R, DIR, V>::run(w);
         if constexpr (LAST) {
 #pragma unroll
             for (int q = 0; q < R; ++q) v[u + q * BF] = w[q];
         } else {
+            // basep is a multiple of 16 when NS = 1 (R = 16).
             const int basep = (jp - k) * R + k;
-#pragma unroll
-            for (int q = 0; q < R; ++q) st(basep + q * NS, w[q]);
+            static_for<R>([&](auto qi) {
+                constexpr int q = decltype(qi)::value;
+                st.template put<q * NS, NS == 1 && R == 16>(basep, w[q]);
+            });
         }
     });
 }
 
 // Full length-L transform (DIR = -1 forward, +1 inverse, unnormalised) of
-// the vector held by thread j.  ld(pos) / st(pos, val) access this
-// vector's LDS slot; every thread of the workgroup must call this together
-// (it contains barriers).
-template <int LOG2L, int DIR, class Load, class Store>
-__device__ __forceinline__ void fft_wg(float2 (&v)[16], int j, const StageBases<LOG2L>& tb, Load&& ld,
-                                       Store&& st) {
+// the vector held by thread j.  lds is the vector's LDS layout (ColLds or
+// PadLds); every thread of the workgroup must call this together
+// (it contains barriers).  With HALF_NORM (float16 forward transforms)
+// every even stage but the first scales its input by 1/16 (the caller
+// scales the first stage's input and applies the remaining 2^-kHalfRem).
+template <int LOG2L, int DIR, bool HALF_NORM = false, class V, class Lds>
+__device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L, V>& tb, const Lds& lds) {
     using S = Sched<LOG2L>;
     constexpr int L = 1 << LOG2L;
     constexpr int TPV = L / 16;
+    constexpr bool HALF = std::is_same<V, h2>::value;
     static_for<S::kStages>([&](auto si) {
         constexpr int s = decltype(si)::value;
         constexpr int R = S::radix(s);
         constexpr int NS = S::ns(s);
         constexpr bool LAST = (s == S::kStages - 1);
+        constexpr bool SC = HALF_NORM && s > 0 && (s % 2 == 0);
+        V base;
+        h2 tw[16];
+        if constexpr (HALF) {
+            base = cone<V>();
+            if constexpr (NS > 1) {
+                float2 b = tb.b[s];
+                asm volatile("" : "+v"(b.x), "+v"(b.y));  // recompute per use, not hoisted
+                stage_tw_h<LOG2L, s>(b, tw);
+            }
+        } else {
+            base = tb.b[s];
+        }
         if constexpr (!LAST) {
             __syncthreads();
-            stockham_stage<L, R, NS, DIR, false>(v, j, tb.b[s], st);
+            stockham_stage<L, R, NS, DIR, false, SC>(v, j, base, lds, tw);
             __syncthreads();
-#pragma unroll
-            for (int e = 0; e < 16; ++e) v[e] = ld(j + TPV * e);
+            static_for<16>([&](auto ei) {
+                constexpr int e = decltype(ei)::value;
+                v[e] = lds.template get<TPV * e>(j);
+            });
         } else {
-            stockham_stage<L, R, NS, DIR, true>(v, j, tb.b[s], st);
+            stockham_stage<L, R, NS, DIR, true, SC>(v, j, base, lds, tw);
         }
     });
 }
@@ -436,7 +664,7 @@ __device__ __forceinline__ void colfft_mfma(int c, int j, const float2* __restri
         float2 v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = lds(j + TPV * e);
-        stockham_stage<L, S::kRem, S::ns(s), DIR, true>(v, j, tb.b[s], [](int, float2) {});
+        stockham_stage<L, S::kRem, S::ns(s), DIR, true>(v, j, tb.b[s], NoLds<float2>{});
         if constexpr (OUT_SYNC) __syncthreads();
 #pragma unroll
         for (int e = 0; e < 16; ++e) out(j + TPV * e, cscale(v[e], scale_rem));

@@ -13,7 +13,7 @@ namespace pond {
 constexpr double kFoldScale = 65536.0;
 constexpr double kFoldRangeLimit = 1099511627776.0;  // 2^40: flag larger single contributions
 
-enum Precision { kFp32 = 0, kMixed = 1, kMixedValu = 2 };
+enum Precision { kFp32 = 0, kMixed = 1, kMixedValu = 2, kHalf = 3 };
 
 // K1: int8 unpack + forward column FFTs (length n2, stride n1).
 struct K1Args {
@@ -44,7 +44,10 @@ struct K2Args {
     const float4* table;    // kRowFull: [n2][n1] four-step twiddle (x, y), inverse ISM response (z, w)
     const float2* tw4;      // kRowFwd, kRowInv: [n2][n1] four-step twiddle
     const float2* chirp;    // kRowInv: [n2][n1] inverse ISM response of one trial
-    float scale;            // power-of-two scale applied on output
+    float scale;            // power-of-two scale applied on output (float32 arithmetic)
+    const void* htable;     // packed float16, kRowFull: [n2][n1] 4 halves (twiddle / 16, chirp * 2^-rem)
+    const void* htw4;       // packed float16, split modes: [n2][n1] twiddle / 16
+    const void* hchirp;     // packed float16, kRowInv: [n2][n1] chirp of one trial
 };
 
 // K3: inverse column FFTs, detection, decimation, fold partials.
@@ -56,7 +59,8 @@ struct K3Args {
     int64_t n_front;
     int64_t block0;
     const float2* tw2;
-    float scale;            // power-of-two scale of the inverse column output
+    float scale;            // power-of-two scale of the inverse column output (float32 arithmetic)
+    float pscale;           // scale of the detected power (packed float16: 256, else 1)
     // series
     float* series;          // NULL: no series this call
     int64_t series_base;    // group index (in units of decim) of series[0]
@@ -90,6 +94,16 @@ hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chi
 hipError_t launch_k2_build_split_tables(float2* tw, float2* chirp, int log2n1, int log2n2, double chirp_a, double f0,
                                         double df, hipStream_t s);
 
+hipError_t launch_k2_build_table_h(void* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
+                                   hipStream_t s);
+hipError_t launch_k2_build_split_tables_h(void* tw, void* chirp, int log2n1, int log2n2, double chirp_a, double f0,
+                                          double df, hipStream_t s);
+// Packed-float16 row transforms apply 2^-half_row_rem(log2n1) of their
+// 1/n1 normalisation after the stages (the rest is spread over them).
+constexpr int half_row_rem(int log2n1) {
+    return log2n1 - 4 * ((log2n1 / 4 + (log2n1 % 4 ? 1 : 0) + 1) / 2);
+}
+
 hipError_t launch_fold_profiles(const uint64_t* acc_sum, const uint64_t* acc_cnt, int64_t n, float* profiles,
                                 hipStream_t s);
 
@@ -106,6 +120,8 @@ int64_t hist_capacity(int log2n2);
 // blocks per launch it picks (max_batch <= 0: the default).
 int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t max_batch);
 int plan_max_batch(int64_t nfft, int32_t precision, int32_t max_batch);
+// Mean power gain of the packed-float16 stage twiddles of a 2^log2l transform.
+double half_twiddle_gain(int log2l);
 
 // Static LDS bytes of the K3 tile for a column length 2^log2n2.
 size_t k3_static_lds(int log2n2);

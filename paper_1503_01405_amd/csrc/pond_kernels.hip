@@ -18,6 +18,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <type_traits>
 
 #include "pond_fft.hpp"
@@ -57,11 +58,57 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
 }
 
 // ------------------------------------------------------------------- K1
-template <int LOG2N2, class T, bool MFMA>
+// Arithmetic of a kernel instance: float32 vector, float16 matrix-core
+// DFT-16 stages (float32 elsewhere), or packed float16 vector.
+constexpr int kFormF32 = 0, kFormMfma = 1, kFormF16 = 2;
+
+template <int FORM>
+using LdsVal = std::conditional_t<FORM == kFormF16, h2, float2>;
+
+// Float16 pair for the complex value (c, s) of magnitude m (float64 in):
+// among the neighbouring float16 values of each component, the pair whose
+// squared magnitude is closest to m^2.  Nearest rounding of each component
+// would leave |w|^2 errors of ~3e-4 that do not average out over a small
+// table (every stage of every block reuses the same few hundred entries).
+__device__ __forceinline__ void f16_neighbours(double x, _Float16 (&h)[2]) {
+    h[0] = (_Float16)x;
+    const uint16_t b = __builtin_bit_cast(uint16_t, h[0]);
+    const double d = (double)h[0];
+    uint16_t o;
+    if (d == x) o = b;
+    else if ((d < x) == (d >= 0.0 && !(b & 0x8000u))) o = (uint16_t)(b + 1);  // away from zero
+    else o = (b & 0x7fffu) ? (uint16_t)(b - 1) : (uint16_t)(b ^ 0x8000u);     // toward zero (or past it)
+    h[1] = __builtin_bit_cast(_Float16, o);
+}
+__device__ __forceinline__ h2 f16_unit(double c, double s, double m) {
+    _Float16 hc[2], hs[2];
+    f16_neighbours(c, hc);
+    f16_neighbours(s, hs);
+    h2 best = {hc[0], hs[0]};
+    double be = 1e300;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const double cc = (double)hc[i], ss = (double)hs[k];
+            const double err = fabs(cc * cc + ss * ss - m * m);
+            if (err < be) {
+                be = err;
+                best = h2{hc[i], hs[k]};
+            }
+        }
+    return best;
+}
+
+// Reinterpret float16 storage as a packed pair.
+__device__ __forceinline__ h2 ld_h2(const __half2* p) { return *reinterpret_cast<const h2*>(p); }
+__device__ __forceinline__ void st_h2(__half2* p, h2 v) { *reinterpret_cast<h2*>(p) = v; }
+
+template <int LOG2N2, class T, int FORM>
 __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     constexpr int L = 1 << LOG2N2;
     constexpr int TPV = L / 16;
-    __shared__ float2 lds[16 * L];
+    __shared__ LdsVal<FORM> lds[16 * L];
 
     const int n1 = 1 << a.log2n1;
     const int tiles_per_block = n1 >> 4;
@@ -82,36 +129,62 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     const int8_t* tbase = a.tail + 2 * (bstart - a.tail_start);
     const int8_t* ibase = a.in + 2 * (bstart - a.in_start);
     const uint32_t o0 = opaque((uint32_t)col);
-    auto load_in = [&](int pos) {
+    auto load_raw = [&](int pos) {
         const uint32_t off = o0 + ((uint32_t)pos << a.log2n1);
         const int8_t* p = off < split ? tbase + 2 * off : ibase + 2 * off;
-        const short s = *reinterpret_cast<const short*>(p);
+        return *reinterpret_cast<const short*>(p);
+    };
+    auto load_in = [&](int pos) {
+        const short s = load_raw(pos);
         return make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)(s >> 8));
     };
     T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
-    StageBases<LOG2N2> tb;
-    tb.load(j, a.tw2);
-    if constexpr (MFMA && LOG2N2 >= 6) {
-        // Normalised forward pass (1/16 per radix-16 stage, folded into the
-        // DFT matrix): no float16 value can exceed the input range.
-        const uint32_t w0 = opaque((uint32_t)col);
-        colfft_mfma<LOG2N2, -1, false>(
-            c, j, a.tw2, tb, 1.0f / 16.0f, 1.0f / (float)Sched<LOG2N2>::kRem, load_in,
-            [&](int pos) -> float2& { return lds[pos * 16 + c]; },
-            [&](int pos, float2 y) {
-                Elem<T>::store(at(out, (w0 + ((uint32_t)pos << a.log2n1)) * (uint32_t)sizeof(T)), y);
-            });
-    } else {
-        float2 v[16];
+    if constexpr (FORM == kFormF16) {
+        // Packed float16: int8 is exact in float16; the first stage's 1/16
+        // is applied here, the even stages scale themselves, and the rest
+        // of the 1/n2 normalisation is applied on output, so no value
+        // exceeds 16x the input bound.
+        StageBases<LOG2N2, h2> tb;
+        tb.load(j, a.tw2);
+        h2 v[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = load_in(j + TPV * e);
-        fft_wg<LOG2N2, -1>(
-            v, j, tb, [&](int pos) { return lds[pos * 16 + c]; }, [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
+        for (int e = 0; e < 16; ++e) {
+            const short s = load_raw(j + TPV * e);
+            const h2 x = {(_Float16)(int8_t)(s & 0xff), (_Float16)(int8_t)(s >> 8)};
+            v[e] = x * (_Float16)0.0625f;
+        }
+        fft_wg<LOG2N2, -1, true>(v, j, tb, ColLds<h2>{lds + c});
+        constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N2>::kHalfRem);
         const uint32_t w0 = opaque((uint32_t)col);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const uint32_t k2 = j + TPV * e;
-            Elem<T>::store(at(out, (w0 + (k2 << a.log2n1)) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+            st_h2(at(out, (w0 + (k2 << a.log2n1)) * (uint32_t)sizeof(T)), v[e] * (_Float16)osc);
+        }
+    } else {
+        StageBases<LOG2N2> tb;
+        tb.load(j, a.tw2);
+        if constexpr (FORM == kFormMfma && LOG2N2 >= 6) {
+            // Normalised forward pass (1/16 per radix-16 stage, folded into
+            // the DFT matrix): no float16 value can exceed the input range.
+            const uint32_t w0 = opaque((uint32_t)col);
+            colfft_mfma<LOG2N2, -1, false>(
+                c, j, a.tw2, tb, 1.0f / 16.0f, 1.0f / (float)Sched<LOG2N2>::kRem, load_in,
+                [&](int pos) -> float2& { return lds[pos * 16 + c]; },
+                [&](int pos, float2 y) {
+                    Elem<T>::store(at(out, (w0 + ((uint32_t)pos << a.log2n1)) * (uint32_t)sizeof(T)), y);
+                });
+        } else {
+            float2 v[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = load_in(j + TPV * e);
+            fft_wg<LOG2N2, -1>(v, j, tb, ColLds<float2>{lds + c});
+            const uint32_t w0 = opaque((uint32_t)col);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t k2 = j + TPV * e;
+                Elem<T>::store(at(out, (w0 + (k2 << a.log2n1)) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+            }
         }
     }
 }
@@ -163,12 +236,18 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 //                  spectrum, row k2 holding bins k2 + n2 k1 (float2 twiddle table).
 //   MODE kRowInv:  spectrum (in) times one trial's chirp (float2 table),
 //                  inverse FFT, conjugate twiddle, to `out`.
-template <int LOG2N1, class T, int MODE>
+// F16: packed float16 arithmetic on float16 storage with float16 tables
+// (kRowFull: 4 halves per entry, twiddle/16 and chirp*2^-kHalfRem; split
+// modes: twiddle/16 and chirp).  The forward transform is normalised stage
+// by stage (1/16 of the first stage in the twiddle table), so the spectrum
+// is the block's spectrum / n; the output is 1/16 of the float32 forms'.
+template <int LOG2N1, class T, int MODE, bool F16>
 __global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k2_row(K2Args a) {
     using Sh = K2Shape<LOG2N1>;
+    using V = std::conditional_t<F16, h2, float2>;
     constexpr int TPV = Sh::TPV;
-    __shared__ float2 lds[Sh::ROWS * Sh::STRIDE];
+    __shared__ V lds[Sh::ROWS * Sh::STRIDE];
 
     const int logical = xcd_logical(blockIdx.x, gridDim.x);
     const int n2 = 1 << a.log2n2;
@@ -181,11 +260,9 @@ k2_row(K2Args a) {
     const int j = threadIdx.x - r * TPV;
     const int row = rg * Sh::ROWS + r;
     const bool valid = row < n2;
-    float2* my = lds + r * Sh::STRIDE;
-    auto ld = [&](int pos) { return my[pos + (pos >> 4)]; };
-    auto st = [&](int pos, float2 x) { my[pos + (pos >> 4)] = x; };
+    const PadLds<V> lrow{lds + r * Sh::STRIDE};
 
-    StageBases<LOG2N1> tb;
+    StageBases<LOG2N1, V> tb;
     tb.load(j, a.tw1);
     // Uniform base pointers plus 32-bit per-thread offsets (rows beyond n2,
     // possible only for the shortest rows, re-read the last row and never
@@ -193,65 +270,166 @@ k2_row(K2Args a) {
     const int row0 = min(rg * Sh::ROWS, n2 - 1);
     const uint32_t toff = (uint32_t)(min(r, n2 - 1 - row0) << LOG2N1) + (uint32_t)j;
     const int64_t rowbase = (((int64_t)b << a.log2n2) + row0) << LOG2N1;
-    const float4* tab = a.table + ((int64_t)row0 << LOG2N1);
-    const float2* tw4 = a.tw4 + ((int64_t)row0 << LOG2N1);
-    const float2* chirp = a.chirp + ((int64_t)row0 << LOG2N1);
     T* rows = reinterpret_cast<T*>(a.work) + rowbase;
     const T* src = MODE == kRowInv ? reinterpret_cast<const T*>(a.in) + rowbase : rows;
     T* dst = MODE == kRowInv ? reinterpret_cast<T*>(a.out) + rowbase : rows;
 
-    float2 v[16];
-    uint32_t to = opaque(toff);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const float2 x = Elem<T>::load(at(src, (to + TPV * e) * (uint32_t)sizeof(T)));
-        if constexpr (MODE == kRowFull) {
-            const float4 t = *at(tab, (to + TPV * e) * 16u);
-            v[e] = cmul(x, make_float2(t.x, t.y));
-        } else if constexpr (MODE == kRowFwd) {
-            v[e] = cmul(x, *at(tw4, (to + TPV * e) * 8u));
-        } else {
-            v[e] = cmul(x, *at(chirp, (to + TPV * e) * 8u));
-        }
-    }
-    if constexpr (MODE != kRowInv) {
-        fft_wg<LOG2N1, -1>(v, j, tb, ld, st);
-    }
-    if constexpr (MODE == kRowFull) {
-        // Re-read the table (from L2) rather than keep it live across the
-        // transforms: registers are the occupancy limit of this kernel.
-        asm volatile("" ::: "memory");
-        to = opaque(toff);
+    if constexpr (F16) {
+        const uint2* tab = reinterpret_cast<const uint2*>(a.htable) + ((int64_t)row0 << LOG2N1);
+        const h2* tw4 = reinterpret_cast<const h2*>(a.htw4) + ((int64_t)row0 << LOG2N1);
+        const h2* chirp = reinterpret_cast<const h2*>(a.hchirp) + ((int64_t)row0 << LOG2N1);
+        auto tw_at = [&](uint32_t i) {
+            if constexpr (MODE == kRowFull) return __builtin_bit_cast(h2, at(tab, i * 8u)->x);
+            else return *at(tw4, i * 4u);
+        };
+        h2 v[16];
+        uint32_t to = opaque(toff);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const float4 t = *at(tab, (to + TPV * e) * 16u);
-            v[e] = cmul(v[e], make_float2(t.z, t.w));
+            const uint32_t i = to + TPV * e;
+            const h2 x = ld_h2(at(src, i * (uint32_t)sizeof(T)));
+            if constexpr (MODE == kRowInv) v[e] = cmul(x, *at(chirp, i * 4u));
+            else v[e] = cmul(x, tw_at(i));
         }
-    }
-    if constexpr (MODE == kRowFwd) {
-        if (valid) {
+        if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true>(v, j, tb, lrow);
+        if constexpr (MODE == kRowFwd) {
+            constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N1>::kHalfRem);
+            if (valid) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    st_h2(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), v[e] * (_Float16)osc);
+            }
+            return;
+        }
+        if constexpr (MODE == kRowFull) {
+            asm volatile("" ::: "memory");
+            to = opaque(toff);
 #pragma unroll
             for (int e = 0; e < 16; ++e)
-                Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+                v[e] = cmul(v[e], __builtin_bit_cast(h2, at(tab, (to + TPV * e) * 8u)->y));
+        }
+        fft_wg<LOG2N1, +1>(v, j, tb, lrow);
+        asm volatile("" ::: "memory");
+        to = opaque(toff);
+        if (valid) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t i = to + TPV * e;
+                st_h2(at(dst, i * (uint32_t)sizeof(T)), cmulc(v[e], tw_at(i)));
+            }
         }
         return;
-    }
-    fft_wg<LOG2N1, +1>(v, j, tb, ld, st);
-    asm volatile("" ::: "memory");
-    to = opaque(toff);
-    if (valid) {
+    } else {
+        const float4* tab = a.table + ((int64_t)row0 << LOG2N1);
+        const float2* tw4 = a.tw4 + ((int64_t)row0 << LOG2N1);
+        const float2* chirp = a.chirp + ((int64_t)row0 << LOG2N1);
+        float2 v[16];
+        uint32_t to = opaque(toff);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            float2 w;
+            const float2 x = Elem<T>::load(at(src, (to + TPV * e) * (uint32_t)sizeof(T)));
             if constexpr (MODE == kRowFull) {
                 const float4 t = *at(tab, (to + TPV * e) * 16u);
-                w = make_float2(t.x, t.y);
+                v[e] = cmul(x, make_float2(t.x, t.y));
+            } else if constexpr (MODE == kRowFwd) {
+                v[e] = cmul(x, *at(tw4, (to + TPV * e) * 8u));
             } else {
-                w = *at(tw4, (to + TPV * e) * 8u);
+                v[e] = cmul(x, *at(chirp, (to + TPV * e) * 8u));
             }
-            Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(cmulc(v[e], w), a.scale));
+        }
+        if constexpr (MODE != kRowInv) {
+            fft_wg<LOG2N1, -1>(v, j, tb, lrow);
+        }
+        if constexpr (MODE == kRowFull) {
+            // Re-read the table (from L2) rather than keep it live across the
+            // transforms: registers are the occupancy limit of this kernel.
+            asm volatile("" ::: "memory");
+            to = opaque(toff);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const float4 t = *at(tab, (to + TPV * e) * 16u);
+                v[e] = cmul(v[e], make_float2(t.z, t.w));
+            }
+        }
+        if constexpr (MODE == kRowFwd) {
+            if (valid) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+            }
+            return;
+        }
+        fft_wg<LOG2N1, +1>(v, j, tb, lrow);
+        asm volatile("" ::: "memory");
+        to = opaque(toff);
+        if (valid) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                float2 w;
+                if constexpr (MODE == kRowFull) {
+                    const float4 t = *at(tab, (to + TPV * e) * 16u);
+                    w = make_float2(t.x, t.y);
+                } else {
+                    w = *at(tw4, (to + TPV * e) * 8u);
+                }
+                Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(cmulc(v[e], w), a.scale));
+            }
         }
     }
+}
+
+// Float16 table of the middle pass for the packed-float16 form, 8 bytes per
+// (k2, k1): the four-step twiddle / 16 and the inverse ISM response times
+// 2^-rem (rem: the part of the row normalisation not applied by the
+// transform's stages), both evaluated in float64 as in k2_build_table.
+__global__ void __launch_bounds__(256) k2_build_table_h(uint2* __restrict__ tab, int log2n1, int log2n2,
+                                                         double chirp_a, double f0, double df, double chirp_scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
+    const int64_t n = 1ll << log2n;
+    if (i >= n) return;
+    const int64_t k2 = i >> log2n1;
+    const int64_t k1 = i & ((1ll << log2n1) - 1);
+    const int64_t r = (k1 * k2) & (n - 1);
+    double s, c;
+    sincospi(2.0 * (double)r / (double)n, &s, &c);
+    const int64_t k = k2 + (k1 << log2n2);
+    const int64_t kk = k < (n >> 1) ? k : k - n;
+    const double f = (double)kk * df;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double cs, cc;
+    sincospi(2.0 * frac, &cs, &cc);
+    const h2 tw = f16_unit(c / 16.0, -s / 16.0, 1.0 / 16.0);
+    const h2 ch = f16_unit(cc * chirp_scale, -cs * chirp_scale, chirp_scale);
+    tab[i] = make_uint2(__builtin_bit_cast(uint32_t, tw), __builtin_bit_cast(uint32_t, ch));
+}
+
+// Float16 tables of the split middle pass: twiddle / 16 (tw) and, per trial
+// DM, the inverse ISM response (chirp).
+__global__ void __launch_bounds__(256) k2_build_split_tables_h(h2* __restrict__ tw, h2* __restrict__ chirp,
+                                                                int log2n1, int log2n2, double chirp_a, double f0,
+                                                                double df) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
+    const int64_t n = 1ll << log2n;
+    if (i >= n) return;
+    const int64_t k2 = i >> log2n1;
+    const int64_t k1 = i & ((1ll << log2n1) - 1);
+    if (tw) {
+        const int64_t r = (k1 * k2) & (n - 1);
+        double s, c;
+        sincospi(2.0 * (double)r / (double)n, &s, &c);
+        tw[i] = f16_unit(c / 16.0, -s / 16.0, 1.0 / 16.0);
+    }
+    const int64_t k = k2 + (k1 << log2n2);
+    const int64_t kk = k < (n >> 1) ? k : k - n;
+    const double f = (double)kk * df;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double cs, cc;
+    sincospi(2.0 * frac, &cs, &cc);
+    chirp[i] = f16_unit(cc, -cs, 1.0);
 }
 
 // Tables of the split middle pass: tw[i] = W_n^(k1 k2) for i = k2 n1 + k1;
@@ -329,7 +507,7 @@ __device__ __forceinline__ void fold_add(const K3Args& a, uint64_t* hsum, uint32
     }
 }
 
-template <int LOG2N2, class T, bool MFMA>
+template <int LOG2N2, class T, int FORM>
 __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     using Sh = K3Shape<LOG2N2>;
     constexpr int L = Sh::L;
@@ -363,7 +541,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     const int chunk = (items + 7) >> 3;
     const int it_end = min(items, (xcd + 1) * chunk);
     uint32_t flags = 0;
-    StageBases<LOG2N2> tb;
+    StageBases<LOG2N2, LdsVal<FORM>> tb;
     tb.load(j, a.tw2);
 
     for (int item = xcd * chunk + local; item < it_end; item += per_xcd) {
@@ -376,7 +554,23 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         auto load_in = [&](int pos) {
             return Elem<T>::load(at(in, (o0 + ((uint32_t)pos << a.log2n1)) * (uint32_t)sizeof(T)));
         };
-        if constexpr (MFMA && LOG2N2 >= 6) {
+        if constexpr (FORM == kFormF16) {
+            // Packed float16 inverse transform (unnormalised), then the
+            // power in float32 from the float16 pair (exact products).
+            h2* lh = reinterpret_cast<h2*>(lds);
+            h2 v[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                v[e] = ld_h2(at(in, (o0 + ((uint32_t)(j + TPV * e) << a.log2n1)) * (uint32_t)sizeof(T)));
+            fft_wg<LOG2N2, +1>(v, j, tb, ColLds<h2>{lh + c});
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const float yx = (float)v[e].x, yy = (float)v[e].y;
+                pf[(j + TPV * e) * PSTRIDE + c] = fmaf(yx, yx, yy * yy) * a.pscale;
+            }
+            __syncthreads();
+        } else if constexpr (FORM == kFormMfma && LOG2N2 >= 6) {
             __syncthreads();  // the previous item's epilogue has finished with the LDS
             colfft_mfma<LOG2N2, +1, true>(
                 c, j, a.tw2, tb, 1.0f, 1.0f, load_in, [&](int pos) -> float2& { return lds[pos * 16 + c]; },
@@ -389,9 +583,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             float2 v[16];
 #pragma unroll
             for (int e = 0; e < 16; ++e) v[e] = load_in(j + TPV * e);
-            fft_wg<LOG2N2, +1>(
-                v, j, tb, [&](int pos) { return lds[pos * 16 + c]; },
-                [&](int pos, float2 x) { lds[pos * 16 + c] = x; });
+            fft_wg<LOG2N2, +1>(v, j, tb, ColLds<float2>{lds + c});
 
             // Detected powers to LDS, one row of 16 columns per output row.
             __syncthreads();
@@ -556,64 +748,69 @@ __global__ void __launch_bounds__(256) zero_u64(uint64_t* p, int64_t n) {
 }
 
 // ---------------------------------------------------------- launchers
-template <class T, bool MFMA, int LOG2N2>
+template <class T, int FORM, int LOG2N2>
 static hipError_t k1_one(const K1Args& a, hipStream_t s) {
     const int ntiles = a.nblocks * ((1 << a.log2n1) >> 4);
     const int grid = (ntiles + 7) & ~7;
-    hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, MFMA>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
+    hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, FORM>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
     return hipGetLastError();
 }
 
-template <class T, bool MFMA>
+template <class T, int FORM>
 static hipError_t k1_dispatch(int log2n2, const K1Args& a, hipStream_t s) {
     switch (log2n2) {
-        case 5: return k1_one<T, MFMA, 5>(a, s);
-        case 6: return k1_one<T, MFMA, 6>(a, s);
-        case 7: return k1_one<T, MFMA, 7>(a, s);
-        case 8: return k1_one<T, MFMA, 8>(a, s);
-        case 9: return k1_one<T, MFMA, 9>(a, s);
-        case 10: return k1_one<T, MFMA, 10>(a, s);
+        case 5: return k1_one<T, FORM, 5>(a, s);
+        case 6: return k1_one<T, FORM, 6>(a, s);
+        case 7: return k1_one<T, FORM, 7>(a, s);
+        case 8: return k1_one<T, FORM, 8>(a, s);
+        case 9: return k1_one<T, FORM, 9>(a, s);
+        case 10: return k1_one<T, FORM, 10>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s) {
     switch (prec) {
-        case kMixed: return k1_dispatch<__half2, true>(log2n2, a, s);
-        case kMixedValu: return k1_dispatch<__half2, false>(log2n2, a, s);
-        default: return k1_dispatch<float2, false>(log2n2, a, s);
+        case kMixed: return k1_dispatch<__half2, kFormMfma>(log2n2, a, s);
+        case kMixedValu: return k1_dispatch<__half2, kFormF32>(log2n2, a, s);
+        case kHalf: return k1_dispatch<__half2, kFormF16>(log2n2, a, s);
+        default: return k1_dispatch<float2, kFormF32>(log2n2, a, s);
     }
 }
 
-template <class T, int MODE, int LOG2N1>
+template <class T, int MODE, bool F16, int LOG2N1>
 static hipError_t k2_one(const K2Args& a, hipStream_t s) {
     using Sh = K2Shape<LOG2N1>;
     const int groups = ((1 << a.log2n2) + Sh::ROWS - 1) / Sh::ROWS * a.nblocks;
     const int grid = (groups + 7) & ~7;
-    hipLaunchKernelGGL((k2_row<LOG2N1, T, MODE>), dim3(grid), dim3(Sh::THREADS), 0, s, a);
+    hipLaunchKernelGGL((k2_row<LOG2N1, T, MODE, F16>), dim3(grid), dim3(Sh::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-template <class T, int MODE>
+template <class T, int MODE, bool F16>
 static hipError_t k2_dispatch(int log2n1, const K2Args& a, hipStream_t s) {
     switch (log2n1) {
-        case 5: return k2_one<T, MODE, 5>(a, s);
-        case 6: return k2_one<T, MODE, 6>(a, s);
-        case 7: return k2_one<T, MODE, 7>(a, s);
-        case 8: return k2_one<T, MODE, 8>(a, s);
-        case 9: return k2_one<T, MODE, 9>(a, s);
-        case 10: return k2_one<T, MODE, 10>(a, s);
-        case 11: return k2_one<T, MODE, 11>(a, s);
-        case 12: return k2_one<T, MODE, 12>(a, s);
-        case 13: return k2_one<T, MODE, 13>(a, s);
-        case 14: return k2_one<T, MODE, 14>(a, s);
+        case 5: return k2_one<T, MODE, F16, 5>(a, s);
+        case 6: return k2_one<T, MODE, F16, 6>(a, s);
+        case 7: return k2_one<T, MODE, F16, 7>(a, s);
+        case 8: return k2_one<T, MODE, F16, 8>(a, s);
+        case 9: return k2_one<T, MODE, F16, 9>(a, s);
+        case 10: return k2_one<T, MODE, F16, 10>(a, s);
+        case 11: return k2_one<T, MODE, F16, 11>(a, s);
+        case 12: return k2_one<T, MODE, F16, 12>(a, s);
+        case 13: return k2_one<T, MODE, F16, 13>(a, s);
+        case 14: return k2_one<T, MODE, F16, 14>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int MODE>
 static hipError_t k2_prec(int prec, int log2n1, const K2Args& a, hipStream_t s) {
-    return prec == kFp32 ? k2_dispatch<float2, MODE>(log2n1, a, s) : k2_dispatch<__half2, MODE>(log2n1, a, s);
+    switch (prec) {
+        case kFp32: return k2_dispatch<float2, MODE, false>(log2n1, a, s);
+        case kHalf: return k2_dispatch<__half2, MODE, true>(log2n1, a, s);
+        default: return k2_dispatch<__half2, MODE, false>(log2n1, a, s);
+    }
 }
 
 hipError_t launch_k2(int prec, int mode, int log2n1, const K2Args& a, hipStream_t s) {
@@ -633,34 +830,52 @@ hipError_t launch_k2_build_split_tables(float2* tw, float2* chirp, int log2n1, i
     return hipGetLastError();
 }
 
-template <class T, bool MFMA, int LOG2N2>
-static hipError_t k3_one(const K3Args& a, int grid, size_t dyn, hipStream_t s) {
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k3_colinv_detect_fold<LOG2N2, T, MFMA>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - K3Shape<LOG2N2>::LDS));
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k3_colinv_detect_fold<LOG2N2, T, MFMA>), dim3(grid), dim3(1 << LOG2N2), dyn, s, a);
+hipError_t launch_k2_build_split_tables_h(void* tw, void* chirp, int log2n1, int log2n2, double chirp_a, double f0,
+                                          double df, hipStream_t s) {
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    hipLaunchKernelGGL(k2_build_split_tables_h, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<h2*>(tw), reinterpret_cast<h2*>(chirp), log2n1, log2n2, chirp_a, f0, df);
     return hipGetLastError();
 }
 
-template <class T, bool MFMA>
+hipError_t launch_k2_build_table_h(void* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
+                                   hipStream_t s) {
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    const double chirp_scale = std::ldexp(1.0, -half_row_rem(log2n1));
+    hipLaunchKernelGGL(k2_build_table_h, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<uint2*>(tab), log2n1, log2n2, chirp_a, f0, df, chirp_scale);
+    return hipGetLastError();
+}
+
+template <class T, int FORM, int LOG2N2>
+static hipError_t k3_one(const K3Args& a, int grid, size_t dyn, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k3_colinv_detect_fold<LOG2N2, T, FORM>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - K3Shape<LOG2N2>::LDS));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k3_colinv_detect_fold<LOG2N2, T, FORM>), dim3(grid), dim3(1 << LOG2N2), dyn, s, a);
+    return hipGetLastError();
+}
+
+template <class T, int FORM>
 static hipError_t k3_dispatch(int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s) {
     switch (log2n2) {
-        case 5: return k3_one<T, MFMA, 5>(a, grid, dyn, s);
-        case 6: return k3_one<T, MFMA, 6>(a, grid, dyn, s);
-        case 7: return k3_one<T, MFMA, 7>(a, grid, dyn, s);
-        case 8: return k3_one<T, MFMA, 8>(a, grid, dyn, s);
-        case 9: return k3_one<T, MFMA, 9>(a, grid, dyn, s);
-        case 10: return k3_one<T, MFMA, 10>(a, grid, dyn, s);
+        case 5: return k3_one<T, FORM, 5>(a, grid, dyn, s);
+        case 6: return k3_one<T, FORM, 6>(a, grid, dyn, s);
+        case 7: return k3_one<T, FORM, 7>(a, grid, dyn, s);
+        case 8: return k3_one<T, FORM, 8>(a, grid, dyn, s);
+        case 9: return k3_one<T, FORM, 9>(a, grid, dyn, s);
+        case 10: return k3_one<T, FORM, 10>(a, grid, dyn, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_k3(int prec, int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s) {
     switch (prec) {
-        case kMixed: return k3_dispatch<__half2, true>(log2n2, a, grid, dyn, s);
-        case kMixedValu: return k3_dispatch<__half2, false>(log2n2, a, grid, dyn, s);
-        default: return k3_dispatch<float2, false>(log2n2, a, grid, dyn, s);
+        case kMixed: return k3_dispatch<__half2, kFormMfma>(log2n2, a, grid, dyn, s);
+        case kMixedValu: return k3_dispatch<__half2, kFormF32>(log2n2, a, grid, dyn, s);
+        case kHalf: return k3_dispatch<__half2, kFormF16>(log2n2, a, grid, dyn, s);
+        default: return k3_dispatch<float2, kFormF32>(log2n2, a, grid, dyn, s);
     }
 }
 
@@ -726,4 +941,14 @@ int k2_threads(int log2n1) {
     return tpv >= 256 ? tpv : 256;
 }
 
+}  // namespace pond
+
+namespace pond {
+// The host-side table scale must match the device schedule.
+static_assert(half_row_rem(5) == Sched<5>::kHalfRem && half_row_rem(6) == Sched<6>::kHalfRem &&
+                  half_row_rem(7) == Sched<7>::kHalfRem && half_row_rem(8) == Sched<8>::kHalfRem &&
+                  half_row_rem(9) == Sched<9>::kHalfRem && half_row_rem(10) == Sched<10>::kHalfRem &&
+                  half_row_rem(11) == Sched<11>::kHalfRem && half_row_rem(12) == Sched<12>::kHalfRem &&
+                  half_row_rem(13) == Sched<13>::kHalfRem && half_row_rem(14) == Sched<14>::kHalfRem,
+              "row normalisation split");
 }  // namespace pond

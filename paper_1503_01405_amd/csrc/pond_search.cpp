@@ -28,11 +28,14 @@ struct Group {
     int64_t nfft = 0, hop = 0;
     int log2n = 0, log2n1 = 0, log2n2 = 0;
     int max_batch = 1;
+    float pscale = 1.0f;  // detected-power scale of K3 (packed float16: see pond_api.cpp)
     std::vector<int> trials;
     float2* tw1 = nullptr;    // exp(-2 pi i t / n1)
     float2* tw2 = nullptr;    // exp(-2 pi i t / n2)
     float2* tw4 = nullptr;    // [n2][n1] four-step twiddle
-    std::vector<float2*> chirp;  // per trial of the group, [n2][n1]
+    std::vector<float2*> chirp;  // per trial of the group, [n2][n1] (float32 forms)
+    void* htw4 = nullptr;        // packed float16 form: [n2][n1] twiddle / 16
+    std::vector<void*> hchirp;   // packed float16 form: per trial, [n2][n1]
     void* spec = nullptr;     // max_batch blocks of spectrum
     void* out = nullptr;      // max_batch blocks of one trial's row-inverse output
 };
@@ -76,10 +79,12 @@ namespace {
 
 void free_search(pond_search* s) {
     for (auto& g : s->groups) {
-        void* ptrs[] = {g.tw1, g.tw2, g.tw4, g.spec, g.out};
+        void* ptrs[] = {g.tw1, g.tw2, g.tw4, g.htw4, g.spec, g.out};
         for (void* q : ptrs)
             if (q) (void)hipFree(q);
         for (float2* c : g.chirp)
+            if (c) (void)hipFree(c);
+        for (void* c : g.hchirp)
             if (c) (void)hipFree(c);
     }
     void* ptrs[] = {s->acc_sum, s->acc_cnt, s->part_sum, s->part_cnt, s->status};
@@ -114,7 +119,8 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
     if (!dms || ntrials < 1 || nbins < 1 || nbins > 65536) return nullptr;
     if (!std::isfinite(f0_mhz) || !std::isfinite(bw_mhz) || !std::isfinite(period_s)) return nullptr;
     if (!(bw_mhz > 0) || !(f0_mhz - bw_mhz / 2 > 0)) return nullptr;
-    if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU) return nullptr;
+    if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU && precision != POND_HALF)
+        return nullptr;
     if (nfft_min <= 0 || (nfft_min & (nfft_min - 1)) || nfft_max < nfft_min || (nfft_max & (nfft_max - 1)))
         return nullptr;
     if (ilog2(nfft_min) < 10 || ilog2(nfft_max) > kSearchMaxLog2N) return nullptr;
@@ -182,17 +188,31 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
         chk(hipMalloc(reinterpret_cast<void**>(&g.tw2), n2 * sizeof(float2)));
         if (e == hipSuccess) chk(hipMemcpy(g.tw1, t1.data(), n1 * sizeof(float2), hipMemcpyHostToDevice));
         if (e == hipSuccess) chk(hipMemcpy(g.tw2, t2.data(), n2 * sizeof(float2), hipMemcpyHostToDevice));
-        chk(hipMalloc(reinterpret_cast<void**>(&g.tw4), g.nfft * sizeof(float2)));
         chk(hipMalloc(&g.spec, (size_t)g.max_batch * g.nfft * s->elem));
         chk(hipMalloc(&g.out, (size_t)g.max_batch * g.nfft * s->elem));
+        const bool half = precision == POND_HALF;
+        if (half)
+            g.pscale = (float)(256.0 / (1.0 + 2.0 * half_twiddle_gain(g.log2n2) + 2.0 * half_twiddle_gain(g.log2n1)));
+        if (half) {
+            chk(hipMalloc(&g.htw4, g.nfft * 4));
+        }
+        else chk(hipMalloc(reinterpret_cast<void**>(&g.tw4), g.nfft * sizeof(float2)));
         g.chirp.assign(g.trials.size(), nullptr);
+        g.hchirp.assign(g.trials.size(), nullptr);
         for (size_t i = 0; i < g.trials.size() && e == hipSuccess; ++i) {
-            chk(hipMalloc(reinterpret_cast<void**>(&g.chirp[i]), g.nfft * sizeof(float2)));
             const double dm = s->dm[g.trials[i]];
-            if (e == hipSuccess)
-                chk(launch_k2_build_split_tables(i == 0 ? g.tw4 : nullptr, g.chirp[i], g.log2n1, g.log2n2,
-                                                 dm / (2.41e-10 * f0_mhz * f0_mhz), f0_mhz,
-                                                 bw_mhz / (double)g.nfft, nullptr));
+            const double a = dm / (2.41e-10 * f0_mhz * f0_mhz), df = bw_mhz / (double)g.nfft;
+            if (half) {
+                chk(hipMalloc(&g.hchirp[i], g.nfft * 4));
+                if (e == hipSuccess)
+                    chk(launch_k2_build_split_tables_h(i == 0 ? g.htw4 : nullptr, g.hchirp[i], g.log2n1, g.log2n2, a,
+                                                       f0_mhz, df, nullptr));
+            } else {
+                chk(hipMalloc(reinterpret_cast<void**>(&g.chirp[i]), g.nfft * sizeof(float2)));
+                if (e == hipSuccess)
+                    chk(launch_k2_build_split_tables(i == 0 ? g.tw4 : nullptr, g.chirp[i], g.log2n1, g.log2n2, a,
+                                                     f0_mhz, df, nullptr));
+            }
         }
     }
     chk(hipMalloc(reinterpret_cast<void**>(&s->acc_sum), (size_t)ntrials * nbins * 8));
@@ -273,6 +293,7 @@ int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* 
             f.log2n2 = g.log2n2;
             f.tw1 = g.tw1;
             f.tw4 = g.tw4;
+            f.htw4 = g.htw4;
             f.scale = std::ldexp(1.0f, -g.log2n1);
             e = launch_k2(s->precision, kRowFwd, g.log2n1, f, stream);
             if (e != hipSuccess) return fail();
@@ -286,6 +307,8 @@ int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* 
                 v.tw1 = g.tw1;
                 v.tw4 = g.tw4;
                 v.chirp = g.chirp[i];
+                v.htw4 = g.htw4;
+                v.hchirp = g.hchirp[i];
                 v.scale = 1.0f;
                 e = launch_k2(s->precision, kRowInv, g.log2n1, v, stream);
                 if (e != hipSuccess) return fail();
@@ -298,6 +321,7 @@ int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* 
                 a3.block0 = b;
                 a3.tw2 = g.tw2;
                 a3.scale = 1.0f;
+                a3.pscale = g.pscale;
                 a3.series = nullptr;
                 a3.series_base = 0;
                 a3.decim = 16;

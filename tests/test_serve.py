@@ -19,7 +19,7 @@ STREAMS = [
     (0.5, 1 << 16, 64, 2.1e-3, 300_000, "fp32"),
     (3.0, 1 << 19, 128, 0.033, 1_000_000, "mixed_valu"),
     (12.0, 1 << 21, 256, 0.25, 0, "mixed"),
-    (1.2, 1 << 18, 100, 0.0891, 700_000, "mixed_valu"),
+    (1.2, 1 << 18, 100, 0.0891, 700_000, "half"),
     (25.0, 1 << 22, 512, 1.3, 2_000_000, "fp32"),
 ]
 NSAMP = 6_000_000
