@@ -160,6 +160,21 @@ int64_t pond_dedisperse_series(pond_plan* p, const int8_t* iq, int64_t nsamp,
                                int64_t* n_series_out, void* hip_stream);
 
 /*
+ * Frequency-domain taper of the inverse filter (Sec. 3.7: the inverse ISM
+ * response is applied together with a taper against leakage of the square
+ * window; the paper does not give the taper).  alpha in [0, 1] is the edge
+ * fraction of a Tukey window over baseband frequency f in [-bw/2, bw/2]:
+ * w(f) = 1 for |f| <= (1 - alpha) bw/2, else
+ * (1 + cos(pi (|f| - (1 - alpha) bw/2) / (alpha bw/2))) / 2, reaching 0 at
+ * the band edge; alpha = 0 (the default of a new plan) is the unit taper.
+ * Allowed only at stream position 0 (new or flushed plan); rebuilds the
+ * plan's middle-pass table and synchronises the device.  Returns POND_OK,
+ * POND_EINVAL (alpha outside [0, 1], or samples already appended) or
+ * POND_EDEVICE.
+ */
+int32_t pond_plan_set_taper(pond_plan* p, double alpha);
+
+/*
  * Geometry and stream position.  Synchronises the plan's last stream to
  * read the device status word.  Returns POND_OK or an error code.
  */

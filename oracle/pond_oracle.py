@@ -27,7 +27,11 @@ fold).  The paper leaves several points open; the readings taken here are:
       samples are dropped, with s = ceil(delta_hi fs) + ceil(delta_lo fs)
       and discard = next_pow2(max(s, 16)) if that is <= N/2, otherwise s
       rounded up to a multiple of 16 (discard = 0 when s = 0).
-  C4  taper: unit (the paper does not say which taper it uses).
+  C4  taper: unit by default (the paper does not say which taper it
+      uses).  Optional reading: a Tukey window over baseband frequency,
+      w(f) = 1 for |f| <= (1 - alpha) bw/2 and
+      w(f) = (1 + cos(pi (|f| - (1 - alpha) bw/2) / (alpha bw/2))) / 2
+      beyond, falling to 0 at the band edge; it multiplies H^-1.
   C5  bin k = N/2 is the frequency -bw/2 (numpy fftfreq).
   C6  forward transform unnormalised, inverse with 1/N.
   C7  detection is |y|^2 with no baseline or bandpass correction.
@@ -143,9 +147,25 @@ def ism_response(nfft, f0_mhz, bw_mhz, dm):
     return np.exp(2j * np.pi * chirp_turns(baseband_freqs_mhz(nfft, bw_mhz), f0_mhz, dm))
 
 
-def dedispersion_chirp(nfft, f0_mhz, bw_mhz, dm):
-    """H^-1 on the FFT grid, exp(-2 pi i turns): the multiplier of Sec. 3.7."""
-    return np.exp(-2j * np.pi * chirp_turns(baseband_freqs_mhz(nfft, bw_mhz), f0_mhz, dm))
+def taper(f_mhz, bw_mhz, alpha):
+    """The frequency-domain taper of the filter (reading C4): a Tukey window
+    of edge fraction alpha over [-bw/2, bw/2]; alpha = 0 is the unit taper."""
+    f = np.abs(np.asarray(f_mhz, dtype=np.float64))
+    if alpha <= 0:
+        return np.ones_like(f)
+    flat = (1.0 - alpha) * bw_mhz / 2
+    edge = alpha * bw_mhz / 2
+    w = np.ones_like(f)
+    m = f > flat
+    w[m] = 0.5 * (1.0 + np.cos(np.pi * np.minimum(f[m] - flat, edge) / edge))
+    return w
+
+
+def dedispersion_chirp(nfft, f0_mhz, bw_mhz, dm, taper_alpha=0.0):
+    """H^-1 on the FFT grid, exp(-2 pi i turns), times the taper: the
+    multiplier of Sec. 3.7."""
+    f = baseband_freqs_mhz(nfft, bw_mhz)
+    return np.exp(-2j * np.pi * chirp_turns(f, f0_mhz, dm)) * taper(f, bw_mhz, taper_alpha)
 
 
 # --------------------------------------------------------------------------
@@ -169,7 +189,7 @@ def dedisperse_block(x_block, chirp, n_front, hop, workers=None):
 
 
 def dedisperse(x, f0_mhz, bw_mhz, dm, nfft, first_block=0, nblocks=None,
-               batch=8, workers=None, hop=None):
+               batch=8, workers=None, hop=None, taper_alpha=0.0):
     """Dedispersed voltages of blocks [first_block, first_block + nblocks).
 
     Block b covers input samples [b*hop, b*hop + nfft); its kept outputs are
@@ -189,7 +209,7 @@ def dedisperse(x, f0_mhz, bw_mhz, dm, nfft, first_block=0, nblocks=None,
         nblocks = total - first_block
     if first_block < 0 or first_block + nblocks > total:
         raise ValueError("block range not covered by the input")
-    chirp = dedispersion_chirp(nfft, f0_mhz, bw_mhz, dm)
+    chirp = dedispersion_chirp(nfft, f0_mhz, bw_mhz, dm, taper_alpha)
     y = np.empty(nblocks * hop, dtype=np.complex128)
     for b0 in range(0, nblocks, batch):
         nb = min(batch, nblocks - b0)
@@ -254,7 +274,7 @@ def profiles_from(sums, cnts):
 
 
 def run(iq, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, subint_nsamp=0,
-        decim=16, batch=8, workers=None, keep_power=False, hop=None):
+        decim=16, batch=8, workers=None, keep_power=False, hop=None, taper_alpha=0.0):
     """The whole path over one stream, every fully covered block.
 
     Returns a dict with
@@ -281,7 +301,8 @@ def run(iq, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, subint_nsamp=0,
     for b0 in range(0, nb, batch):
         k = min(batch, nb - b0)
         y, m0 = dedisperse(x, f0_mhz, bw_mhz, dm, nfft, first_block=b0,
-                           nblocks=k, batch=batch, workers=workers, hop=hop)
+                           nblocks=k, batch=batch, workers=workers, hop=hop,
+                           taper_alpha=taper_alpha)
         p = detect(y)
         series[m0 // decim:(m0 + p.size) // decim] = decimate(p, decim)
         s, c, s0 = fold(p, m0, n_front, period_s, g["fs"], nbins, subint_nsamp)

@@ -8,7 +8,7 @@ from .pond import (POND_EBUSY, POND_EDEVICE, POND_EINVAL, POND_ENOMEM, FORMS, PO
                    POND_OK, POND_STATUS_NONFINITE, POND_STATUS_RANGE, Plan, PondError,
                    pond_dedisperse_fold, pond_dedisperse_series, pond_plan_create,
                    pond_plan_destroy, pond_plan_expect, pond_plan_kernel_times,
-                   pond_plan_query, pond_plan_set_timing, pond_search_create, pond_search_destroy,
+                   pond_plan_query, pond_plan_set_taper, pond_plan_set_timing, pond_search_create, pond_search_destroy,
                    pond_search_run, pond_search_trial, pond_server_close, pond_server_create,
                    pond_server_destroy, pond_server_open, pond_server_poll, pond_server_query,
                    pond_server_stream_bytes, pond_server_submit, pond_server_take_profiles,

@@ -50,6 +50,7 @@ struct pond_plan {
     float4* table = nullptr;    // float32 forms
     void* htable = nullptr;     // packed float16 form (8 bytes per entry)
     float pscale = 1.0f;        // detected-power scale applied in K3
+    double taper = 0.0;         // Tukey edge fraction of the inverse filter (0: unit taper)
     uint64_t* acc_sum = nullptr;
     uint64_t* acc_cnt = nullptr;
     int64_t acc_slots = 0;
@@ -381,11 +382,11 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     if (precision == POND_HALF) {
         chk(hipMalloc(&p->htable, (size_t)nfft * 8));
         if (e == hipSuccess)
-            chk(launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, nullptr));
+            chk(launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, 0.0, nullptr));
     } else {
         chk(hipMalloc(reinterpret_cast<void**>(&p->table), (size_t)nfft * sizeof(float4)));
         if (e == hipSuccess)
-            chk(launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, nullptr));
+            chk(launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, 0.0, nullptr));
     }
     p->acc_slots = 4;
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_sum), (size_t)p->acc_slots * nbins * 8));
@@ -424,6 +425,30 @@ void pond_plan_destroy(pond_plan* p) {
         free_plan_memory(p);
     }
     delete p;
+}
+
+int32_t pond_plan_set_taper(pond_plan* p, double alpha) {
+    if (!p || !std::isfinite(alpha) || alpha < 0.0 || alpha > 1.0) return POND_EINVAL;
+    if (p->sticky) return POND_EDEVICE;
+    if (p->samples_in != 0) return POND_EINVAL;
+    DeviceGuard g(p->device);
+    if (p->last_stream && hipStreamSynchronize(p->last_stream) != hipSuccess) {
+        p->sticky = true;
+        return POND_EDEVICE;
+    }
+    hipError_t e = p->precision == POND_HALF
+                       ? launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha,
+                                                 nullptr)
+                       : launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha,
+                                               nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p->sticky = true;
+        return POND_EDEVICE;
+    }
+    p->taper = alpha;
+    return POND_OK;
 }
 
 int32_t pond_plan_query(pond_plan* p, pond_info* out) {

@@ -90,12 +90,12 @@ hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins,
                                 float* profiles, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
-                                 hipStream_t s);
+                                 double taper, hipStream_t s);
 hipError_t launch_k2_build_split_tables(float2* tw, float2* chirp, int log2n1, int log2n2, double chirp_a, double f0,
                                         double df, hipStream_t s);
 
 hipError_t launch_k2_build_table_h(void* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
-                                   hipStream_t s);
+                                   double taper, hipStream_t s);
 hipError_t launch_k2_build_split_tables_h(void* tw, void* chirp, int log2n1, int log2n2, double chirp_a, double f0,
                                           double df, hipStream_t s);
 // Packed-float16 row transforms apply 2^-half_row_rem(log2n1) of their

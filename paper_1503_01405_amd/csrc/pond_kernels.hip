@@ -199,13 +199,24 @@ struct K2Shape {
     static constexpr int STRIDE = L + L / 16;  // LDS row stride: one pad slot per 16 values
 };
 
+// Frequency-domain taper of the inverse filter at baseband frequency f
+// (MHz): a Tukey window of edge fraction alpha over [-bw/2, bw/2]
+// (alpha = 0: unit taper).  The paper applies an unspecified taper with the
+// inverse ISM response against leakage of the square window (Sec. 3.7).
+__device__ __forceinline__ double taper_w(double f, double bw, double alpha) {
+    if (!(alpha > 0.0)) return 1.0;
+    const double af = fabs(f), flat = (1.0 - alpha) * bw * 0.5, edge = alpha * bw * 0.5;
+    if (af <= flat) return 1.0;
+    return 0.5 * (1.0 + cos(M_PI * fmin(af - flat, edge) / edge));
+}
+
 // Row table of the middle pass, one float4 per (k2, k1):
 //   (x, y) = W_n^(k1 k2) = exp(-2 pi i (k1 k2 mod n) / n), the four-step twiddle
 //   (z, w) = exp(-2 pi i turns_k), k = k2 + n2 k1, the inverse ISM response
 //            of Sec. 3.7 / Eq. (4); turns_k and its reduction mod 1 are float64.
 // Built once per plan; every block reads the same table.
 __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, int log2n1, int log2n2,
-                                                       double chirp_a, double f0, double df) {
+                                                       double chirp_a, double f0, double df, double taper) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int log2n = log2n1 + log2n2;
     const int64_t n = 1ll << log2n;
@@ -222,7 +233,8 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
     const double frac = turns - rint(turns);
     double cs, cc;
     sincospi(2.0 * frac, &cs, &cc);
-    tab[i] = make_float4((float)c, (float)-s, (float)cc, (float)-cs);
+    const double w = taper_w(f, df * (double)n, taper);
+    tab[i] = make_float4((float)c, (float)-s, (float)(cc * w), (float)(-cs * w));
 }
 
 // One workgroup takes row k2 (ROWS rows for short rows) of one block.  The
@@ -383,7 +395,8 @@ k2_row(K2Args a) {
 // 2^-rem (rem: the part of the row normalisation not applied by the
 // transform's stages), both evaluated in float64 as in k2_build_table.
 __global__ void __launch_bounds__(256) k2_build_table_h(uint2* __restrict__ tab, int log2n1, int log2n2,
-                                                         double chirp_a, double f0, double df, double chirp_scale) {
+                                                         double chirp_a, double f0, double df, double chirp_scale,
+                                                         double taper) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int log2n = log2n1 + log2n2;
     const int64_t n = 1ll << log2n;
@@ -401,7 +414,8 @@ __global__ void __launch_bounds__(256) k2_build_table_h(uint2* __restrict__ tab,
     double cs, cc;
     sincospi(2.0 * frac, &cs, &cc);
     const h2 tw = f16_unit(c / 16.0, -s / 16.0, 1.0 / 16.0);
-    const h2 ch = f16_unit(cc * chirp_scale, -cs * chirp_scale, chirp_scale);
+    const double m = chirp_scale * taper_w(f, df * (double)n, taper);
+    const h2 ch = f16_unit(cc * m, -cs * m, m);
     tab[i] = make_uint2(__builtin_bit_cast(uint32_t, tw), __builtin_bit_cast(uint32_t, ch));
 }
 
@@ -839,11 +853,11 @@ hipError_t launch_k2_build_split_tables_h(void* tw, void* chirp, int log2n1, int
 }
 
 hipError_t launch_k2_build_table_h(void* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
-                                   hipStream_t s) {
+                                   double taper, hipStream_t s) {
     const int64_t n = 1ll << (log2n1 + log2n2);
     const double chirp_scale = std::ldexp(1.0, -half_row_rem(log2n1));
     hipLaunchKernelGGL(k2_build_table_h, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       reinterpret_cast<uint2*>(tab), log2n1, log2n2, chirp_a, f0, df, chirp_scale);
+                       reinterpret_cast<uint2*>(tab), log2n1, log2n2, chirp_a, f0, df, chirp_scale, taper);
     return hipGetLastError();
 }
 
@@ -894,10 +908,10 @@ hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins,
 }
 
 hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
-                                 hipStream_t s) {
+                                 double taper, hipStream_t s) {
     const int64_t n = 1ll << (log2n1 + log2n2);
     hipLaunchKernelGGL(k2_build_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n1, log2n2,
-                       chirp_a, f0, df);
+                       chirp_a, f0, df, taper);
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ EXPORTS = (
     "pond_plan_create", "pond_plan_create_ex", "pond_create_status",
     "pond_dedisperse_fold", "pond_dedisperse_series", "pond_plan_query",
     "pond_plan_expect", "pond_plan_destroy", "pond_strerror",
-    "pond_plan_set_timing", "pond_plan_kernel_times",
+    "pond_plan_set_timing", "pond_plan_kernel_times", "pond_plan_set_taper",
     "pond_search_create", "pond_search_run", "pond_search_trial", "pond_search_destroy",
     "pond_server_create", "pond_server_stream_bytes", "pond_server_open", "pond_server_submit",
     "pond_server_poll", "pond_server_take_profiles", "pond_server_close", "pond_server_query",
@@ -112,6 +112,8 @@ def _load():
     lib.pond_plan_destroy.restype = None
     lib.pond_plan_set_timing.argtypes = [P, i32]
     lib.pond_plan_set_timing.restype = i32
+    lib.pond_plan_set_taper.argtypes = [P, dbl]
+    lib.pond_plan_set_taper.restype = i32
     lib.pond_plan_kernel_times.argtypes = [P, ctypes.POINTER(pond_kernel_times)]
     lib.pond_plan_kernel_times.restype = i32
     lib.pond_search_create.argtypes = [dbl, dbl, ctypes.POINTER(dbl), i32, i32, dbl, i64, i64, i32]
@@ -232,6 +234,12 @@ def pond_plan_kernel_times(plan):
     return {KERNEL_NAMES[i]: (t.ms[i], t.launches[i], t.blocks[i]) for i in range(5)}
 
 
+def pond_plan_set_taper(plan, alpha):
+    r = _lib.pond_plan_set_taper(plan, float(alpha))
+    if r != POND_OK:
+        raise PondError(r, "pond_plan_set_taper")
+
+
 def pond_search_create(f0_mhz, bw_mhz, dms, nbins, period_s, nfft_min=1 << 20, nfft_max=1 << 23,
                        precision=POND_FP32):
     arr = (ctypes.c_double * len(dms))(*[float(d) for d in dms])
@@ -337,9 +345,11 @@ class Plan:
     """
 
     def __init__(self, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision="fp32",
-                 max_batch=0, subint_nsamp=0, decim=16):
+                 max_batch=0, subint_nsamp=0, decim=16, taper_alpha=0.0):
         prec = FORMS.get(precision, precision)
         self.handle = pond_plan_create(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, prec, max_batch)
+        if taper_alpha:
+            pond_plan_set_taper(self.handle, taper_alpha)
         self.nbins = int(nbins)
         self.subint = int(subint_nsamp)
         self.decim = int(decim)

@@ -23,7 +23,7 @@ def dispersed_pulsar_stream(seed, nsamp, dm, nfft_gen=1 << 20, period=synth.PERI
 
 
 def gpu_run(iq, dm, nfft, nbins, period, subint=0, decim=16, precision="fp32",
-            chunks=None, max_batch=0, want_series=True):
+            chunks=None, max_batch=0, want_series=True, taper=0.0):
     """Stream iq (numpy int8) through a plan in the given chunk sizes (one
     call if None), flush, and return (profiles [k, nbins], series) as numpy."""
     import torch
@@ -34,7 +34,7 @@ def gpu_run(iq, dm, nfft, nbins, period, subint=0, decim=16, precision="fp32",
     if chunks is None:
         chunks = [nsamp]
     plan = Plan(F0, BW, dm, nfft, nbins, period, precision=precision, max_batch=max_batch,
-                subint_nsamp=subint, decim=decim)
+                subint_nsamp=subint, decim=decim, taper_alpha=taper)
     profs, sers = [], []
     pos = 0
     for c in chunks:
@@ -55,11 +55,12 @@ def gpu_run(iq, dm, nfft, nbins, period, subint=0, decim=16, precision="fp32",
     return prof, ser
 
 
-def oracle_run(iq, dm, nfft, nbins, period, subint=0, decim=16):
+def oracle_run(iq, dm, nfft, nbins, period, subint=0, decim=16, taper=0.0):
     """Oracle profiles in the order the library emits them (completed
     sub-integrations, then the open one at the end of the stream) and the
     full decimated series."""
-    r = O.run(iq, F0, BW, dm, nfft, nbins, period, subint_nsamp=subint, decim=decim, workers=8)
+    r = O.run(iq, F0, BW, dm, nfft, nbins, period, subint_nsamp=subint, decim=decim, workers=8,
+              taper_alpha=taper)
     n_out = r["n_out"]
     if subint > 0:
         k = r["complete"]

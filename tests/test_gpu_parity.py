@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import dispersed_pulsar_stream, gpu_run, oracle_run, profile_rel_l2, rel_l2
+from gpu_helpers import BW, F0, dispersed_pulsar_stream, gpu_run, oracle_run, profile_rel_l2, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -183,3 +183,33 @@ def test_abi_errors_leave_state_untouched():
         assert P.pond_plan_query(h)["samples_in"] == 0
     finally:
         P.pond_plan_destroy(h)
+
+
+@pytest.mark.parametrize("alpha", [0.25, 1.0])
+def test_taper_parity(alpha):
+    """The optional Tukey taper of the inverse filter, every form, against
+    the oracle with the same taper; a taper can only be set on a new or
+    flushed plan."""
+    import paper_1503_01405_amd as P
+    nfft, dm, nbins, period, nsamp = 1 << 19, 3.1, 256, 3.3e-2, 1_500_007
+    print(f"case: taper alpha={alpha} nfft=2^19 dm={dm}", flush=True)
+    iq = dispersed_pulsar_stream(13, nsamp, dm, period=period)
+    oprof, oser, r = oracle_run(iq, dm, nfft, nbins, period, taper=alpha)
+    for precision in FORMS:
+        prof, ser = gpu_run(iq, dm, nfft, nbins, period, precision=precision, taper=alpha)
+        ep, es = profile_rel_l2(prof, oprof), rel_l2(ser, oser)
+        tp, ts = profile_tol(precision, r["n_out"], 0, nbins), TOL[precision][1]
+        print(f"{precision}: profile rel-L2 {ep:.3e} (tol {tp:.1e}) series rel-L2 {es:.3e}")
+        assert ep <= tp and es <= ts, precision
+    import torch
+    x = torch.from_numpy(iq[:2 * (1 << 20)]).to("cuda")
+    plan = P.Plan(F0, BW, dm, nfft, nbins, period)
+    plan.process(x)
+    with pytest.raises(P.PondError):
+        P.pond_plan_set_taper(plan.handle, 0.5)
+    plan.flush(device=x.device)
+    P.pond_plan_set_taper(plan.handle, 0.5)
+    with pytest.raises(P.PondError):
+        P.pond_plan_set_taper(plan.handle, 1.5)
+    torch.cuda.synchronize()
+    plan.close()

@@ -302,3 +302,47 @@ def test_dm0_processing_leaves_the_dispersion_smear(config0_iq):
     w_good = np.sum(good - base > pk_good / 2)
     w_raw = np.sum(raw - base > pk_raw / 2)
     assert w_raw > 2.5 * w_good
+
+
+# ---------------------------------------------------------------- taper (C4)
+def test_taper_window_shape():
+    """Tukey window over [-bw/2, bw/2]: 1 in the flat part, 1/2 at the middle
+    of each edge, 0 at the band edge, even in f, non-increasing in |f|;
+    alpha = 0 is the unit taper."""
+    bw, alpha = 16.0, 0.3
+    f = np.linspace(-8.0, 8.0, 4001)
+    w = O.taper(f, bw, alpha)
+    assert np.all(O.taper(f, bw, 0.0) == 1.0)
+    assert O.taper(np.array([0.0]), bw, alpha)[0] == 1.0
+    assert np.allclose(O.taper(np.array([-8.0, 8.0]), bw, alpha), 0.0, atol=1e-15)
+    mid = (1 - alpha / 2) * bw / 2
+    assert np.allclose(O.taper(np.array([-mid, mid]), bw, alpha), 0.5)
+    assert np.allclose(w, w[::-1])
+    half = w[f >= 0]
+    assert np.all(np.diff(half) <= 1e-15) and np.all((w >= 0) & (w <= 1))
+
+
+def test_full_band_taper_is_three_tap_filter():
+    """alpha = 1 makes the window 1/2 + cos(2 pi k / N)/2 on the FFT grid,
+    whose inverse transform is the three taps 1/4, 1/2, 1/4: at DM 0 an
+    impulse comes out as exactly that, and a white stream keeps 3/8 of its
+    power (sum of squared taps)."""
+    n = 1 << 10
+    x = np.zeros(n, dtype=np.complex128)
+    x[300] = 1.0
+    y, _ = O.dedisperse(x, 326.5, 16.0, 0.0, n, taper_alpha=1.0)
+    want = np.zeros(n)
+    want[299:302] = [0.25, 0.5, 0.25]
+    assert np.allclose(y.real, want, atol=1e-12) and np.allclose(y.imag, 0, atol=1e-12)
+    rng = np.random.default_rng(3)
+    z = rng.normal(size=n) + 1j * rng.normal(size=n)
+    y, _ = O.dedisperse(z, 326.5, 16.0, 0.0, n, taper_alpha=1.0)
+    brute = 0.25 * np.roll(z, 1) + 0.5 * z + 0.25 * np.roll(z, -1)
+    assert np.allclose(y, brute, atol=1e-12)
+
+
+def test_unit_taper_is_the_default():
+    iq = synth.white_stream_int8(8, 20000)
+    a = O.run(iq, 326.5, 16.0, 0.01, 1 << 12, 32, 1e-3)
+    b = O.run(iq, 326.5, 16.0, 0.01, 1 << 12, 32, 1e-3, taper_alpha=0.0)
+    assert np.array_equal(a["profiles"], b["profiles"]) and np.array_equal(a["series"], b["series"])
