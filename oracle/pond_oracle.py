@@ -399,3 +399,71 @@ def profile_snr(profile, on_frac=0.1):
         mask[(k + d) % n] = False
     off = p[mask]
     return float((p[k] - np.median(off)) / off.std())
+
+
+# --------------------------------------------------------------------------
+# Incoherent dedispersion with an FFT filterbank (AID mode, Sec. 3.4 and
+# Sec. 3.4.1): spectra of consecutive blocks, squared and added to the
+# wanted time resolution, each channel shifted by its dispersive delay
+# (Eq. (3)) and the channels summed, then folded.  Readings:
+#   A1  input as the coherent mode: single-pol complex int8 I/Q (C14); the
+#       adding of the two telescope halves is therefore absent.
+#   A2  channel c of an nchan-point transform is baseband frequency
+#       fftfreq(nchan) * bw, i.e. sky f0 + f_c (upper side, as C2); square
+#       window, no overlap.
+#   A3  delays by the constant of C1, referred to f0 like the coherent
+#       outputs: dt_c = (DM / 2.41e-4) (f_c^-2 - f0^-2) s, rounded to the
+#       nearest integrated sample: d_c = floor(dt_c / t_s + 1/2),
+#       t_s = nchan * nint / fs.
+#   A4  output m (m >= 0) is the sum over c of channel c at integrated
+#       sample m + d_c - d_min; only outputs every channel covers exist.
+#       Its time (that of its f0 channel, d = 0) is (m - d_min) t_s from the
+#       stream start, and its fold phase x = (m - d_min) nchan nint / (P fs)
+#       (float64), binned as C9.
+# --------------------------------------------------------------------------
+def aid_filterbank(iq, nchan, nint):
+    """Integrated power spectra F[t, c] (float64): the sum over nint
+    consecutive spectra of |FFT_nchan(block)|^2, blocks back to back."""
+    x = unpack(iq)
+    t = x.size // (nchan * nint)
+    blocks = x[:t * nchan * nint].reshape(t * nint, nchan)
+    p = np.abs(sfft.fft(blocks, axis=1)) ** 2
+    return p.reshape(t, nint, nchan).sum(axis=1)
+
+
+def aid_delays(f0_mhz, bw_mhz, dm, nchan, nint):
+    """Per-channel delay in integrated samples (reading A3) and t_s."""
+    f = f0_mhz + sfft.fftfreq(nchan, d=1.0 / bw_mhz)
+    ts = nchan * nint / (bw_mhz * 1e6)
+    dt = DM_CONST_S * dm * (1.0 / (f * f) - 1.0 / (f0_mhz * f0_mhz))
+    return np.floor(dt / ts + 0.5).astype(np.int64), ts
+
+
+def aid_dedisperse(F, d):
+    """D[m] = sum_c F[m + d_c - d_min, c] over the outputs every channel
+    covers (reading A4)."""
+    dd = d - d.min()
+    t_out = F.shape[0] - int(dd.max())
+    if t_out <= 0:
+        return np.zeros(0)
+    D = np.zeros(t_out)
+    for c in range(F.shape[1]):
+        D += F[dd[c]:dd[c] + t_out, c]
+    return D
+
+
+def aid_run(iq, f0_mhz, bw_mhz, dm, nchan, nint, nbins, period_s):
+    """The AID path over one stream: dedispersed series and its folded
+    profile (mean per bin)."""
+    F = aid_filterbank(iq, nchan, nint)
+    d, ts = aid_delays(f0_mhz, bw_mhz, dm, nchan, nint)
+    D = aid_dedisperse(F, d)
+    dmin = int(d.min())
+    m = np.arange(D.size)
+    inv_pfs = 1.0 / (period_s * bw_mhz * 1e6)
+    x = (m - dmin).astype(np.float64) * float(nchan * nint) * inv_pfs
+    b = np.minimum(np.floor((x - np.floor(x)) * nbins).astype(np.int64), nbins - 1)
+    sums = np.bincount(b, weights=D, minlength=nbins)
+    cnts = np.bincount(b, minlength=nbins)
+    prof = np.where(cnts > 0, sums / np.maximum(cnts, 1), 0.0)
+    return dict(series=D, profile=prof, counts=cnts, delays=d, d_min=dmin, t_s=ts, filterbank=F)
