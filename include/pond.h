@@ -331,6 +331,44 @@ int32_t pond_server_query(const pond_server* s, int64_t* used_bytes, int64_t* bu
 /* Destroy a server (NULL-safe): waits for and frees every open stream. */
 void pond_server_destroy(pond_server* s);
 
+/*
+ * Incoherent dedispersion with an FFT filterbank (the AID pulsar mode,
+ * Sec. 3.4 / Sec. 3.4.1; Eq. (2) gives its residual smear, Eq. (3) its
+ * per-channel delays).  Input as above (complex int8 I/Q, device).  The
+ * stream is cut into back-to-back blocks of nchan samples; each block's
+ * nchan-point spectrum is squared, nint consecutive spectra are summed
+ * (integrated sample t_s = nchan nint / fs); channel c (baseband frequency
+ * fftfreq(nchan) * bw, sky f0 + f) is delayed by
+ * d_c = floor((1/2.41e-4) DM (f^-2 - f0^-2) / t_s + 1/2) integrated
+ * samples, referred to f0; dedispersed output m (m >= 0) is the sum over
+ * channels of channel c's sample m + d_c - d_min, and exists where every
+ * channel covers it.  Output m has time (m - d_min) t_s and is folded with
+ * x = (m - d_min) nchan nint / (P fs) as the coherent mode's outputs.
+ */
+typedef struct pond_aid pond_aid;
+
+/* nchan: power of two in [64, 4096]; nint in [1, 65536]; other arguments as
+   pond_plan_create.  NULL on invalid arguments or device failure. */
+pond_aid* pond_aid_create(double f0_mhz, double bw_mhz, double dm, int32_t nchan,
+                          int32_t nint, int32_t nbins, double period_s);
+
+/* For a segment of nsamp samples: integrated spectra, dedispersed outputs,
+   the smallest and largest channel delays and t_s (any pointer may be
+   NULL).  Host arithmetic only. */
+int32_t pond_aid_geometry(const pond_aid* a, int64_t nsamp, int64_t* n_spectra,
+                          int64_t* n_series, int32_t* d_min, int32_t* d_max, double* t_s);
+
+/* Process one resident segment (nothing is carried between calls): the
+   folded profile (nbins float32 means, device) and, if series is not NULL,
+   the dedispersed series (device, capacity series_cap >= n_series).
+   Returns n_series or POND_EINVAL / POND_ENOMEM / POND_EDEVICE.
+   Asynchronous on hip_stream. */
+int64_t pond_aid_run(pond_aid* a, const int8_t* iq, int64_t nsamp, float* profile,
+                     float* series, int64_t series_cap, void* hip_stream);
+
+/* Destroy (NULL-safe); waits for the last call's work. */
+void pond_aid_destroy(pond_aid* a);
+
 /* Static text for a return code. */
 const char* pond_strerror(int64_t code);
 

@@ -12,4 +12,5 @@ from .pond import (POND_EBUSY, POND_EDEVICE, POND_EINVAL, POND_ENOMEM, FORMS, PO
                    pond_search_run, pond_search_trial, pond_server_close, pond_server_create,
                    pond_server_destroy, pond_server_open, pond_server_poll, pond_server_query,
                    pond_server_stream_bytes, pond_server_submit, pond_server_take_profiles,
-                   pond_stream_desc, pond_completion, _desc as stream_desc)
+                   pond_stream_desc, pond_completion, _desc as stream_desc, pond_aid_create,
+                   pond_aid_destroy, pond_aid_geometry, pond_aid_run)

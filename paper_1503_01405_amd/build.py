@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpond.so")
 
-SOURCES = ["pond_kernels.hip", "pond_api.cpp", "pond_search.cpp", "pond_serve.cpp"]
+SOURCES = ["pond_kernels.hip", "pond_api.cpp", "pond_search.cpp", "pond_serve.cpp", "pond_aid.cpp"]
 HEADERS = ["pond_fft.hpp", "pond_internal.hpp"]
 
 # -ffp-contract=off: no implicit fused multiply-adds, so the float64 fold

@@ -80,6 +80,27 @@ struct K3Args {
     uint32_t* status;
 };
 
+// Incoherent (AID) mode: filterbank, then channel shift-and-sum and fold.
+struct AidArgs {
+    const int8_t* iq;       // nspec * nint * nchan complex int8 samples
+    int64_t nspec;          // integrated spectra (output times of the filterbank)
+    int32_t nint;           // spectra summed per output time
+    int32_t nchan;          // channels (FFT length)
+    const float2* tw;       // exp(-2 pi i t / nchan), t < nchan
+    float* F;               // [nchan][nspec] integrated powers, channel-major
+    const int32_t* dd;      // [nchan] delay minus the smallest delay (integrated samples)
+    int32_t d_min;          // smallest delay
+    int64_t nout;           // dedispersed outputs
+    float* series;          // [nout] or NULL
+    int32_t nbins;
+    double inv_pfs;         // 1 / (period * fs)
+    uint64_t* part_sum;     // [grid][nbins]
+    uint32_t* part_cnt;
+    uint32_t* status;
+};
+hipError_t launch_aid_filterbank(int log2c, const AidArgs& a, hipStream_t s);
+hipError_t launch_aid_dedisperse_fold(const AidArgs& a, int grid, hipStream_t s);
+
 // Launchers; each returns the HIP error of the launch.
 hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s);
 hipError_t launch_k2(int prec, int mode, int log2n1, const K2Args& a, hipStream_t s);

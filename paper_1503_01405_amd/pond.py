@@ -37,6 +37,7 @@ EXPORTS = (
     "pond_server_create", "pond_server_stream_bytes", "pond_server_open", "pond_server_submit",
     "pond_server_poll", "pond_server_take_profiles", "pond_server_close", "pond_server_query",
     "pond_server_destroy",
+    "pond_aid_create", "pond_aid_geometry", "pond_aid_run", "pond_aid_destroy",
 )
 KERNEL_NAMES = ("k1_unpack_colfft", "k2_row", "k3_colinv_detect_fold", "fold_reduce", "fold_finalize")
 
@@ -143,6 +144,15 @@ def _load():
     lib.pond_server_query.restype = i32
     lib.pond_server_destroy.argtypes = [P]
     lib.pond_server_destroy.restype = None
+    lib.pond_aid_create.argtypes = [dbl, dbl, dbl, i32, i32, i32, dbl]
+    lib.pond_aid_create.restype = P
+    lib.pond_aid_geometry.argtypes = [P, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    lib.pond_aid_geometry.restype = i32
+    lib.pond_aid_run.argtypes = [P, P, i64, P, P, i64, P]
+    lib.pond_aid_run.restype = i64
+    lib.pond_aid_destroy.argtypes = [P]
+    lib.pond_aid_destroy.restype = None
     lib.pond_strerror.argtypes = [i64]
     lib.pond_strerror.restype = ctypes.c_char_p
     return lib
@@ -331,6 +341,34 @@ def pond_server_query(server):
 
 def pond_server_destroy(server):
     _lib.pond_server_destroy(server)
+
+
+def pond_aid_create(f0_mhz, bw_mhz, dm, nchan, nint, nbins, period_s):
+    h = _lib.pond_aid_create(float(f0_mhz), float(bw_mhz), float(dm), int(nchan), int(nint), int(nbins),
+                             float(period_s))
+    if not h:
+        raise PondError(POND_EINVAL, "pond_aid_create")
+    return h
+
+
+def pond_aid_geometry(aid, nsamp):
+    ns, no = ctypes.c_int64(0), ctypes.c_int64(0)
+    dmin, dmax = ctypes.c_int32(0), ctypes.c_int32(0)
+    ts = ctypes.c_double(0)
+    r = _lib.pond_aid_geometry(aid, int(nsamp), ctypes.byref(ns), ctypes.byref(no), ctypes.byref(dmin),
+                               ctypes.byref(dmax), ctypes.byref(ts))
+    if r != POND_OK:
+        raise PondError(r, "pond_aid_geometry")
+    return dict(n_spectra=ns.value, n_series=no.value, d_min=dmin.value, d_max=dmax.value, t_s=ts.value)
+
+
+def pond_aid_run(aid, iq, nsamp, profile, series=None, series_cap=0, stream=None):
+    return _lib.pond_aid_run(aid, _ptr(iq), int(nsamp), _ptr(profile), _ptr(series), int(series_cap),
+                             _stream(stream))
+
+
+def pond_aid_destroy(aid):
+    _lib.pond_aid_destroy(aid)
 
 
 # ------------------------------------------------------- convenience class
