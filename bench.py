@@ -21,6 +21,10 @@ log-uniform 0.5-200, period uniform 2 ms-2 s, FFT length by smear between
 p50/p99 block latency; a saturated run (every block queued at once) gives
 the aggregate throughput and real-time factor.
 
+`--workload aid` times the incoherent (filterbank) mode on the same 60 s
+stream: 1024 channels, 4 spectra per integrated sample (256 us), channel
+delays of Eq. (3) at DM 50, 1024 bins.
+
 `--workload search` times the batched DM-trial search instead: a 10 s
 stream of the same generator (160,000,000 samples) folded at 128 trial DMs
 0-63.5 in steps of 0.5 into 512 bins, FFT length per trial by smear
@@ -444,6 +448,76 @@ def main_serve(args):
     print(json.dumps(out), flush=True)
 
 
+AID_NCHAN, AID_NINT = 1024, 4
+AID_METRIC = "AID Msamples/s filterbank+incoherent dedispersion+fold at DM 50 (1024 ch, 256 us)"
+
+
+def aid_cpu_baseline(iq_np):
+    """The oracle's AID path, as it stands, on the first 2^28 samples."""
+    import oracle as O
+    n = 1 << 28
+    t0 = time.perf_counter()
+    O.aid_run(iq_np[:2 * n], F0, BW, DM, AID_NCHAN, AID_NINT, NBINS, PERIOD)
+    dt = time.perf_counter() - t0
+    return dict(value=round(n / dt / 1e6, 3), unit="Msamples/s", cores=1, kind="oracle",
+                sample=f"first {n} samples ({n / 16e6:.1f} s) of the same stream, {dt:.1f} s of CPU work (numpy FFTs, one thread)")
+
+
+def main_aid(args):
+    import torch
+    import paper_1503_01405_amd as P
+    import synth
+
+    t = time.perf_counter()
+    iq = synth.pulsed_stream_int8(SEED, NSAMP)
+    log(f"generated {NSAMP} samples in {time.perf_counter() - t:.1f} s")
+    x = torch.from_numpy(iq).to("cuda:0")
+    h = P.pond_aid_create(F0, BW, DM, AID_NCHAN, AID_NINT, NBINS, PERIOD)
+    geo = P.pond_aid_geometry(h, NSAMP)
+    prof = torch.empty(NBINS, device="cuda:0")
+    ser = torch.empty(geo["n_series"], device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        n = P.pond_aid_run(h, x, NSAMP, prof, ser, ser.numel(), stream)
+        if n != geo["n_series"]:
+            raise RuntimeError(f"pond_aid_run returned {n}")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = max((time.perf_counter() - t0) / args.steps * 1e3, ev0.elapsed_time(ev1) / args.steps)
+    P.pond_aid_destroy(h)
+    value = NSAMP / (ms / 1e3) / 1e6
+    # bytes the two passes must move: int8 input, the integrated
+    # filterbank written and read once, the series written
+    algo = NSAMP * 2 + 2 * geo["n_spectra"] * AID_NCHAN * 4 + geo["n_series"] * 4
+    out = {
+        "metric": AID_METRIC, "value": round(value, 1), "unit": "Msamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "60 s 16 Msps int8 I/Q at 326.5 MHz, DM 50, 1024-channel filterbank, 4 spectra per "
+                               "sample, 1024 bins", "nsamp": NSAMP, "nchan": AID_NCHAN, "nint": AID_NINT,
+                   "n_series": geo["n_series"], "d_min": geo["d_min"], "d_max": geo["d_max"]},
+        "xrealtime": round(value / 16.0, 1),
+        "roofline": dict(bound="hbm", kernel="whole step (both passes)", achieved=round(algo / (ms / 1e3) / 1e9, 1),
+                         peak=HBM_PEAK_GBS, unit="GB/s", frac=round(algo / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                         traffic=None, algorithmic_bytes_per_step=algo),
+    }
+    if not args.no_cpu_baseline:
+        del x
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = aid_cpu_baseline(iq)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,7 +528,7 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="also time the step captured once into a HIP graph and replayed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["dm50", "search", "serve"], default="dm50",
+    ap.add_argument("--workload", choices=["dm50", "search", "serve", "aid"], default="dm50",
                     help="dm50: the single-DM production stream (default); search: the 128-trial DM search; "
                          "serve: the 16-stream serving loop")
     ap.add_argument("--serve-seconds", type=int, default=8, help="paced serving run length (s)")
@@ -473,6 +547,9 @@ def main():
         return
     if args.workload == "serve":
         main_serve(args)
+        return
+    if args.workload == "aid":
+        main_aid(args)
         return
 
     import numpy as np
