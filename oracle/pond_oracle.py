@@ -467,3 +467,102 @@ def aid_run(iq, f0_mhz, bw_mhz, dm, nchan, nint, nbins, period_s):
     cnts = np.bincount(b, minlength=nbins)
     prof = np.where(cnts > 0, sums / np.maximum(cnts, 1), 0.0)
     return dict(series=D, profile=prof, counts=cnts, delays=d, d_min=dmin, t_s=ts, filterbank=F)
+
+
+# --------------------------------------------------------------------------
+# The paper's own input path: two telescope halves, real-sampled (Sec. 2:
+# two 8-bit ADC channels, the 16 MHz band Nyquist-sampled at 32 Msps each),
+# added in phase (the AIP kernel, Sec. 3.7) and dedispersed through a
+# real-to-complex transform.  Readings:
+#   R1  input bytes interleave the channels, A0 B0 A1 B1 ...; adding in
+#       phase is the plain sum x[n] = A[n] + B[n] (the halves arrive
+#       phased; the paper gives no further step).
+#   R2  x is sampled at fs_r = 2 bw; real-FFT bin k (0 <= k <= N_r/2) is
+#       baseband fb = k fs_r / N_r.  Upper sideband: sky f0 - bw/2 + fb;
+#       lower sideband (the paper's 38 MHz mix of a 22-38 MHz IF): sky
+#       f0 + bw/2 - fb.  With f the offset from f0, bin k is multiplied by
+#       exp(-2 pi i turns(f)) (upper) or exp(+2 pi i turns(f)) (lower: the
+#       band is mirrored, so its phase is conjugated), times the taper of
+#       C4; the DC and Nyquist bins keep only the real part of that factor
+#       (the inverse real transform has no imaginary part there).
+#   R3  geometry in complex-equivalent units: a block of N_r = 2 N real
+#       samples, with N, n_front and hop of the complex plan of the same
+#       bandwidth (plan_geometry(f0, bw, dm, N)), doubled: the real-rate
+#       smear never exceeds twice the complex-rate one.
+#   R4  detection y[n]^2 of the real dedispersed voltage; series sums of
+#       decim real samples; fold phase of real output r is
+#       (r + 2 n_front) / (P fs_r).
+# --------------------------------------------------------------------------
+def aip(raw):
+    """Adding in phase (R1): interleaved int8 A0 B0 A1 B1 ... -> A + B, float64."""
+    raw = np.asarray(raw)
+    return raw[0::2].astype(np.float64) + raw[1::2].astype(np.float64)
+
+
+def real_chirp(nfft_r, f0_mhz, bw_mhz, dm, sideband, taper_alpha=0.0):
+    """Multiplier of the real-FFT bins 0..nfft_r/2 (reading R2)."""
+    fb = np.arange(nfft_r // 2 + 1) * (2.0 * bw_mhz / nfft_r)
+    if sideband == "usb":
+        f = fb - bw_mhz / 2
+        m = np.exp(-2j * np.pi * chirp_turns(f, f0_mhz, dm))
+    elif sideband == "lsb":
+        f = bw_mhz / 2 - fb
+        m = np.exp(+2j * np.pi * chirp_turns(f, f0_mhz, dm))
+    else:
+        raise ValueError("sideband must be 'usb' or 'lsb'")
+    m = m * taper(f, bw_mhz, taper_alpha)
+    m[0] = m[0].real
+    m[-1] = m[-1].real
+    return m
+
+
+def run_real(raw, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, sideband="lsb",
+             subint_nsamp=0, decim=32, taper_alpha=0.0, keep_power=False):
+    """The real two-channel path (R1-R4) over one stream: blocks of 2*nfft
+    real samples, every fully covered block; subint_nsamp and decim in real
+    samples.  Same result dict as `run`, with outputs counted in real
+    samples."""
+    g = plan_geometry(f0_mhz, bw_mhz, dm, nfft)
+    n_r, hop_r, nf_r = 2 * nfft, 2 * g["hop"], 2 * g["n_front"]
+    fs_r = 2.0 * bw_mhz * 1e6
+    x = aip(raw)
+    nb = n_blocks(x.size, n_r, hop_r)
+    n_out = nb * hop_r
+    m = real_chirp(n_r, f0_mhz, bw_mhz, dm, sideband, taper_alpha)
+    p = np.empty(n_out)
+    for b in range(nb):
+        y = sfft.irfft(sfft.rfft(x[b * hop_r:b * hop_r + n_r]) * m, n=n_r)
+        p[b * hop_r:(b + 1) * hop_r] = y[nf_r:nf_r + hop_r] ** 2
+    series = decimate(p, decim)
+    ns_total = (max(n_out - 1, 0) // subint_nsamp + 1) if (subint_nsamp > 0 and n_out) else (1 if n_out else 0)
+    sums = np.zeros((ns_total, nbins))
+    cnts = np.zeros((ns_total, nbins), dtype=np.int64)
+    if n_out:
+        s, c, s0 = fold(p, 0, nf_r, period_s, fs_r, nbins, subint_nsamp)
+        sums[s0:s0 + s.shape[0]] += s
+        cnts[s0:s0 + c.shape[0]] += c
+    complete = (n_out // subint_nsamp) if subint_nsamp > 0 else 0
+    return dict(geometry=dict(g, n_r=n_r, hop_r=hop_r, n_front_r=nf_r, fs_r=fs_r), n_out=n_out,
+                series=series, sums=sums, cnts=cnts, profiles=profiles_from(sums, cnts),
+                complete=complete, power=p if keep_power else None)
+
+
+def disperse_real(x, f0_mhz, bw_mhz, dm, nfft_r, sideband="lsb"):
+    """The real-path forward model: the ISM response applied to a real
+    stream by overlap-save (the conjugate of real_chirp's phase); x covers
+    2*pad_lo samples before and 2*pad_hi after the part kept."""
+    pad_lo, pad_hi = disperse_pads(f0_mhz, bw_mhz, dm)
+    lo, hi = 2 * pad_lo, 2 * pad_hi
+    hop = nfft_r - lo - hi
+    if hop <= 0:
+        raise ValueError("nfft too short to disperse")
+    n_keep = x.size - lo - hi
+    h = np.conj(real_chirp(nfft_r, f0_mhz, bw_mhz, dm, sideband))
+    nb = -(-n_keep // hop)
+    xp = np.zeros(nb * hop + lo + hi + nfft_r)
+    xp[:x.size] = x
+    out = np.empty(nb * hop)
+    for b in range(nb):
+        y = sfft.irfft(sfft.rfft(xp[b * hop:b * hop + nfft_r]) * h, n=nfft_r)
+        out[b * hop:(b + 1) * hop] = y[lo:lo + hop]
+    return out[:n_keep]
