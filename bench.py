@@ -25,6 +25,11 @@ the aggregate throughput and real-time factor.
 stream: 1024 channels, 4 spectra per integrated sample (256 us), channel
 delays of Eq. (3) at DM 50, 1024 bins.
 
+`--workload real` times the real two-channel input path (channels A and B
+added in phase, packed real-to-complex transforms): 60 s of int8 A/B pairs
+at 32 Msps real (1,920,000,000 real samples, 3.84 GB resident), DM 50,
+real blocks of 2^24 (packed 2^23), 1 us series, 1024 bins per 10 s.
+
 `--workload search` times the batched DM-trial search instead: a 10 s
 stream of the same generator (160,000,000 samples) folded at 128 trial DMs
 0-63.5 in steps of 0.5 into 512 bins, FFT length per trial by smear
@@ -518,6 +523,125 @@ def main_aid(args):
     print(json.dumps(out), flush=True)
 
 
+REAL_NSAMP = 2 * NSAMP          # real samples, 60 s at 32 Msps
+REAL_NFFT = 2 * NFFT            # real block length
+REAL_SUBINT = 2 * SUBINT        # 10 s of real outputs
+REAL_DECIM = 2 * DECIM          # 1 us
+REAL_METRIC = "Msamples/s (real) dedispersed+folded at DM 50, real two-channel input"
+
+
+def real_algorithmic_bytes(kernel, blocks, elem, n, hop_e):
+    """Per kernel slot of the real path, for `blocks` blocks of n packed
+    elements: int8 A/B pairs (4 B per element) read once; the middle pass
+    (forward rows, split + filter, inverse rows) reads and writes the block
+    three times; the inverse columns read it once and write the series."""
+    if kernel == "k1_unpack_colfft":
+        return blocks * n * (4 + elem)
+    if kernel == "k2_row":
+        return blocks * n * 6 * elem
+    if kernel == "k3_colinv_detect_fold":
+        return blocks * (n * elem + hop_e // 16 * 4)
+    return 0
+
+
+def real_cpu_baseline(raw_np, sideband, nblocks):
+    """The oracle's real path, as it stands, on the first `nblocks` blocks."""
+    import oracle as O
+    g = O.plan_geometry(F0, BW, DM, NFFT)
+    n = 2 * g["hop"] * (nblocks - 1) + REAL_NFFT
+    t0 = time.perf_counter()
+    r = O.run_real(raw_np[:2 * n], F0, BW, DM, NFFT, NBINS, PERIOD, sideband=sideband, decim=REAL_DECIM)
+    dt = time.perf_counter() - t0
+    return dict(value=round(r["n_out"] / dt / 1e6, 3), unit="Msamples/s", cores=1, kind="oracle",
+                sample=f"first {nblocks} blocks ({n} real samples) of the same stream, {dt:.1f} s of CPU work "
+                       f"(scipy real FFTs, one thread)")
+
+
+def main_real(args):
+    import torch
+    import paper_1503_01405_amd as P
+    import synth
+
+    t = time.perf_counter()
+    # A and B: the I and Q draws of the generator at 32 Msps, each with half
+    # the noise power, so that A + B has the complex recipe's component power
+    raw = synth.pulsed_stream_int8(SEED, REAL_NSAMP, fs_hz=2 * BW * 1e6, sigma=synth.SIGMA / 2 ** 0.5)
+    log(f"generated {REAL_NSAMP} real samples in {time.perf_counter() - t:.1f} s")
+    x = torch.from_numpy(raw).to("cuda:0")
+    forms = [f for f in args.forms.split(",") if f in ("fp32", "mixed_valu")] or ["fp32", "mixed_valu"]
+    res = {}
+    for f in forms:
+        plan = P.Plan(F0, BW, DM, REAL_NFFT, NBINS, PERIOD, precision=f, subint_nsamp=REAL_SUBINT,
+                      decim=REAL_DECIM, sideband="lsb")
+        info = plan.info()
+        nprof, nout = P.pond_real_expect(plan.handle, REAL_NSAMP, REAL_SUBINT)
+        prof = torch.empty((nprof + 1, NBINS), dtype=torch.float32, device=x.device)
+        ser = torch.empty(nout // REAL_DECIM, dtype=torch.float32, device=x.device)
+        stream = torch.cuda.current_stream()
+
+        def step():
+            r, ns = P.pond_real_dedisperse(plan.handle, x, REAL_NSAMP, REAL_SUBINT, prof, nprof, REAL_DECIM,
+                                           ser, ser.numel(), stream)
+            if r != nprof or ns != ser.numel():
+                raise RuntimeError(f"unexpected call result {r} {ns}")
+            r, _ = P.pond_real_dedisperse(plan.handle, None, 0, REAL_SUBINT, prof[nprof:], 1, REAL_DECIM,
+                                          None, 0, stream)
+            if r != 1:
+                raise RuntimeError(f"flush returned {r}")
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        P.pond_plan_set_timing(plan.handle, True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = max((time.perf_counter() - t0) / args.steps * 1e3, ev0.elapsed_time(ev1) / args.steps)
+        kt = P.pond_plan_kernel_times(plan.handle)
+        plan.close()
+        res[f] = dict(ms=ms, outputs=nout, kernels=kt, info=info)
+        log(f"{f}: {ms:.3f} ms/step  kernels {kt}")
+    head = "mixed_valu" if "mixed_valu" in res else forms[0]
+    h = res[head]
+    value = h["outputs"] / (h["ms"] / 1e3) / 1e6
+    elem = 8 if head == "fp32" else 4
+    kt = h["kernels"]
+    dom = max(kt, key=lambda k: kt[k][0])
+    ms, launches, blocks = kt[dom]
+    n_e, hop_e = REAL_NFFT // 2, h["info"]["hop"] // 2
+    algo = real_algorithmic_bytes(dom, blocks, elem, n_e, hop_e)
+    achieved = algo / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    out = {
+        "metric": REAL_METRIC, "value": round(value, 2), "unit": "Msamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(h["ms"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"mixed_valu": "f16-storage/f32", "fp32": "f32"}[head], "data": "synthetic",
+        "config": {"workload": "60 s of 32 Msps real int8 A/B channel pairs at 326.5 MHz (lower sideband), DM 50, "
+                               "real nfft 2^24, 1024 bins per 10 s subint, 1 us series",
+                   "nsamp_real": REAL_NSAMP, "nfft_real": REAL_NFFT, "dm": DM, "nbins": NBINS,
+                   "period_s": PERIOD, "subint_real": REAL_SUBINT, "decim_real": REAL_DECIM,
+                   "valid_outputs_real": h["outputs"], "form": head},
+        "xrealtime": round(value / 32.0, 1),
+        "forms": {f: dict(value=round(r["outputs"] / (r["ms"] / 1e3) / 1e6, 2), ms_per_step=round(r["ms"], 3),
+                          kernel_ms_per_step={k: round(kv[0] / args.steps, 4) for k, kv in r["kernels"].items()})
+                  for f, r in res.items()},
+        "roofline": dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                         algorithmic_bytes_per_launch=int(algo / max(launches, 1)),
+                         avg_launch_us=round(ms / max(launches, 1) * 1e3, 2)),
+    }
+    if not args.no_cpu_baseline:
+        del x
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = real_cpu_baseline(raw, "lsb", args.cpu_blocks)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -528,9 +652,10 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="also time the step captured once into a HIP graph and replayed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["dm50", "search", "serve", "aid"], default="dm50",
+    ap.add_argument("--workload", choices=["dm50", "search", "serve", "aid", "real"], default="dm50",
                     help="dm50: the single-DM production stream (default); search: the 128-trial DM search; "
-                         "serve: the 16-stream serving loop")
+                         "serve: the 16-stream serving loop; aid: the filterbank mode; real: the real "
+                         "two-channel input path")
     ap.add_argument("--serve-seconds", type=int, default=8, help="paced serving run length (s)")
     ap.add_argument("--serve-burst-blocks", type=int, default=8, help="1 s blocks per stream in the saturated run")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -550,6 +675,9 @@ def main():
         return
     if args.workload == "aid":
         main_aid(args)
+        return
+    if args.workload == "real":
+        main_real(args)
         return
 
     import numpy as np

@@ -92,8 +92,16 @@ typedef struct pond_info {
     int32_t nbins;
     int32_t precision;     /* POND_FP32, POND_MIXED, POND_MIXED_VALU or POND_HALF  */
     uint32_t status;       /* POND_STATUS_* bits (read synchronously)              */
-    int32_t reserved;
+    int32_t input_kind;    /* POND_INPUT_*                                         */
 } pond_info;
+
+/* Input kinds of a plan (pond_info.input_kind).  For a real-input plan the
+   counts of pond_info are in real samples (nfft, n_front, discard, hop,
+   samples_in, outputs_done), fs_hz is the real sample rate 2 bw, and
+   n1 * n2 = nfft / 2 factors the packed transform. */
+#define POND_INPUT_COMPLEX   0
+#define POND_INPUT_REAL_LSB  1
+#define POND_INPUT_REAL_USB  2
 
 /*
  * Create a plan (plain FP32 form).
@@ -216,6 +224,60 @@ int32_t pond_plan_kernel_times(pond_plan* p, pond_kernel_times* out);
 
 /* Destroy a plan (NULL-safe); waits for the plan's pending work. */
 void pond_plan_destroy(pond_plan* p);
+
+/*
+ * Real two-channel input (the paper's own receiver path, Sec. 3.1 and
+ * Sec. 3.2: two real-sampled channels A and B of one polarisation, added
+ * in phase, x[r] = A[r] + B[r], at the real sample rate 2 bw).
+ *   raw: device, int8 interleaved A0 B0 A1 B1 ..., 2 bytes per real
+ *        sample, 4-byte aligned.
+ * Block b covers real samples [b*hop, b*hop + nfft) (nfft, hop, n_front in
+ * real samples: twice the complex plan's at the same f0, bw, dm and
+ * nfft/2).  Its real spectrum bins k = 0..nfft/2 (baseband k bw/(nfft/2),
+ * from 0 to bw) are multiplied by the inverse ISM response of Eq. (4) at
+ * sky frequency f0 + f:
+ *   POND_USB  f = k bw/(nfft/2) - bw/2,  factor exp(-2 pi i turns(f))
+ *   POND_LSB  f = bw/2 - k bw/(nfft/2),  factor exp(+2 pi i turns(f))
+ *             (the lower sideband runs backwards, so the phase is conjugated)
+ * with turns(f) = dm f^2 / (2.41e-10 f0^2 (f0 + f)) in float64 reduced mod
+ * 1 turn, times the taper; the factors of bins 0 and nfft/2 keep only their
+ * real part.  The inverse real transform (1/nfft) gives the dedispersed
+ * real voltage y; the detected output of real sample r is y[r]^2 (r =
+ * b*hop + j, j in [0, hop), input sample r + n_front).  Series groups sum
+ * decim consecutive outputs; the fold takes x = (r + n_front) / (P 2 bw)
+ * and sub-integrations of S real samples, as above.
+ * Computed as a packed complex transform of length nfft/2 (element m =
+ * x[2m] + i x[2m+1]): forward, split into the real transform's bins,
+ * filter, recombine, inverse.
+ */
+#define POND_LSB 0
+#define POND_USB 1
+
+/* nfft: real block length, a power of two in [2^11, 2^25]; precision
+   POND_FP32 or POND_MIXED_VALU; sideband POND_LSB or POND_USB; the rest as
+   pond_plan_create_ex.  NULL on failure (pond_create_status()). */
+pond_plan* pond_real_plan_create(double f0_mhz, double bw_mhz, double dm, int64_t nfft,
+                                 int32_t nbins, double period_s, int32_t precision,
+                                 int32_t max_batch, int32_t sideband);
+
+/*
+ * Append nsamp real samples (raw: device, 2*nsamp int8 A/B pairs; nsamp
+ * even) and fold every newly completed output, as pond_dedisperse_series:
+ * subint_nsamp (even, fixed for the stream) and decim (2, 4, 8, 16 or 32;
+ * <= 0 means 32, 1 us at 32 Msps) in real samples; series NULL: fold only.
+ * raw == NULL with nsamp == 0 ends the stream.  Returns the number of
+ * profiles written or an error code; only for real-input plans (the
+ * complex entry points refuse them, and this one refuses complex plans).
+ */
+int64_t pond_real_dedisperse(pond_plan* p, const int8_t* raw, int64_t nsamp,
+                             int64_t subint_nsamp, float* profiles, int64_t max_profiles,
+                             int32_t decim, float* series, int64_t series_cap,
+                             int64_t* n_series_out, void* hip_stream);
+
+/* pond_plan_expect for a real-input plan, in real samples (nsamp and
+   subint_nsamp even). */
+int32_t pond_real_expect(const pond_plan* p, int64_t nsamp, int64_t subint_nsamp,
+                         int64_t* n_profiles, int64_t* n_outputs);
 
 /*
  * DM-trial search (one stream dedispersed and folded at many trial DMs).

@@ -40,6 +40,13 @@ struct pond_plan {
     int32_t nbins = 0, precision = 0;
     int max_batch = 1;
     size_t elem = 8;
+    // Real two-channel input (Sec. 3.1: channels A and B added in phase):
+    // element m packs real samples 2m, 2m+1; every count above is in
+    // elements, the filter and fold in real samples.
+    int32_t kind = POND_INPUT_COMPLEX;
+    int bpe = 2;                // input bytes per element
+    float2* tw4 = nullptr;      // real input: [n2][n1] four-step twiddle
+    float4* rtab = nullptr;     // real input: [nfft + 1] (split twiddle, filter)
 
     void* work = nullptr;
     int8_t* tail[2] = {nullptr, nullptr};
@@ -133,7 +140,7 @@ void free_plan_memory(pond_plan* p) {
     p->marks.clear();
     for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     p->event_pool.clear();
-    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->table, p->htable,
+    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->table, p->htable, p->tw4, p->rtab,
                     p->acc_sum, p->acc_cnt, p->part_sum, p->part_cnt, p->status};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -294,9 +301,24 @@ const char* pond_strerror(int64_t code) {
     }
 }
 
-pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins,
-                               double period_s, int32_t precision, int32_t max_batch) {
+}  // extern "C"
+
+namespace {
+
+// Builds the filter table of the plan's middle pass (for the taper alpha).
+hipError_t build_filter(pond_plan* p, double alpha) {
+    if (p->kind != POND_INPUT_COMPLEX)
+        return launch_real_build_table(p->rtab, p->log2n, p->chirp_a, p->f0, p->bw,
+                                       p->kind == POND_INPUT_REAL_LSB ? 1 : 0, alpha, nullptr);
+    if (p->precision == POND_HALF)
+        return launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
+    return launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
+}
+
+pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins, double period_s,
+                       int32_t precision, int32_t max_batch, int32_t kind) {
     g_create_status = POND_EINVAL;
+    if (kind != POND_INPUT_COMPLEX && precision != POND_FP32 && precision != POND_MIXED_VALU) return nullptr;
     if (!std::isfinite(f0_mhz) || !std::isfinite(bw_mhz) || !std::isfinite(dm) || !std::isfinite(period_s))
         return nullptr;
     if (!(bw_mhz > 0) || !(f0_mhz - bw_mhz / 2 > 0) || !(dm >= 0)) return nullptr;
@@ -346,7 +368,10 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     p->fs = fs;
     p->delta_lo = delta_lo;
     p->delta_hi = delta_hi;
-    p->inv_pfs = 1.0 / (period_s * fs);
+    p->kind = kind;
+    p->bpe = kind == POND_INPUT_COMPLEX ? 2 : 4;
+    // The fold counts real samples at 2 fs on the real path.
+    p->inv_pfs = 1.0 / (period_s * fs * (kind == POND_INPUT_COMPLEX ? 1.0 : 2.0));
     p->chirp_a = dm / (2.41e-10 * f0_mhz * f0_mhz);
     p->df = bw_mhz / (double)nfft;
     p->nfft = nfft;
@@ -374,20 +399,22 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
         if (e == hipSuccess) e = x;
     };
     chk(hipMalloc(&p->work, (size_t)max_batch * (size_t)nfft * p->elem));
-    chk(hipMalloc(reinterpret_cast<void**>(&p->tail[0]), (size_t)nfft * 2));
-    chk(hipMalloc(reinterpret_cast<void**>(&p->tail[1]), (size_t)nfft * 2));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->tail[0]), (size_t)nfft * p->bpe));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->tail[1]), (size_t)nfft * p->bpe));
     const int64_t n1 = (int64_t)1 << p->log2n1, n2 = (int64_t)1 << p->log2n2;
     if (e == hipSuccess) chk(upload(&p->tw1, twiddles(n1, n1, 1)));
     if (e == hipSuccess) chk(upload(&p->tw2, twiddles(n2, n2, 1)));
-    if (precision == POND_HALF) {
-        chk(hipMalloc(&p->htable, (size_t)nfft * 8));
+    if (kind != POND_INPUT_COMPLEX) {
+        chk(hipMalloc(reinterpret_cast<void**>(&p->tw4), (size_t)nfft * sizeof(float2)));
+        chk(hipMalloc(reinterpret_cast<void**>(&p->rtab), (size_t)(nfft + 1) * sizeof(float4)));
         if (e == hipSuccess)
-            chk(launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, 0.0, nullptr));
+            chk(launch_k2_build_split_tables(p->tw4, nullptr, p->log2n1, p->log2n2, 0.0, p->f0, p->df, nullptr));
+    } else if (precision == POND_HALF) {
+        chk(hipMalloc(&p->htable, (size_t)nfft * 8));
     } else {
         chk(hipMalloc(reinterpret_cast<void**>(&p->table), (size_t)nfft * sizeof(float4)));
-        if (e == hipSuccess)
-            chk(launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, 0.0, nullptr));
     }
+    if (e == hipSuccess) chk(build_filter(p, 0.0));
     p->acc_slots = 4;
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_sum), (size_t)p->acc_slots * nbins * 8));
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_cnt), (size_t)p->acc_slots * nbins * 8));
@@ -408,6 +435,24 @@ pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t 
     }
     g_create_status = POND_OK;
     return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins,
+                               double period_s, int32_t precision, int32_t max_batch) {
+    return create_plan(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision, max_batch, POND_INPUT_COMPLEX);
+}
+
+pond_plan* pond_real_plan_create(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins,
+                                 double period_s, int32_t precision, int32_t max_batch, int32_t sideband) {
+    g_create_status = POND_EINVAL;
+    if (sideband != POND_LSB && sideband != POND_USB) return nullptr;
+    if (nfft < 2 || (nfft & 1)) return nullptr;
+    return create_plan(f0_mhz, bw_mhz, dm, nfft / 2, nbins, period_s, precision, max_batch,
+                       sideband == POND_LSB ? POND_INPUT_REAL_LSB : POND_INPUT_REAL_USB);
 }
 
 pond_plan* pond_plan_create(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins,
@@ -436,11 +481,7 @@ int32_t pond_plan_set_taper(pond_plan* p, double alpha) {
         p->sticky = true;
         return POND_EDEVICE;
     }
-    hipError_t e = p->precision == POND_HALF
-                       ? launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha,
-                                                 nullptr)
-                       : launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha,
-                                               nullptr);
+    hipError_t e = build_filter(p, alpha);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -454,16 +495,18 @@ int32_t pond_plan_set_taper(pond_plan* p, double alpha) {
 int32_t pond_plan_query(pond_plan* p, pond_info* out) {
     if (!p || !out) return POND_EINVAL;
     std::memset(out, 0, sizeof(*out));
-    out->nfft = p->nfft;
-    out->n_front = p->n_front;
-    out->discard = p->discard;
-    out->hop = p->hop;
+    const int64_t u = p->kind == POND_INPUT_COMPLEX ? 1 : 2;  // samples per element
+    out->nfft = u * p->nfft;
+    out->n_front = u * p->n_front;
+    out->discard = u * p->discard;
+    out->hop = u * p->hop;
     out->n1 = (int64_t)1 << p->log2n1;
     out->n2 = (int64_t)1 << p->log2n2;
-    out->samples_in = p->samples_in;
-    out->outputs_done = p->blocks_done * p->hop;
+    out->samples_in = u * p->samples_in;
+    out->outputs_done = u * p->blocks_done * p->hop;
     out->max_batch = p->max_batch;
-    out->fs_hz = p->fs;
+    out->fs_hz = (double)u * p->fs;
+    out->input_kind = p->kind;
     out->delta_lo_s = p->delta_lo;
     out->delta_hi_s = p->delta_hi;
     out->inv_pfs = p->inv_pfs;
@@ -518,8 +561,8 @@ int32_t pond_plan_kernel_times(pond_plan* p, pond_kernel_times* out) {
     return POND_OK;
 }
 
-int32_t pond_plan_expect(const pond_plan* p, int64_t nsamp, int64_t subint, int64_t* n_profiles,
-                         int64_t* n_outputs) {
+static int32_t expect(const pond_plan* p, int64_t nsamp, int64_t subint, int64_t* n_profiles,
+                      int64_t* n_outputs) {
     if (!p || nsamp < 0 || subint < 0) return POND_EINVAL;
     const int64_t m_before = p->blocks_done * p->hop;
     const int64_t s_open = subint > 0 ? m_before / subint : 0;
@@ -537,6 +580,23 @@ int32_t pond_plan_expect(const pond_plan* p, int64_t nsamp, int64_t subint, int6
     return POND_OK;
 }
 
+int32_t pond_plan_expect(const pond_plan* p, int64_t nsamp, int64_t subint, int64_t* n_profiles,
+                         int64_t* n_outputs) {
+    if (!p || p->kind != POND_INPUT_COMPLEX) return POND_EINVAL;
+    return expect(p, nsamp, subint, n_profiles, n_outputs);
+}
+
+int32_t pond_real_expect(const pond_plan* p, int64_t nsamp, int64_t subint_nsamp, int64_t* n_profiles,
+                         int64_t* n_outputs) {
+    if (!p || p->kind == POND_INPUT_COMPLEX || (nsamp & 1) || (subint_nsamp & 1)) return POND_EINVAL;
+    int64_t no = 0;
+    const int32_t r = expect(p, nsamp / 2, subint_nsamp / 2, n_profiles, &no);
+    if (r == POND_OK && n_outputs) *n_outputs = 2 * no;
+    return r;
+}
+
+// nsamp, subint and decim in elements of the plan (complex samples, or
+// pairs of real samples on the real path).
 static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t subint, float* profiles,
                         int64_t max_profiles, int32_t decim, float* series, int64_t series_cap,
                         int64_t* n_series_out, bool want_series, void* stream_ptr) {
@@ -546,7 +606,8 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
     const bool flush = (iq == nullptr && nsamp == 0);
     if (!flush) {
         if (nsamp < 0) return POND_EINVAL;
-        if (nsamp > 0 && (iq == nullptr || (reinterpret_cast<uintptr_t>(iq) & 1u))) return POND_EINVAL;
+        if (nsamp > 0 && (iq == nullptr || (reinterpret_cast<uintptr_t>(iq) & (uintptr_t)(p->bpe - 1))))
+            return POND_EINVAL;
     }
     if (subint < 0 || max_profiles < 0) return POND_EINVAL;
     if (p->subint >= 0 && subint != p->subint) return POND_EINVAL;
@@ -678,7 +739,10 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a1.work = p->work;
         a1.tw2 = p->tw2;
         a1.scale = k1_scale;
-        e = timed(0, nb, [&] { return launch_k1(p->precision, n2log, a1, stream); });
+        const bool real = p->kind != POND_INPUT_COMPLEX;
+        e = timed(0, nb, [&] {
+            return real ? launch_k1_aip(p->precision, n2log, a1, stream) : launch_k1(p->precision, n2log, a1, stream);
+        });
         if (e != hipSuccess) return fail(e);
 
         K2Args a2{};
@@ -689,7 +753,25 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a2.table = p->table;
         a2.htable = p->htable;
         a2.scale = k2_scale;
-        e = timed(1, nb, [&] { return launch_k2(p->precision, kRowFull, p->log2n1, a2, stream); });
+        if (real) {
+            // Forward rows, the real split with the filter (in place), then
+            // the inverse rows with no further filter: one timed middle pass.
+            a2.tw4 = p->tw4;
+            a2.in = p->work;
+            a2.out = p->work;
+            a2.chirp = nullptr;
+            RealSplitArgs rs{p->work, (int32_t)nb, p->log2n1, n2log, p->rtab};
+            e = timed(1, nb, [&] {
+                hipError_t r = launch_k2(p->precision, kRowFwd, p->log2n1, a2, stream);
+                if (r == hipSuccess) r = launch_real_split(p->precision, rs, stream);
+                K2Args ai = a2;
+                ai.scale = 1.0f;
+                if (r == hipSuccess) r = launch_k2(p->precision, kRowInv, p->log2n1, ai, stream);
+                return r;
+            });
+        } else {
+            e = timed(1, nb, [&] { return launch_k2(p->precision, kRowFull, p->log2n1, a2, stream); });
+        }
         if (e != hipSuccess) return fail(e);
 
         K3Args a3;
@@ -721,7 +803,10 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a3.status = reinterpret_cast<uint32_t*>(p->status);
         const size_t dyn = global_mode ? 0 : (size_t)entries * 12;
         const int grid = k3_grid(n2log, dyn, nb * (n1 / 16), entries, global_mode);
-        e = timed(2, nb, [&] { return launch_k3(p->precision, n2log, a3, (int)grid, dyn, stream); });
+        e = timed(2, nb, [&] {
+            return real ? launch_k3_real(p->precision, n2log, a3, (int)grid, dyn, stream)
+                        : launch_k3(p->precision, n2log, a3, (int)grid, dyn, stream);
+        });
         if (e != hipSuccess) return fail(e);
         if (!global_mode) {
             e = timed(3, nb, [&] {
@@ -749,7 +834,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         const int64_t from = new_start > p->tail_start ? new_start : p->tail_start;
         const int64_t cnt = p->samples_in - from;
         if (cnt > 0) {
-            e = hipMemcpyAsync(dst, p->tail[p->tcur] + 2 * (from - p->tail_start), (size_t)cnt * 2,
+            e = hipMemcpyAsync(dst, p->tail[p->tcur] + p->bpe * (from - p->tail_start), (size_t)cnt * p->bpe,
                                hipMemcpyDeviceToDevice, stream);
             if (e != hipSuccess) return fail(e);
             filled = cnt;
@@ -759,7 +844,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         const int64_t from = new_start > p->samples_in ? new_start : p->samples_in;
         const int64_t cnt = total - from;
         if (cnt > 0) {
-            e = hipMemcpyAsync(dst + 2 * filled, iq + 2 * (from - p->samples_in), (size_t)cnt * 2,
+            e = hipMemcpyAsync(dst + p->bpe * filled, iq + p->bpe * (from - p->samples_in), (size_t)cnt * p->bpe,
                                hipMemcpyDeviceToDevice, stream);
             if (e != hipSuccess) return fail(e);
         }
@@ -776,14 +861,28 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
 
 int64_t pond_dedisperse_fold(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t subint_nsamp, float* profiles,
                              int64_t max_profiles, void* hip_stream) {
+    if (p && p->kind != POND_INPUT_COMPLEX) return POND_EINVAL;
     return run_call(p, iq, nsamp, subint_nsamp, profiles, max_profiles, 16, nullptr, 0, nullptr, false, hip_stream);
 }
 
 int64_t pond_dedisperse_series(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t subint_nsamp, float* profiles,
                                int64_t max_profiles, int32_t decim, float* series, int64_t series_cap,
                                int64_t* n_series_out, void* hip_stream) {
+    if (p && p->kind != POND_INPUT_COMPLEX) return POND_EINVAL;
     return run_call(p, iq, nsamp, subint_nsamp, profiles, max_profiles, decim, series, series_cap, n_series_out, true,
                     hip_stream);
+}
+
+int64_t pond_real_dedisperse(pond_plan* p, const int8_t* raw, int64_t nsamp, int64_t subint_nsamp, float* profiles,
+                             int64_t max_profiles, int32_t decim, float* series, int64_t series_cap,
+                             int64_t* n_series_out, void* hip_stream) {
+    if (n_series_out) *n_series_out = 0;
+    if (!p || p->kind == POND_INPUT_COMPLEX) return POND_EINVAL;
+    if ((nsamp & 1) || (subint_nsamp & 1)) return POND_EINVAL;
+    if (decim <= 0) decim = 32;
+    if (decim != 2 && decim != 4 && decim != 8 && decim != 16 && decim != 32) return POND_EINVAL;
+    return run_call(p, raw, nsamp / 2, subint_nsamp / 2, profiles, max_profiles, decim / 2, series, series_cap,
+                    n_series_out, series != nullptr, hip_stream);
 }
 
 }  // extern "C"

@@ -104,8 +104,12 @@ __device__ __forceinline__ h2 f16_unit(double c, double s, double m) {
 __device__ __forceinline__ h2 ld_h2(const __half2* p) { return *reinterpret_cast<const h2*>(p); }
 __device__ __forceinline__ void st_h2(__half2* p, h2 v) { *reinterpret_cast<h2*>(p) = v; }
 
-template <int LOG2N2, class T, int FORM>
+// AIP: the input is two real-sampled channels interleaved (A0 B0 A1 B1 ...);
+// element m packs the added-in-phase samples 2m and 2m+1 as (re, im), so a
+// block of 2N real samples is read as N complex elements of 4 bytes.
+template <int LOG2N2, class T, int FORM, bool AIP = false>
 __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
+    constexpr int BPE = AIP ? 4 : 2;  // input bytes per element
     constexpr int L = 1 << LOG2N2;
     constexpr int TPV = L / 16;
     __shared__ LdsVal<FORM> lds[16 * L];
@@ -126,8 +130,8 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     const int64_t bstart = (a.block0 + b) * a.hop;
     const int64_t split64 = a.in_start - bstart;
     const uint32_t split = split64 <= 0 ? 0u : (uint32_t)min(split64, (int64_t)1 << (a.log2n1 + LOG2N2));
-    const int8_t* tbase = a.tail + 2 * (bstart - a.tail_start);
-    const int8_t* ibase = a.in + 2 * (bstart - a.in_start);
+    const int8_t* tbase = a.tail + BPE * (bstart - a.tail_start);
+    const int8_t* ibase = a.in + BPE * (bstart - a.in_start);
     const uint32_t o0 = opaque((uint32_t)col);
     auto load_raw = [&](int pos) {
         const uint32_t off = o0 + ((uint32_t)pos << a.log2n1);
@@ -135,8 +139,16 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
         return *reinterpret_cast<const short*>(p);
     };
     auto load_in = [&](int pos) {
-        const short s = load_raw(pos);
-        return make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)(s >> 8));
+        if constexpr (AIP) {
+            const uint32_t off = o0 + ((uint32_t)pos << a.log2n1);
+            const int8_t* p = off < split ? tbase + 4 * off : ibase + 4 * off;
+            const int w = *reinterpret_cast<const int*>(p);
+            return make_float2((float)((int)(int8_t)(w & 0xff) + (int)(int8_t)((w >> 8) & 0xff)),
+                               (float)((int)(int8_t)((w >> 16) & 0xff) + (int)(int8_t)(w >> 24)));
+        } else {
+            const short s = load_raw(pos);
+            return make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)(s >> 8));
+        }
     };
     T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
     if constexpr (FORM == kFormF16) {
@@ -346,7 +358,8 @@ k2_row(K2Args a) {
             } else if constexpr (MODE == kRowFwd) {
                 v[e] = cmul(x, *at(tw4, (to + TPV * e) * 8u));
             } else {
-                v[e] = cmul(x, *at(chirp, (to + TPV * e) * 8u));
+                // no chirp table: the filter was applied before (real input path)
+                v[e] = a.chirp ? cmul(x, *at(chirp, (to + TPV * e) * 8u)) : x;
             }
         }
         if constexpr (MODE != kRowInv) {
@@ -464,6 +477,7 @@ __global__ void __launch_bounds__(256) k2_build_split_tables(float2* __restrict_
         sincospi(2.0 * (double)r / (double)n, &s, &c);
         tw[i] = make_float2((float)c, (float)-s);
     }
+    if (!chirp) return;
     const int64_t k = k2 + (k1 << log2n2);
     const int64_t kk = k < (n >> 1) ? k : k - n;
     const double f = (double)kk * df;
@@ -521,12 +535,20 @@ __device__ __forceinline__ void fold_add(const K3Args& a, uint64_t* hsum, uint32
     }
 }
 
-template <int LOG2N2, class T, int FORM>
+// REAL (real input path, float32 arithmetic): element m of the output is
+// y[2m] + i y[2m+1] of the real dedispersed voltage, detected per real
+// sample (y^2); the group of 16 elements is 32 real outputs, the series
+// (sums over decim elements = 2 decim real samples) is unchanged, and the
+// fold takes real sample r = 2 m + j with phase (r + 2 n_front) inv_pfs
+// (inv_pfs of the real sample rate).
+template <int LOG2N2, class T, int FORM, bool REAL = false>
 __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     using Sh = K3Shape<LOG2N2>;
     constexpr int L = Sh::L;
     constexpr int TPV = Sh::TPV;
-    constexpr int PSTRIDE = 20;  // floats per row of the power buffer (16 + 4 pad, 16-byte aligned)
+    // floats per row of the power buffer: 16 + 4 pad, 16-byte aligned; REAL:
+    // two powers per column, 32 (the buffer then fills the FFT tile exactly)
+    constexpr int PSTRIDE = REAL ? 32 : 20;
     __shared__ float2 lds[16 * L];
     extern __shared__ uint64_t dyn_u64[];
     uint64_t* hsum = dyn_u64;
@@ -604,7 +626,11 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const float2 y = cscale(v[e], a.scale);
-                pf[(j + TPV * e) * PSTRIDE + c] = fmaf(y.x, y.x, y.y * y.y);
+                if constexpr (REAL) {
+                    *reinterpret_cast<float2*>(pf + (j + TPV * e) * PSTRIDE + 2 * c) = make_float2(y.x * y.x, y.y * y.y);
+                } else {
+                    pf[(j + TPV * e) * PSTRIDE + c] = fmaf(y.x, y.x, y.y * y.y);
+                }
             }
             __syncthreads();
         }
@@ -616,7 +642,29 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         const int64_t nstart = (int64_t)(r0 + 16 * t) + ((int64_t)q << a.log2n1);
         const int64_t off = nstart - a.n_front;
         float p[16];
-        if (r0 + 16 * t + 15 < n1) {
+        float pr[REAL ? 32 : 1];  // REAL: the 32 real-sample powers of the group
+        if constexpr (REAL) {
+            if (r0 + 16 * t + 15 < n1) {
+                const float4* row = reinterpret_cast<const float4*>(pf + q * PSTRIDE);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const float4 x4 = row[i];
+                    pr[4 * i] = x4.x;
+                    pr[4 * i + 1] = x4.y;
+                    pr[4 * i + 2] = x4.z;
+                    pr[4 * i + 3] = x4.w;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int rsrc = q + ((r0 + 16 * t + i) >> a.log2n1);
+                    pr[2 * i] = rsrc < L ? pf[rsrc * PSTRIDE + 2 * i] : 0.f;
+                    pr[2 * i + 1] = rsrc < L ? pf[rsrc * PSTRIDE + 2 * i + 1] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) p[i] = pr[2 * i] + pr[2 * i + 1];
+        } else if (r0 + 16 * t + 15 < n1) {
             const float4* row = reinterpret_cast<const float4*>(pf + q * PSTRIDE);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -670,19 +718,21 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         // sub-integration (the first and last decide, phase being monotone),
         // otherwise one per output.
         double t0, t15;
-        const int bin0 = fold_bin(m0, a.n_front, a.inv_pfs, a.nbins, &t0);
-        const int bin15 = fold_bin(m0 + 15, a.n_front, a.inv_pfs, a.nbins, &t15);
+        constexpr int G = REAL ? 32 : 16;  // fold samples of the group
+        const int64_t f0i = REAL ? 2 * m0 : m0, fnf = REAL ? 2 * a.n_front : a.n_front;
+        const int bin0 = fold_bin(f0i, fnf, a.inv_pfs, a.nbins, &t0);
+        const int bin15 = fold_bin(f0i + G - 1, fnf, a.inv_pfs, a.nbins, &t15);
         const int64_t d0 = m0 - a.s_base * a.subint;
         const int64_t sub0 = a.subint > 0 ? subint_rel(d0, a.subint, inv_s) : 0;
         const int64_t sub15 = a.subint > 0 ? subint_rel(d0 + 15, a.subint, inv_s) : 0;
         if (bin0 == bin15 && t0 == t15 && sub0 == sub15) {
-            fold_add(a, hsum, hcnt, sub0, bin0, s16, 16, flags);
+            fold_add(a, hsum, hcnt, sub0, bin0, s16, G, flags);
         } else {
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < G; ++i) {
                 double ti;
-                const int bi = fold_bin(m0 + i, a.n_front, a.inv_pfs, a.nbins, &ti);
-                const int64_t si = a.subint > 0 ? subint_rel(d0 + i, a.subint, inv_s) : 0;
-                fold_add(a, hsum, hcnt, si, bi, p[i], 1, flags);
+                const int bi = fold_bin(f0i + i, fnf, a.inv_pfs, a.nbins, &ti);
+                const int64_t si = a.subint > 0 ? subint_rel(d0 + (REAL ? i / 2 : i), a.subint, inv_s) : 0;
+                fold_add(a, hsum, hcnt, si, bi, REAL ? pr[i] : p[i], 1, flags);
             }
         }
     }
@@ -759,6 +809,99 @@ __global__ void __launch_bounds__(256) fold_profiles(const uint64_t* acc_sum, co
 __global__ void __launch_bounds__(256) zero_u64(uint64_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
+}
+
+// ----------------------------------------------------- real input path
+// The block holds Z = FFT_N(z) / N of z[m] = x[2m] + i x[2m+1] (x real, 2N
+// samples), row k2 / column k1 holding bin k = k2 + n2 k1 (after the
+// forward row pass).  Per bin, with its partner bin N - k (row n2 - k2,
+// column n1 - 1 - k1; row 0: column -k1 mod n1):
+//   E = (Z[k] + conj Z[N-k]) / 2,  O = -i (Z[k] - conj Z[N-k]) / 2
+//   X[k] = E + W^k O,  X[N-k] = conj(E - W^k O)      (W = exp(-2 pi i / 2N))
+// X are the bins 0..N of the real 2N-point transform.  Y = X M (the real
+// path's filter per bin, with the DC and Nyquist factors real), then
+//   Z'[k] = e + i o,  e = (Y[k] + conj Y[N-k]) / 2,  o = conj(W^k) (Y[k] - conj Y[N-k]) / 2
+//   Z'[N-k] = conj(e) + i conj(o)
+// is the N-point spectrum of z'[m] = y[2m] + i y[2m+1], y the filtered real
+// signal.  tab[k] = (W^k, M[k]) for k <= N.  In place: one thread per pair
+// {k, N-k} (rows 0..n2/2; on the two rows that pair with themselves, the
+// thread of the lower index), which reads and writes both bins.
+template <class T>
+__global__ void __launch_bounds__(256) real_split(RealSplitArgs a) {
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = a.log2n1 + a.log2n2;
+    const int n1 = 1 << a.log2n1, n2 = 1 << a.log2n2, N = 1 << log2n;
+    const int per_block = (n2 / 2 + 1) << a.log2n1;  // rows 0..n2/2
+    if (gi >= (int64_t)a.nblocks * per_block) return;
+    const int64_t b = gi / per_block;
+    const int i = (int)(gi - b * per_block);
+    const int k2 = i >> a.log2n1, k1 = i & (n1 - 1);
+    const int ip = k2 == 0 ? ((n1 - k1) & (n1 - 1)) : (((n2 - k2) << a.log2n1) + (n1 - 1 - k1));
+    if (ip < i) return;  // the pair belongs to the thread of index ip
+    const int k = k2 + (k1 << a.log2n2);
+    T* z = reinterpret_cast<T*>(a.data) + (b << log2n);
+    const float2 A = Elem<T>::load(z + i), B = Elem<T>::load(z + ip);
+    const float4 tk = a.tab[k], tn = a.tab[N - k];
+    const float2 w = make_float2(tk.x, tk.y), mk = make_float2(tk.z, tk.w), mn = make_float2(tn.z, tn.w);
+    const float2 E = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
+    const float2 D = make_float2(0.5f * (A.x - B.x), 0.5f * (A.y + B.y));  // (Z[k] - conj Z[N-k]) / 2
+    const float2 O = make_float2(D.y, -D.x);                                // -i D
+    const float2 wo = cmul(w, O);
+    const float2 yk = cmul(cadd(E, wo), mk);
+    const float2 en = csub(E, wo);
+    const float2 yn = cmul(make_float2(en.x, -en.y), mn);                    // Y[N-k]
+    const float2 ync = make_float2(yn.x, -yn.y);
+    const float2 e2 = cscale(cadd(yk, ync), 0.5f);
+    const float2 o2 = cmulc(cscale(csub(yk, ync), 0.5f), w);
+    Elem<T>::store(z + i, make_float2(e2.x - o2.y, e2.y + o2.x));
+    if (ip != i) Elem<T>::store(z + ip, make_float2(e2.x + o2.y, o2.x - e2.y));
+}
+
+// tab[k] = (W^k, M[k]) for k = 0..N of the real path's split: W^k =
+// exp(-i pi k / N); M[k] the filter of real-transform bin k (baseband
+// k bw / N): upper sideband exp(-2 pi i turns(f)), f = k bw/N - bw/2; lower
+// sideband exp(+2 pi i turns(f)), f = bw/2 - k bw/N; times the taper; real
+// part only at k = 0 and k = N.  Float64, reduced mod 1 turn.
+__global__ void __launch_bounds__(256) real_build_table(float4* __restrict__ tab, int log2n, double chirp_a,
+                                                         double f0, double bw, int lsb, double taper) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = 1ll << log2n;
+    if (k > N) return;
+    double sw, cw;
+    sincospi((double)k / (double)N, &sw, &cw);
+    const double fb = (double)k * bw / (double)N;
+    const double f = lsb ? bw * 0.5 - fb : fb - bw * 0.5;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double sm, cm;
+    sincospi(2.0 * frac, &sm, &cm);
+    const double wt = taper_w(f, bw, taper);
+    double mx = cm * wt, my = (lsb ? sm : -sm) * wt;
+    if (k == 0 || k == N) my = 0.0;
+    tab[k] = make_float4((float)cw, (float)-sw, (float)mx, (float)my);
+}
+
+template <class T>
+static hipError_t real_split_t(const RealSplitArgs& a, hipStream_t s) {
+    const int64_t n = (int64_t)a.nblocks * (((1 << a.log2n2) / 2 + 1) << a.log2n1);
+    hipLaunchKernelGGL(real_split<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_real_split(int prec, const RealSplitArgs& a, hipStream_t s) {
+    switch (prec) {
+        case kFp32: return real_split_t<float2>(a, s);
+        case kMixedValu: return real_split_t<__half2>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_real_build_table(float4* tab, int log2n, double chirp_a, double f0, double bw, int lsb,
+                                   double taper, hipStream_t s) {
+    const int64_t n = (1ll << log2n) + 1;
+    hipLaunchKernelGGL(real_build_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n, chirp_a, f0,
+                       bw, lsb, taper);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------- incoherent (AID) mode
@@ -921,6 +1064,35 @@ static hipError_t k1_dispatch(int log2n2, const K1Args& a, hipStream_t s) {
     }
 }
 
+template <class T, int LOG2N2>
+static hipError_t k1_aip_one(const K1Args& a, hipStream_t s) {
+    const int ntiles = a.nblocks * ((1 << a.log2n1) >> 4);
+    const int grid = (ntiles + 7) & ~7;
+    hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, kFormF32, true>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t k1_aip_dispatch(int log2n2, const K1Args& a, hipStream_t s) {
+    switch (log2n2) {
+        case 5: return k1_aip_one<T, 5>(a, s);
+        case 6: return k1_aip_one<T, 6>(a, s);
+        case 7: return k1_aip_one<T, 7>(a, s);
+        case 8: return k1_aip_one<T, 8>(a, s);
+        case 9: return k1_aip_one<T, 9>(a, s);
+        case 10: return k1_aip_one<T, 10>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_k1_aip(int prec, int log2n2, const K1Args& a, hipStream_t s) {
+    switch (prec) {
+        case kFp32: return k1_aip_dispatch<float2>(log2n2, a, s);
+        case kMixedValu: return k1_aip_dispatch<__half2>(log2n2, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s) {
     switch (prec) {
         case kMixed: return k1_dispatch<__half2, kFormMfma>(log2n2, a, s);
@@ -1018,6 +1190,37 @@ static hipError_t k3_dispatch(int log2n2, const K3Args& a, int grid, size_t dyn,
         case 8: return k3_one<T, FORM, 8>(a, grid, dyn, s);
         case 9: return k3_one<T, FORM, 9>(a, grid, dyn, s);
         case 10: return k3_one<T, FORM, 10>(a, grid, dyn, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T, int LOG2N2>
+static hipError_t k3_real_one(const K3Args& a, int grid, size_t dyn, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k3_colinv_detect_fold<LOG2N2, T, kFormF32, true>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - K3Shape<LOG2N2>::LDS));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k3_colinv_detect_fold<LOG2N2, T, kFormF32, true>), dim3(grid), dim3(1 << LOG2N2), dyn, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t k3_real_dispatch(int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s) {
+    switch (log2n2) {
+        case 5: return k3_real_one<T, 5>(a, grid, dyn, s);
+        case 6: return k3_real_one<T, 6>(a, grid, dyn, s);
+        case 7: return k3_real_one<T, 7>(a, grid, dyn, s);
+        case 8: return k3_real_one<T, 8>(a, grid, dyn, s);
+        case 9: return k3_real_one<T, 9>(a, grid, dyn, s);
+        case 10: return k3_real_one<T, 10>(a, grid, dyn, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_k3_real(int prec, int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s) {
+    switch (prec) {
+        case kFp32: return k3_real_dispatch<float2>(log2n2, a, grid, dyn, s);
+        case kMixedValu: return k3_real_dispatch<__half2>(log2n2, a, grid, dyn, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -28,6 +28,13 @@ FORMS = {"fp32": POND_FP32, "mixed": POND_MIXED, "mixed_valu": POND_MIXED_VALU, 
 POND_STATUS_NONFINITE = 1
 POND_STATUS_RANGE = 2
 
+POND_INPUT_COMPLEX = 0
+POND_INPUT_REAL_LSB = 1
+POND_INPUT_REAL_USB = 2
+POND_LSB = 0
+POND_USB = 1
+SIDEBANDS = {"lsb": POND_LSB, "usb": POND_USB}
+
 EXPORTS = (
     "pond_plan_create", "pond_plan_create_ex", "pond_create_status",
     "pond_dedisperse_fold", "pond_dedisperse_series", "pond_plan_query",
@@ -38,6 +45,7 @@ EXPORTS = (
     "pond_server_poll", "pond_server_take_profiles", "pond_server_close", "pond_server_query",
     "pond_server_destroy",
     "pond_aid_create", "pond_aid_geometry", "pond_aid_run", "pond_aid_destroy",
+    "pond_real_plan_create", "pond_real_dedisperse", "pond_real_expect",
 )
 KERNEL_NAMES = ("k1_unpack_colfft", "k2_row", "k3_colinv_detect_fold", "fold_reduce", "fold_finalize")
 
@@ -59,7 +67,7 @@ class pond_info(ctypes.Structure):
         ("fs_hz", ctypes.c_double), ("delta_lo_s", ctypes.c_double),
         ("delta_hi_s", ctypes.c_double), ("inv_pfs", ctypes.c_double),
         ("nbins", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("status", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+        ("status", ctypes.c_uint32), ("input_kind", ctypes.c_int32),
     ]
 
 
@@ -153,6 +161,12 @@ def _load():
     lib.pond_aid_run.restype = i64
     lib.pond_aid_destroy.argtypes = [P]
     lib.pond_aid_destroy.restype = None
+    lib.pond_real_plan_create.argtypes = [dbl, dbl, dbl, i64, i32, dbl, i32, i32, i32]
+    lib.pond_real_plan_create.restype = P
+    lib.pond_real_dedisperse.argtypes = [P, P, i64, i64, P, i64, i32, P, i64, ctypes.POINTER(i64), P]
+    lib.pond_real_dedisperse.restype = i64
+    lib.pond_real_expect.argtypes = [P, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.pond_real_expect.restype = i32
     lib.pond_strerror.argtypes = [i64]
     lib.pond_strerror.restype = ctypes.c_char_p
     return lib
@@ -248,6 +262,36 @@ def pond_plan_set_taper(plan, alpha):
     r = _lib.pond_plan_set_taper(plan, float(alpha))
     if r != POND_OK:
         raise PondError(r, "pond_plan_set_taper")
+
+
+def pond_real_plan_create(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision=POND_FP32, max_batch=0,
+                          sideband=POND_LSB):
+    """Real two-channel input plan (nfft: real block length); raises PondError."""
+    if isinstance(sideband, str):
+        sideband = SIDEBANDS[sideband]
+    h = _lib.pond_real_plan_create(float(f0_mhz), float(bw_mhz), float(dm), int(nfft), int(nbins),
+                                   float(period_s), int(precision), int(max_batch), int(sideband))
+    if not h:
+        raise PondError(_lib.pond_create_status(), "pond_real_plan_create")
+    return h
+
+
+def pond_real_dedisperse(plan, raw, nsamp, subint_nsamp, profiles, max_profiles, decim=32, series=None,
+                         series_cap=0, stream=None):
+    """Returns (profiles written or error code, series values written)."""
+    n = ctypes.c_int64(0)
+    r = _lib.pond_real_dedisperse(plan, _ptr(raw), int(nsamp), int(subint_nsamp), _ptr(profiles),
+                                  int(max_profiles), int(decim), _ptr(series), int(series_cap),
+                                  ctypes.byref(n), _stream(stream))
+    return r, n.value
+
+
+def pond_real_expect(plan, nsamp, subint_nsamp):
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    r = _lib.pond_real_expect(plan, int(nsamp), int(subint_nsamp), ctypes.byref(a), ctypes.byref(b))
+    if r != POND_OK:
+        raise PondError(r, "pond_real_expect")
+    return a.value, b.value
 
 
 def pond_search_create(f0_mhz, bw_mhz, dms, nbins, period_s, nfft_min=1 << 20, nfft_max=1 << 23,
@@ -375,25 +419,44 @@ def pond_aid_destroy(aid):
 class Plan:
     """A dedispersion + fold plan on the current torch device.
 
-    ``process(iq)`` appends a device int8 I/Q tensor and returns the
-    profiles completed by the call (float32, [k, nbins]) and, if asked, the
-    new decimated series values; ``flush()`` ends the stream and returns the
+    ``process(iq)`` appends a device int8 tensor and returns the profiles
+    completed by the call (float32, [k, nbins]) and, if asked, the new
+    decimated series values; ``flush()`` ends the stream and returns the
     open sub-integration's profile.  Output tensors are allocated with torch
-    on the plan's device.
+    on the plan's device.  With ``sideband`` ("lsb" or "usb") the plan takes
+    the real two-channel input (int8 A/B pairs) and nfft, subint_nsamp and
+    decim count real samples.
     """
 
     def __init__(self, f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision="fp32",
-                 max_batch=0, subint_nsamp=0, decim=16, taper_alpha=0.0):
+                 max_batch=0, subint_nsamp=0, decim=None, taper_alpha=0.0, sideband=None):
         prec = FORMS.get(precision, precision)
-        self.handle = pond_plan_create(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, prec, max_batch)
+        self.real = sideband is not None
+        if self.real:
+            self.handle = pond_real_plan_create(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, prec,
+                                                max_batch, sideband)
+        else:
+            self.handle = pond_plan_create(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, prec, max_batch)
         if taper_alpha:
             pond_plan_set_taper(self.handle, taper_alpha)
         self.nbins = int(nbins)
         self.subint = int(subint_nsamp)
-        self.decim = int(decim)
+        self.decim = int(decim) if decim is not None else (32 if self.real else 16)
 
     def info(self):
         return pond_plan_query(self.handle)
+
+    def _expect(self, nsamp):
+        return (pond_real_expect if self.real else pond_plan_expect)(self.handle, nsamp, self.subint)
+
+    def _call(self, iq, nsamp, prof, nprof, ser, stream):
+        if self.real:
+            return pond_real_dedisperse(self.handle, iq, nsamp, self.subint, prof, nprof, self.decim,
+                                        ser, ser.numel() if ser is not None else 0, stream)
+        if ser is not None:
+            return pond_dedisperse_series(self.handle, iq, nsamp, self.subint, prof, nprof,
+                                          self.decim, ser, ser.numel(), stream)
+        return pond_dedisperse_fold(self.handle, iq, nsamp, self.subint, prof, nprof, stream), 0
 
     def process(self, iq, want_series=True, stream=None):
         import torch
@@ -401,25 +464,20 @@ class Plan:
         if nsamp == 0:   # a NULL/0 call would end the stream
             empty = torch.empty((0, self.nbins), dtype=torch.float32, device=iq.device)
             return empty, (torch.empty(0, dtype=torch.float32, device=iq.device) if want_series else None)
-        nprof, nout = pond_plan_expect(self.handle, nsamp, self.subint)
+        nprof, nout = self._expect(nsamp)
         prof = torch.empty((max(nprof, 0), self.nbins), dtype=torch.float32, device=iq.device)
-        if want_series:
-            ser = torch.empty(nout // self.decim, dtype=torch.float32, device=iq.device)
-            r, ns = pond_dedisperse_series(self.handle, iq, nsamp, self.subint, prof, nprof,
-                                           self.decim, ser, ser.numel(), stream)
-        else:
-            ser, ns = None, 0
-            r = pond_dedisperse_fold(self.handle, iq, nsamp, self.subint, prof, nprof, stream)
+        ser = torch.empty(nout // self.decim, dtype=torch.float32, device=iq.device) if want_series else None
+        r, ns = self._call(iq, nsamp, prof, nprof, ser, stream)
         if r < 0:
             raise PondError(r, "process")
         return prof[:r], (ser[:ns] if ser is not None else None)
 
     def flush(self, device=None, stream=None):
         import torch
-        nprof, _ = pond_plan_expect(self.handle, 0, self.subint)
+        nprof, _ = self._expect(0)
         prof = torch.empty((nprof, self.nbins), dtype=torch.float32,
                            device=device if device is not None else torch.device("cuda"))
-        r = pond_dedisperse_fold(self.handle, None, 0, self.subint, prof, nprof, stream)
+        r, _ = self._call(None, 0, prof, nprof, None, stream)
         if r < 0:
             raise PondError(r, "flush")
         return prof[:r]

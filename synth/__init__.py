@@ -21,6 +21,12 @@ Recipe (one stream):
     noise power;
   * quantisation rounds half to even and clips to the int8 range
     [-128, 127]; I and Q are interleaved, I first.
+
+Real two-channel recipe (the receiver's own sampling, Sec. 3.1): a real
+voltage sampled at twice the bandwidth (the I component of the stream
+above, at that rate) is given to two channels A and B as x/2 plus
+independent N(0, noise^2) receiver noise each, quantised as above and
+interleaved A0 B0 A1 B1 ...
 """
 from __future__ import annotations
 
@@ -156,4 +162,27 @@ def white_stream_int8(seed: int, nsamp: int, sigma: float = SIGMA):
         out[2 * s:2 * e] = d.astype(np.int8).reshape(-1)
 
     _for_chunks(nsamp, fill)
+    return out
+
+
+def pulsed_real_noise(seed: int, nsamp: int, first_index: int = 0,
+                      fs_hz: float = 2 * BW_MHZ * 1e6, period_s: float = PERIOD_S,
+                      fwhm_s: float = FWHM_S, peak: float = PEAK,
+                      phase0: float = PHASE0, sigma: float = SIGMA):
+    """Undispersed real float64 stream at the real sample rate: the I
+    component of pulsed_noise."""
+    return pulsed_noise(seed, nsamp, first_index, fs_hz, period_s, fwhm_s, peak, phase0, sigma).real.copy()
+
+
+def two_channel_int8(x, seed: int, noise: float = 5.0):
+    """Interleaved int8 A0 B0 A1 B1 ...: A, B = x/2 plus independent
+    N(0, noise^2) noise each, rounded half to even and clipped."""
+    x = np.asarray(x, dtype=np.float64)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty(2 * x.size, dtype=np.int8)
+    for k in range(2):
+        d = x / 2 + noise * rng.standard_normal(x.size)
+        np.rint(d, out=d)
+        np.clip(d, -128, 127, out=d)
+        out[k::2] = d.astype(np.int8)
     return out
