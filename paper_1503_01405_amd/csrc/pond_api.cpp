@@ -308,7 +308,7 @@ namespace {
 // Builds the filter table of the plan's middle pass (for the taper alpha).
 hipError_t build_filter(pond_plan* p, double alpha) {
     if (p->kind != POND_INPUT_COMPLEX)
-        return launch_real_build_table(p->rtab, p->log2n, p->chirp_a, p->f0, p->bw,
+        return launch_real_build_table(p->rtab, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->bw,
                                        p->kind == POND_INPUT_REAL_LSB ? 1 : 0, alpha, nullptr);
     if (p->precision == POND_HALF)
         return launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);

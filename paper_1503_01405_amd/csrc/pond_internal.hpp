@@ -87,13 +87,13 @@ struct RealSplitArgs {
                             // by the spectrum of the filtered packed block
     int32_t nblocks;
     int32_t log2n1, log2n2;
-    const float4* tab;      // [N + 1] (W^k, M[k])
+    const float4* tab;      // [N + 1] (W^k, M[k]) of the bin at each position, then bin N
 };
 hipError_t launch_k1_aip(int prec, int log2n2, const K1Args& a, hipStream_t s);
 hipError_t launch_real_split(int prec, const RealSplitArgs& a, hipStream_t s);
 hipError_t launch_k3_real(int prec, int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s);
-hipError_t launch_real_build_table(float4* tab, int log2n, double chirp_a, double f0, double bw, int lsb,
-                                   double taper, hipStream_t s);
+hipError_t launch_real_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double bw,
+                                   int lsb, double taper, hipStream_t s);
 
 // Incoherent (AID) mode: filterbank, then channel shift-and-sum and fold.
 struct AidArgs {

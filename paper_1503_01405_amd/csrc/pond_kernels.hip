@@ -823,7 +823,9 @@ __global__ void __launch_bounds__(256) zero_u64(uint64_t* p, int64_t n) {
 //   Z'[k] = e + i o,  e = (Y[k] + conj Y[N-k]) / 2,  o = conj(W^k) (Y[k] - conj Y[N-k]) / 2
 //   Z'[N-k] = conj(e) + i conj(o)
 // is the N-point spectrum of z'[m] = y[2m] + i y[2m+1], y the filtered real
-// signal.  tab[k] = (W^k, M[k]) for k <= N.  In place: one thread per pair
+// signal.  tab[i] = (W^k, M[k]) for the bin k held at position i of the
+// block (so that both table reads are contiguous), tab[N] = (-1, M[N]).
+// In place: one thread per pair
 // {k, N-k} (rows 0..n2/2; on the two rows that pair with themselves, the
 // thread of the lower index), which reads and writes both bins.
 template <class T>
@@ -838,10 +840,9 @@ __global__ void __launch_bounds__(256) real_split(RealSplitArgs a) {
     const int k2 = i >> a.log2n1, k1 = i & (n1 - 1);
     const int ip = k2 == 0 ? ((n1 - k1) & (n1 - 1)) : (((n2 - k2) << a.log2n1) + (n1 - 1 - k1));
     if (ip < i) return;  // the pair belongs to the thread of index ip
-    const int k = k2 + (k1 << a.log2n2);
     T* z = reinterpret_cast<T*>(a.data) + (b << log2n);
     const float2 A = Elem<T>::load(z + i), B = Elem<T>::load(z + ip);
-    const float4 tk = a.tab[k], tn = a.tab[N - k];
+    const float4 tk = a.tab[i], tn = a.tab[i == 0 ? N : ip];
     const float2 w = make_float2(tk.x, tk.y), mk = make_float2(tk.z, tk.w), mn = make_float2(tn.z, tn.w);
     const float2 E = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
     const float2 D = make_float2(0.5f * (A.x - B.x), 0.5f * (A.y + B.y));  // (Z[k] - conj Z[N-k]) / 2
@@ -857,16 +858,21 @@ __global__ void __launch_bounds__(256) real_split(RealSplitArgs a) {
     if (ip != i) Elem<T>::store(z + ip, make_float2(e2.x + o2.y, o2.x - e2.y));
 }
 
-// tab[k] = (W^k, M[k]) for k = 0..N of the real path's split: W^k =
-// exp(-i pi k / N); M[k] the filter of real-transform bin k (baseband
-// k bw / N): upper sideband exp(-2 pi i turns(f)), f = k bw/N - bw/2; lower
-// sideband exp(+2 pi i turns(f)), f = bw/2 - k bw/N; times the taper; real
-// part only at k = 0 and k = N.  Float64, reduced mod 1 turn.
-__global__ void __launch_bounds__(256) real_build_table(float4* __restrict__ tab, int log2n, double chirp_a,
-                                                         double f0, double bw, int lsb, double taper) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Table of the real path's split, in the block's layout: entry i < N (row
+// k2 = i / n1, column k1 = i mod n1) holds bin k = k2 + n2 k1, entry N bin
+// N; each is (W^k, M[k]) with W^k = exp(-i pi k / N) and M[k] the filter of
+// real-transform bin k (baseband k bw / N): upper sideband
+// exp(-2 pi i turns(f)), f = k bw/N - bw/2; lower sideband
+// exp(+2 pi i turns(f)), f = bw/2 - k bw/N; times the taper; real part only
+// at k = 0 and k = N.  Float64, reduced mod 1 turn.
+__global__ void __launch_bounds__(256) real_build_table(float4* __restrict__ tab, int log2n1, int log2n2,
+                                                         double chirp_a, double f0, double bw, int lsb,
+                                                         double taper) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
     const int64_t N = 1ll << log2n;
-    if (k > N) return;
+    if (i > N) return;
+    const int64_t k = i == N ? N : (i >> log2n1) + ((i & ((1ll << log2n1) - 1)) << log2n2);
     double sw, cw;
     sincospi((double)k / (double)N, &sw, &cw);
     const double fb = (double)k * bw / (double)N;
@@ -878,7 +884,7 @@ __global__ void __launch_bounds__(256) real_build_table(float4* __restrict__ tab
     const double wt = taper_w(f, bw, taper);
     double mx = cm * wt, my = (lsb ? sm : -sm) * wt;
     if (k == 0 || k == N) my = 0.0;
-    tab[k] = make_float4((float)cw, (float)-sw, (float)mx, (float)my);
+    tab[i] = make_float4((float)cw, (float)-sw, (float)mx, (float)my);
 }
 
 template <class T>
@@ -896,11 +902,11 @@ hipError_t launch_real_split(int prec, const RealSplitArgs& a, hipStream_t s) {
     }
 }
 
-hipError_t launch_real_build_table(float4* tab, int log2n, double chirp_a, double f0, double bw, int lsb,
-                                   double taper, hipStream_t s) {
-    const int64_t n = (1ll << log2n) + 1;
-    hipLaunchKernelGGL(real_build_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n, chirp_a, f0,
-                       bw, lsb, taper);
+hipError_t launch_real_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double bw,
+                                   int lsb, double taper, hipStream_t s) {
+    const int64_t n = (1ll << (log2n1 + log2n2)) + 1;
+    hipLaunchKernelGGL(real_build_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n1, log2n2,
+                       chirp_a, f0, bw, lsb, taper);
     return hipGetLastError();
 }
 
