@@ -530,15 +530,16 @@ REAL_DECIM = 2 * DECIM          # 1 us
 REAL_METRIC = "Msamples/s (real) dedispersed+folded at DM 50, real two-channel input"
 
 
-def real_algorithmic_bytes(kernel, blocks, elem, n, hop_e):
+def real_algorithmic_bytes(kernel, blocks, elem, n, hop_e, n1):
     """Per kernel slot of the real path, for `blocks` blocks of n packed
     elements: int8 A/B pairs (4 B per element) read once; the middle pass
-    (forward rows, split + filter, inverse rows) reads and writes the block
-    three times; the inverse columns read it once and write the series."""
+    reads and writes the block once (rows up to 2^13: one fused kernel;
+    longer rows: forward rows, split, inverse rows, three times); the
+    inverse columns read it once and write the series."""
     if kernel == "k1_unpack_colfft":
         return blocks * n * (4 + elem)
     if kernel == "k2_row":
-        return blocks * n * 6 * elem
+        return blocks * n * (2 if n1 <= 1 << 13 else 6) * elem
     if kernel == "k3_colinv_detect_fold":
         return blocks * (n * elem + hop_e // 16 * 4)
     return 0
@@ -614,7 +615,7 @@ def main_real(args):
     dom = max(kt, key=lambda k: kt[k][0])
     ms, launches, blocks = kt[dom]
     n_e, hop_e = REAL_NFFT // 2, h["info"]["hop"] // 2
-    algo = real_algorithmic_bytes(dom, blocks, elem, n_e, hop_e)
+    algo = real_algorithmic_bytes(dom, blocks, elem, n_e, hop_e, h["info"]["n1"])
     achieved = algo / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     out = {
         "metric": REAL_METRIC, "value": round(value, 2), "unit": "Msamples/s", "n_gpus": 1,

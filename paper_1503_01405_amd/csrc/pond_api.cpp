@@ -45,8 +45,13 @@ struct pond_plan {
     // elements, the filter and fold in real samples.
     int32_t kind = POND_INPUT_COMPLEX;
     int bpe = 2;                // input bytes per element
-    float2* tw4 = nullptr;      // real input: [n2][n1] four-step twiddle
-    float4* rtab = nullptr;     // real input: [nfft + 1] (split twiddle, filter)
+    // Rows up to 2^13: one fused middle pass (k2_real_pair) with rtab =
+    // (four-step twiddle, filter) and wk; longer rows: forward rows, split,
+    // inverse rows with tw4 and rtab = (split twiddle, filter).
+    bool real_fused = false;
+    float2* tw4 = nullptr;
+    float4* rtab = nullptr;     // [nfft + 1]
+    float2* wk = nullptr;       // [n2 + n1]
 
     void* work = nullptr;
     int8_t* tail[2] = {nullptr, nullptr};
@@ -140,7 +145,7 @@ void free_plan_memory(pond_plan* p) {
     p->marks.clear();
     for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     p->event_pool.clear();
-    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->table, p->htable, p->tw4, p->rtab,
+    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->table, p->htable, p->tw4, p->rtab, p->wk,
                     p->acc_sum, p->acc_cnt, p->part_sum, p->part_cnt, p->status};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -307,9 +312,12 @@ namespace {
 
 // Builds the filter table of the plan's middle pass (for the taper alpha).
 hipError_t build_filter(pond_plan* p, double alpha) {
+    const int lsb = p->kind == POND_INPUT_REAL_LSB ? 1 : 0;
+    if (p->kind != POND_INPUT_COMPLEX && p->real_fused)
+        return launch_real_build_pair_table(p->rtab, p->wk, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->bw, lsb,
+                                            alpha, nullptr);
     if (p->kind != POND_INPUT_COMPLEX)
-        return launch_real_build_table(p->rtab, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->bw,
-                                       p->kind == POND_INPUT_REAL_LSB ? 1 : 0, alpha, nullptr);
+        return launch_real_build_table(p->rtab, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->bw, lsb, alpha, nullptr);
     if (p->precision == POND_HALF)
         return launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
     return launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
@@ -405,10 +413,15 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     if (e == hipSuccess) chk(upload(&p->tw1, twiddles(n1, n1, 1)));
     if (e == hipSuccess) chk(upload(&p->tw2, twiddles(n2, n2, 1)));
     if (kind != POND_INPUT_COMPLEX) {
-        chk(hipMalloc(reinterpret_cast<void**>(&p->tw4), (size_t)nfft * sizeof(float2)));
+        p->real_fused = p->log2n1 <= kRealPairMaxLog2N1;
         chk(hipMalloc(reinterpret_cast<void**>(&p->rtab), (size_t)(nfft + 1) * sizeof(float4)));
-        if (e == hipSuccess)
-            chk(launch_k2_build_split_tables(p->tw4, nullptr, p->log2n1, p->log2n2, 0.0, p->f0, p->df, nullptr));
+        if (p->real_fused) {
+            chk(hipMalloc(reinterpret_cast<void**>(&p->wk), (size_t)(n1 + n2) * sizeof(float2)));
+        } else {
+            chk(hipMalloc(reinterpret_cast<void**>(&p->tw4), (size_t)nfft * sizeof(float2)));
+            if (e == hipSuccess)
+                chk(launch_k2_build_split_tables(p->tw4, nullptr, p->log2n1, p->log2n2, 0.0, p->f0, p->df, nullptr));
+        }
     } else if (precision == POND_HALF) {
         chk(hipMalloc(&p->htable, (size_t)nfft * 8));
     } else {
@@ -753,7 +766,10 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a2.table = p->table;
         a2.htable = p->htable;
         a2.scale = k2_scale;
-        if (real) {
+        if (real && p->real_fused) {
+            RealPairArgs rp{p->work, (int32_t)nb, n2log, p->tw1, p->rtab, p->wk, k2_scale};
+            e = timed(1, nb, [&] { return launch_real_pair(p->precision, p->log2n1, rp, stream); });
+        } else if (real) {
             // Forward rows, the real split with the filter (in place), then
             // the inverse rows with no further filter: one timed middle pass.
             a2.tw4 = p->tw4;

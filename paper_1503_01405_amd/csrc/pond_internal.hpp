@@ -89,6 +89,20 @@ struct RealSplitArgs {
     int32_t log2n1, log2n2;
     const float4* tab;      // [N + 1] (W^k, M[k]) of the bin at each position, then bin N
 };
+// Real input path, fused middle pass (rows up to 2^13; see k2_real_pair).
+struct RealPairArgs {
+    void* data;             // [nblocks][n2][n1], forward column pass output, replaced in place
+    int32_t nblocks;
+    int32_t log2n2;
+    const float2* tw1;      // exp(-2 pi i t / n1), t < n1
+    const float4* tab;      // [N + 1] (four-step twiddle, M[k]) per block position; tab[N].z = M[N]
+    const float2* wk;       // [n2 + n1] exp(-i pi k2 / N), then exp(-i pi k1 / n1)
+    float scale;            // power-of-two scale of the forward row output
+};
+constexpr int kRealPairMaxLog2N1 = 13;
+hipError_t launch_real_pair(int prec, int log2n1, const RealPairArgs& a, hipStream_t s);
+hipError_t launch_real_build_pair_table(float4* tab, float2* wk, int log2n1, int log2n2, double chirp_a, double f0,
+                                        double bw, int lsb, double taper, hipStream_t s);
 hipError_t launch_k1_aip(int prec, int log2n2, const K1Args& a, hipStream_t s);
 hipError_t launch_real_split(int prec, const RealSplitArgs& a, hipStream_t s);
 hipError_t launch_k3_real(int prec, int log2n2, const K3Args& a, int grid, size_t dyn, hipStream_t s);

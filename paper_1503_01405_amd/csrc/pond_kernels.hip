@@ -547,8 +547,11 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     constexpr int L = Sh::L;
     constexpr int TPV = Sh::TPV;
     // floats per row of the power buffer: 16 + 4 pad, 16-byte aligned; REAL:
-    // two powers per column, 32 (the buffer then fills the FFT tile exactly)
+    // two powers per column, 32 with no pad (the buffer then fills the FFT
+    // tile exactly) but rotated by 4 (row mod 8) floats, so that the row
+    // reads of the epilogue spread over the banks
     constexpr int PSTRIDE = REAL ? 32 : 20;
+    auto rot = [](int row, int x) { return (x + 4 * (row & 7)) & 31; };
     __shared__ float2 lds[16 * L];
     extern __shared__ uint64_t dyn_u64[];
     uint64_t* hsum = dyn_u64;
@@ -627,7 +630,8 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             for (int e = 0; e < 16; ++e) {
                 const float2 y = cscale(v[e], a.scale);
                 if constexpr (REAL) {
-                    *reinterpret_cast<float2*>(pf + (j + TPV * e) * PSTRIDE + 2 * c) = make_float2(y.x * y.x, y.y * y.y);
+                    const int row = j + TPV * e;
+                    *reinterpret_cast<float2*>(pf + row * PSTRIDE + rot(row, 2 * c)) = make_float2(y.x * y.x, y.y * y.y);
                 } else {
                     pf[(j + TPV * e) * PSTRIDE + c] = fmaf(y.x, y.x, y.y * y.y);
                 }
@@ -645,10 +649,9 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         float pr[REAL ? 32 : 1];  // REAL: the 32 real-sample powers of the group
         if constexpr (REAL) {
             if (r0 + 16 * t + 15 < n1) {
-                const float4* row = reinterpret_cast<const float4*>(pf + q * PSTRIDE);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const float4 x4 = row[i];
+                    const float4 x4 = *reinterpret_cast<const float4*>(pf + q * PSTRIDE + rot(q, 4 * i));
                     pr[4 * i] = x4.x;
                     pr[4 * i + 1] = x4.y;
                     pr[4 * i + 2] = x4.z;
@@ -658,8 +661,8 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const int rsrc = q + ((r0 + 16 * t + i) >> a.log2n1);
-                    pr[2 * i] = rsrc < L ? pf[rsrc * PSTRIDE + 2 * i] : 0.f;
-                    pr[2 * i + 1] = rsrc < L ? pf[rsrc * PSTRIDE + 2 * i + 1] : 0.f;
+                    pr[2 * i] = rsrc < L ? pf[rsrc * PSTRIDE + rot(rsrc, 2 * i)] : 0.f;
+                    pr[2 * i + 1] = rsrc < L ? pf[rsrc * PSTRIDE + rot(rsrc, 2 * i) + 1] : 0.f;
                 }
             }
 #pragma unroll
@@ -714,9 +717,9 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         }
         if (!isfinite(s16)) flags |= 1u;
 
-        // Fold: one contribution when all 16 outputs share period, bin and
-        // sub-integration (the first and last decide, phase being monotone),
-        // otherwise one per output.
+        // Fold: one contribution when all outputs of the group share pulse,
+        // bin and sub-integration (the first and last decide, phase being
+        // monotone).
         double t0, t15;
         constexpr int G = REAL ? 32 : 16;  // fold samples of the group
         const int64_t f0i = REAL ? 2 * m0 : m0, fnf = REAL ? 2 * a.n_front : a.n_front;
@@ -727,6 +730,38 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         const int64_t sub15 = a.subint > 0 ? subint_rel(d0 + 15, a.subint, inv_s) : 0;
         if (bin0 == bin15 && t0 == t15 && sub0 == sub15) {
             fold_add(a, hsum, hcnt, sub0, bin0, s16, G, flags);
+            continue;
+        }
+        // Phase grows with the sample index, so each (pulse, bin) cell holds
+        // consecutive samples: bisect for the end of the first cell (with
+        // the per-sample float64 evaluation itself) and, if the rest of the
+        // group is one cell, add two partial sums; otherwise (a bin shorter
+        // than the group, or a sub-integration edge) one add per sample.
+        int hi = G - 1;
+        bool two = sub0 == sub15;
+        if (two) {
+            int lo = 0;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                double tm;
+                const int bm = fold_bin(f0i + mid, fnf, a.inv_pfs, a.nbins, &tm);
+                if (bm == bin0 && tm == t0) lo = mid;
+                else hi = mid;
+            }
+            double th;
+            const int bh = fold_bin(f0i + hi, fnf, a.inv_pfs, a.nbins, &th);
+            two = bh == bin15 && th == t15;
+        }
+        if (two) {
+            float sa = 0.f, sb = 0.f;
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                const float v = REAL ? pr[i] : p[i];
+                sa += i < hi ? v : 0.f;
+                sb += i < hi ? 0.f : v;
+            }
+            fold_add(a, hsum, hcnt, sub0, bin0, sa, (uint32_t)hi, flags);
+            fold_add(a, hsum, hcnt, sub0, bin15, sb, (uint32_t)(G - hi), flags);
         } else {
             for (int i = 0; i < G; ++i) {
                 double ti;
@@ -885,6 +920,200 @@ __global__ void __launch_bounds__(256) real_build_table(float4* __restrict__ tab
     double mx = cm * wt, my = (lsb ? sm : -sm) * wt;
     if (k == 0 || k == N) my = 0.0;
     tab[i] = make_float4((float)cw, (float)-sw, (float)mx, (float)my);
+}
+
+// The real path's whole middle pass in one kernel, for rows up to 2^13:
+// a workgroup takes row pairs {k2, n2 - k2} (pair 0: rows 0 and n2/2, each
+// its own partner), since bin k = k2 + n2 k1 and its partner N - k lie in
+// the two rows of one pair.  Per row: four-step twiddle, forward row FFT,
+// scale; the pair's spectra meet in LDS, each element takes its partner's
+// value and does the split, filter and recombination of real_split for its
+// own bin; then inverse row FFT, conjugate twiddle, store (in place).  The
+// block therefore crosses HBM once, as in the complex path's middle pass.
+// tab[i] = (four-step twiddle, M[k]) at block position i, tab[N].z = M[N];
+// W^k = wk[k2] wk[n2 + k1] (exp(-i pi k2 / N) and exp(-i pi k1 / n1)).
+template <int LOG2N1>
+struct K2PairShape {
+    static constexpr int L = 1 << LOG2N1;
+    static constexpr int TPV = L / 16;
+    static constexpr int ROWS = TPV >= 256 ? 2 : 256 / TPV;  // even: whole pairs
+    static constexpr int THREADS = ROWS * TPV;
+    static constexpr int STRIDE = L + L / 16;
+};
+
+template <int LOG2N1, class T>
+__global__ void __launch_bounds__(K2PairShape<LOG2N1>::THREADS) k2_real_pair(RealPairArgs a) {
+    using Sh = K2PairShape<LOG2N1>;
+    constexpr int L = Sh::L;
+    constexpr int TPV = Sh::TPV;
+    constexpr int PAIRS = Sh::ROWS / 2;
+    __shared__ float2 lds[Sh::ROWS * Sh::STRIDE];
+
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    const int n2 = 1 << a.log2n2;
+    const int npairs = n2 / 2;
+    const int pair_groups = (npairs + PAIRS - 1) / PAIRS;
+    if (logical >= pair_groups * a.nblocks) return;
+    const int pg = logical / a.nblocks;
+    const int b = logical - pg * a.nblocks;
+
+    const int r = threadIdx.x / TPV;  // LDS row slot
+    const int j = threadIdx.x - r * TPV;
+    const int side = r & 1;
+    const int pr = pg * PAIRS + (r >> 1);
+    const bool valid = pr < npairs;   // pairs beyond the last re-run it and never store
+    const int pc = min(pr, npairs - 1);
+    const int row = side == 0 ? pc : (pc == 0 ? n2 / 2 : n2 - pc);
+    const PadLds<float2> lrow{lds + r * Sh::STRIDE};
+
+    StageBases<LOG2N1> tb;
+    tb.load(j, a.tw1);
+    T* data = reinterpret_cast<T*>(a.data) + (((int64_t)b << a.log2n2) << LOG2N1);
+    const uint32_t rowoff = (uint32_t)row << LOG2N1;
+    const float4* tab = a.tab;
+
+    float2 v[16];
+    uint32_t to = opaque(rowoff + (uint32_t)j);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const float2 x = Elem<T>::load(at(data, (to + TPV * e) * (uint32_t)sizeof(T)));
+        const float4 t = *at(tab, (to + TPV * e) * 16u);
+        v[e] = cmul(x, make_float2(t.x, t.y));
+    }
+    fft_wg<LOG2N1, -1>(v, j, tb, lrow);
+
+    // The pair's spectra (scaled) to LDS, then each element reads its partner.
+    __syncthreads();
+    static_for<16>([&](auto ei) {
+        constexpr int e = decltype(ei)::value;
+        lrow.template put<TPV * e>(j, cscale(v[e], a.scale));
+    });
+    __syncthreads();
+    // partner of (row, k1): row 0 -> (0, -k1 mod n1); row n2/2 -> (n2/2,
+    // n1-1-k1); otherwise the other row of the pair at n1-1-k1
+    const int pslot = (pc == 0) ? r : (r ^ 1);
+    const PadLds<float2> prow{lds + pslot * Sh::STRIDE};
+    const uint32_t prowoff = (pc == 0 ? (uint32_t)row : (uint32_t)(n2 - row)) << LOG2N1;
+    const float2 wr = a.wk[row];
+    const float m_nyq = tab[(int64_t)1 << (LOG2N1 + a.log2n2)].z;
+    asm volatile("" ::: "memory");
+    to = opaque(rowoff + (uint32_t)j);
+    static_for<16>([&](auto ei) {
+        constexpr int e = decltype(ei)::value;
+        const int k1 = j + TPV * e;
+        const int kp = (row == 0) ? ((L - k1) & (L - 1)) : (L - 1 - k1);
+        const float2 A = lrow.template get<TPV * e>(j);
+        const float2 B = *prow.template addr<0>(kp);
+        const float4 tk = *at(tab, (to + TPV * e) * 16u);
+        const float4 tn = *at(tab, (prowoff + (uint32_t)kp) * 16u);
+        const float2 mk = make_float2(tk.z, tk.w);
+        const float2 mn = (row == 0 && k1 == 0) ? make_float2(m_nyq, 0.f) : make_float2(tn.z, tn.w);
+        const float2 w = cmul(wr, a.wk[n2 + k1]);
+        const float2 E = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
+        const float2 D = make_float2(0.5f * (A.x - B.x), 0.5f * (A.y + B.y));
+        const float2 O = make_float2(D.y, -D.x);
+        const float2 wo = cmul(w, O);
+        const float2 yk = cmul(cadd(E, wo), mk);
+        const float2 en = csub(E, wo);
+        const float2 yn = cmul(make_float2(en.x, -en.y), mn);
+        const float2 ync = make_float2(yn.x, -yn.y);
+        const float2 e2 = cscale(cadd(yk, ync), 0.5f);
+        const float2 o2 = cmulc(cscale(csub(yk, ync), 0.5f), w);
+        v[e] = make_float2(e2.x - o2.y, e2.y + o2.x);
+    });
+    fft_wg<LOG2N1, +1>(v, j, tb, lrow);
+    asm volatile("" ::: "memory");
+    to = opaque(rowoff + (uint32_t)j);
+    if (valid) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float4 t = *at(tab, (to + TPV * e) * 16u);
+            Elem<T>::store(at(data, (to + TPV * e) * (uint32_t)sizeof(T)), cmulc(v[e], make_float2(t.x, t.y)));
+        }
+    }
+}
+
+// Table of k2_real_pair: tab[i] = (W_N^(k1 k2), M[k]) at block position i
+// (row k2, column k1, bin k = k2 + n2 k1), tab[N] = (0, 0, M[N], 0);
+// wk[k2] = exp(-i pi k2 / N) for k2 < n2, wk[n2 + k1] = exp(-i pi k1 / n1).
+// M as real_build_table (float64, reduced mod 1 turn).
+__global__ void __launch_bounds__(256) real_build_pair_table(float4* __restrict__ tab, float2* __restrict__ wk,
+                                                              int log2n1, int log2n2, double chirp_a, double f0,
+                                                              double bw, int lsb, double taper) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
+    const int64_t N = 1ll << log2n, n1 = 1ll << log2n1, n2 = 1ll << log2n2;
+    if (i > N) return;
+    const int64_t k2 = i >> log2n1, k1 = i & (n1 - 1);
+    const int64_t k = i == N ? N : k2 + (k1 << log2n2);
+    const double fb = (double)k * bw / (double)N;
+    const double f = lsb ? bw * 0.5 - fb : fb - bw * 0.5;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double sm, cm;
+    sincospi(2.0 * frac, &sm, &cm);
+    const double wt = taper_w(f, bw, taper);
+    double mx = cm * wt, my = (lsb ? sm : -sm) * wt;
+    if (k == 0 || k == N) my = 0.0;
+    if (i == N) {
+        tab[i] = make_float4(0.f, 0.f, (float)mx, 0.f);
+        return;
+    }
+    double st, ct;
+    sincospi(2.0 * (double)((k1 * k2) & (N - 1)) / (double)N, &st, &ct);
+    tab[i] = make_float4((float)ct, (float)-st, (float)mx, (float)my);
+    if (i < n2) {
+        double s2, c2;
+        sincospi((double)i / (double)N, &s2, &c2);
+        wk[i] = make_float2((float)c2, (float)-s2);
+    }
+    if (i < n1) {
+        double s1, c1;
+        sincospi((double)i / (double)n1, &s1, &c1);
+        wk[n2 + i] = make_float2((float)c1, (float)-s1);
+    }
+}
+
+template <class T, int LOG2N1>
+static hipError_t real_pair_one(const RealPairArgs& a, hipStream_t s) {
+    using Sh = K2PairShape<LOG2N1>;
+    const int npairs = (1 << a.log2n2) / 2;
+    const int groups = (npairs + Sh::ROWS / 2 - 1) / (Sh::ROWS / 2) * a.nblocks;
+    const int grid = (groups + 7) & ~7;
+    hipLaunchKernelGGL((k2_real_pair<LOG2N1, T>), dim3(grid), dim3(Sh::THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t real_pair_dispatch(int log2n1, const RealPairArgs& a, hipStream_t s) {
+    switch (log2n1) {
+        case 5: return real_pair_one<T, 5>(a, s);
+        case 6: return real_pair_one<T, 6>(a, s);
+        case 7: return real_pair_one<T, 7>(a, s);
+        case 8: return real_pair_one<T, 8>(a, s);
+        case 9: return real_pair_one<T, 9>(a, s);
+        case 10: return real_pair_one<T, 10>(a, s);
+        case 11: return real_pair_one<T, 11>(a, s);
+        case 12: return real_pair_one<T, 12>(a, s);
+        case 13: return real_pair_one<T, 13>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_real_pair(int prec, int log2n1, const RealPairArgs& a, hipStream_t s) {
+    switch (prec) {
+        case kFp32: return real_pair_dispatch<float2>(log2n1, a, s);
+        case kMixedValu: return real_pair_dispatch<__half2>(log2n1, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_real_build_pair_table(float4* tab, float2* wk, int log2n1, int log2n2, double chirp_a, double f0,
+                                        double bw, int lsb, double taper, hipStream_t s) {
+    const int64_t n = (1ll << (log2n1 + log2n2)) + 1;
+    hipLaunchKernelGGL(real_build_pair_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, wk, log2n1,
+                       log2n2, chirp_a, f0, bw, lsb, taper);
+    return hipGetLastError();
 }
 
 template <class T>
