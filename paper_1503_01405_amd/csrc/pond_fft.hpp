@@ -341,14 +341,28 @@ struct StageBases<LOG2L, h2> : StageBases<LOG2L, float2> {};
 // index in the vector).  put<D>(p0, x) / get<D>(p0) access position p0 + D
 // for a compile-time D, so that D's part of the address is an immediate.
 // Columns interleaved by 16 (K1/K3 tiles): index = pos * 16 (from the
-// column's base).
-template <class V>
+// column's base).  PAD adds four spare slots per four positions (index =
+// 16 pos + 4 (pos / 4)): the first stage's stores, 16 positions apart in
+// the four column groups of a wave, then fall in different banks, and the
+// other accesses stay contiguous.  The split p0 + D -> idx(p0) + idx(D)
+// holds when D is a multiple of 4, or when p0 is (AL).
+template <class V, bool PAD = false>
 struct ColLds {
     V* base;
+    static constexpr uint32_t kSlots(uint32_t n) { return PAD ? n * 16 + 4 * (n / 4) : n * 16; }
+    static __device__ __forceinline__ uint32_t idx(uint32_t p) { return PAD ? p * 16 + 4 * (p >> 2) : p * 16; }
     template <int D, bool AL = false>
-    __device__ __forceinline__ void put(int p0, V x) const { base[(p0 + D) * 16] = x; }
+    __device__ __forceinline__ V* addr(int p0) const {
+        if constexpr (!PAD || D % 4 == 0 || AL) {
+            return base + idx((uint32_t)p0) + kSlots(D);
+        } else {
+            return base + idx((uint32_t)(p0 + D));
+        }
+    }
+    template <int D, bool AL = false>
+    __device__ __forceinline__ void put(int p0, V x) const { *addr<D, AL>(p0) = x; }
     template <int D>
-    __device__ __forceinline__ V get(int p0) const { return base[(p0 + D) * 16]; }
+    __device__ __forceinline__ V get(int p0) const { return *addr<D>(p0); }
 };
 // One row with a pad slot per 16 values (K2): index = pos + pos / 16.  The
 // split p0 + D -> (p0 + p0/16) + (D + D/16) holds when D is a multiple of 16,

@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     constexpr int BPE = AIP ? 4 : 2;  // input bytes per element
     constexpr int L = 1 << LOG2N2;
     constexpr int TPV = L / 16;
-    __shared__ LdsVal<FORM> lds[16 * L];
+    __shared__ LdsVal<FORM> lds[ColLds<LdsVal<FORM>, true>::kSlots(L)];
 
     const int n1 = 1 << a.log2n1;
     const int tiles_per_block = n1 >> 4;
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
             const h2 x = {(_Float16)(int8_t)(s & 0xff), (_Float16)(int8_t)(s >> 8)};
             v[e] = x * (_Float16)0.0625f;
         }
-        fft_wg<LOG2N2, -1, true>(v, j, tb, ColLds<h2>{lds + c});
+        fft_wg<LOG2N2, -1, true>(v, j, tb, ColLds<h2, true>{lds + c});
         constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N2>::kHalfRem);
         const uint32_t w0 = opaque((uint32_t)col);
 #pragma unroll
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
             float2 v[16];
 #pragma unroll
             for (int e = 0; e < 16; ++e) v[e] = load_in(j + TPV * e);
-            fft_wg<LOG2N2, -1>(v, j, tb, ColLds<float2>{lds + c});
+            fft_wg<LOG2N2, -1>(v, j, tb, ColLds<float2, true>{lds + c});
             const uint32_t w0 = opaque((uint32_t)col);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
@@ -601,7 +601,8 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 #pragma unroll
             for (int e = 0; e < 16; ++e)
                 v[e] = ld_h2(at(in, (o0 + ((uint32_t)(j + TPV * e) << a.log2n1)) * (uint32_t)sizeof(T)));
-            fft_wg<LOG2N2, +1>(v, j, tb, ColLds<h2>{lh + c});
+            static_assert(ColLds<h2, true>::kSlots(L) * sizeof(h2) <= sizeof(float2) * 16 * L, "padded tile fits");
+            fft_wg<LOG2N2, +1>(v, j, tb, ColLds<h2, true>{lh + c});
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
