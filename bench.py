@@ -76,6 +76,28 @@ def algorithmic_bytes(kernel, blocks, elem, nfft, hop):
     return 0
 
 
+def copy_bandwidth(nbytes=1 << 31, reps=10):
+    """Achievable HBM bandwidth (GB/s, bytes read + written) of the
+    library's own streaming copy kernel over nbytes, event-timed."""
+    import torch
+    import paper_1503_01405_amd as P
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    P.pond_copy_device(dst, src, nbytes, s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        P.pond_copy_device(dst, src, nbytes, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
 def kernel_source_hash():
     """sha256[:16] over the HIP/C++ sources of the library (as recorded in
     the committed rocprofv3 summaries)."""
@@ -633,6 +655,7 @@ def main_real(args):
                   for f, r in res.items()},
         "roofline": dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                          frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                         copy_achievable=round(copy_bandwidth(), 1),
                          algorithmic_bytes_per_launch=int(algo / max(launches, 1)),
                          avg_launch_us=round(ms / max(launches, 1) * 1e3, 2)),
     }
@@ -724,8 +747,11 @@ def main():
     achieved = algo / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     avg_s = ms / 1e3 / max(launches, 1)
     meas = measured_traffic(dom, head) if head != "fp32" else None
+    copy_gbs = copy_bandwidth()
+    log(f"library streaming copy: {copy_gbs:.0f} GB/s")
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
+                copy_achievable=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4),
                 traffic=round(meas / avg_s / 1e9, 1) if meas else None,
                 traffic_bytes_per_launch=meas,
                 algorithmic_bytes_per_launch=int(algo / max(launches, 1)),

@@ -431,6 +431,16 @@ int64_t pond_aid_run(pond_aid* a, const int8_t* iq, int64_t nsamp, float* profil
 /* Destroy (NULL-safe); waits for the last call's work. */
 void pond_aid_destroy(pond_aid* a);
 
+/*
+ * Device-to-device copy of `bytes` (a multiple of 16; dst and src device
+ * pointers, 16-byte aligned, not overlapping) with the library's own
+ * streaming kernel, asynchronous on hip_stream.  For measurement: the
+ * bandwidth it reaches is the achievable HBM rate that the kernels' byte
+ * counts are set against, beside the device's nominal peak.  Returns POND_OK,
+ * POND_EINVAL or POND_EDEVICE.
+ */
+int32_t pond_copy_device(void* dst, const void* src, int64_t bytes, void* hip_stream);
+
 /* Static text for a return code. */
 const char* pond_strerror(int64_t code);
 

@@ -295,6 +295,18 @@ extern "C" {
 
 int32_t pond_create_status(void) { return g_create_status; }
 
+int32_t pond_copy_device(void* dst, const void* src, int64_t bytes, void* hip_stream) {
+    if (bytes < 0 || (bytes > 0 && (!dst || !src))) return POND_EINVAL;
+    if ((bytes & 15) || (reinterpret_cast<uintptr_t>(dst) & 15) || (reinterpret_cast<uintptr_t>(src) & 15))
+        return POND_EINVAL;
+    const hipError_t e = launch_copy_u128(dst, src, bytes / 16, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return POND_EDEVICE;
+    }
+    return POND_OK;
+}
+
 const char* pond_strerror(int64_t code) {
     switch (code) {
         case POND_OK: return "ok";

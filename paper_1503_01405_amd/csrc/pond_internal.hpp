@@ -138,6 +138,7 @@ hipError_t launch_fold_reduce(const uint64_t* part_sum, const uint32_t* part_cnt
                               uint64_t* acc_sum, uint64_t* acc_cnt, int64_t acc_off, hipStream_t s);
 hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins, int n_complete, int n_touched,
                                 float* profiles, hipStream_t s);
+hipError_t launch_copy_u128(void* dst, const void* src, int64_t n16, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
                                  double taper, hipStream_t s);

@@ -842,6 +842,29 @@ __global__ void __launch_bounds__(256) fold_profiles(const uint64_t* acc_sum, co
     profiles[i] = c ? (float)(((double)acc_sum[i] / kFoldScale) / (double)c) : 0.f;
 }
 
+// Streaming copy of n16 16-byte words (measurement of the achievable HBM
+// bandwidth): each workgroup moves contiguous 16 KB chunks, a thread's four
+// loads of a chunk in flight before its stores.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) copy_u128(u32x4* __restrict__ dst, const u32x4* __restrict__ src,
+                                                 int64_t n16) {
+    constexpr int U = 4;
+    constexpr int64_t kChunk = 256 * U;
+    for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n16; base += (int64_t)gridDim.x * kChunk) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = base + u * 256 + threadIdx.x;
+            v[u] = k < n16 ? src[k] : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = base + u * 256 + threadIdx.x;
+            if (k < n16) dst[k] = v[u];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) zero_u64(uint64_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -1489,6 +1512,15 @@ hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chi
     const int64_t n = 1ll << (log2n1 + log2n2);
     hipLaunchKernelGGL(k2_build_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n1, log2n2,
                        chirp_a, f0, df, taper);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u128(void* dst, const void* src, int64_t n16, hipStream_t s) {
+    if (n16 <= 0) return hipSuccess;
+    const int64_t chunks = (n16 + 1023) / 1024;
+    const unsigned grid = (unsigned)(chunks < 16384 ? chunks : 16384);
+    hipLaunchKernelGGL(copy_u128, dim3(grid), dim3(256), 0, s, reinterpret_cast<u32x4*>(dst),
+                       reinterpret_cast<const u32x4*>(src), n16);
     return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ EXPORTS = (
     "pond_server_destroy",
     "pond_aid_create", "pond_aid_geometry", "pond_aid_run", "pond_aid_destroy",
     "pond_real_plan_create", "pond_real_dedisperse", "pond_real_expect",
+    "pond_copy_device",
 )
 KERNEL_NAMES = ("k1_unpack_colfft", "k2_row", "k3_colinv_detect_fold", "fold_reduce", "fold_finalize")
 
@@ -167,6 +168,8 @@ def _load():
     lib.pond_real_dedisperse.restype = i64
     lib.pond_real_expect.argtypes = [P, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.pond_real_expect.restype = i32
+    lib.pond_copy_device.argtypes = [P, P, i64, P]
+    lib.pond_copy_device.restype = i32
     lib.pond_strerror.argtypes = [i64]
     lib.pond_strerror.restype = ctypes.c_char_p
     return lib
@@ -292,6 +295,13 @@ def pond_real_expect(plan, nsamp, subint_nsamp):
     if r != POND_OK:
         raise PondError(r, "pond_real_expect")
     return a.value, b.value
+
+
+def pond_copy_device(dst, src, nbytes, stream=None):
+    """The library's streaming device copy (for bandwidth measurement)."""
+    r = _lib.pond_copy_device(_ptr(dst), _ptr(src), int(nbytes), _stream(stream))
+    if r != POND_OK:
+        raise PondError(r, "pond_copy_device")
 
 
 def pond_search_create(f0_mhz, bw_mhz, dms, nbins, period_s, nfft_min=1 << 20, nfft_max=1 << 23,

@@ -58,6 +58,35 @@ def test_null_plan_calls():
     assert lib.pond_plan_expect(None, 0, 0, None, None) == B.POND_EINVAL
     lib.pond_plan_destroy(None)
     assert lib.pond_strerror(B.POND_EDEVICE)
+    assert lib.pond_real_dedisperse(None, None, 0, 0, None, 0, 32, None, 0, None, None) == B.POND_EINVAL
+    assert lib.pond_real_expect(None, 0, 0, None, None) == B.POND_EINVAL
+    assert lib.pond_aid_run(None, None, 0, None, None, 0, None) == B.POND_EINVAL
+
+
+def test_copy_arguments_are_checked_before_device_work():
+    import paper_1503_01405_amd.pond as B
+    lib = B.lib()
+    assert lib.pond_copy_device(None, None, 0, None) == B.POND_OK          # nothing to copy
+    assert lib.pond_copy_device(None, None, 16, None) == B.POND_EINVAL      # null pointers
+    assert lib.pond_copy_device(4096, 8192, 15, None) == B.POND_EINVAL      # not whole 16-byte words
+    assert lib.pond_copy_device(4104, 8192, 16, None) == B.POND_EINVAL      # misaligned destination
+    assert lib.pond_copy_device(4096, 8200, 16, None) == B.POND_EINVAL      # misaligned source
+    assert lib.pond_copy_device(4096, 8192, -16, None) == B.POND_EINVAL
+
+
+@pytest.mark.parametrize("args", [
+    (326.5, 16.0, 1.0, 1 << 20, 256, 0.0891, 0, 0, 5),           # no such sideband
+    (326.5, 16.0, 1.0, (1 << 20) + 2, 256, 0.0891, 0, 0, 0),     # real block not a power of two
+    (326.5, 16.0, 1.0, 1 << 10, 256, 0.0891, 0, 0, 0),           # packed length below 2^10
+    (326.5, 16.0, 1.0, 1 << 20, 256, 0.0891, 1, 0, 1),           # matrix-core form not offered
+    (326.5, 16.0, 1.0, 1 << 20, 256, 0.0891, 3, 0, 1),           # packed float16 form not offered
+    (326.5, 16.0, 200.0, 1 << 21, 256, 0.0891, 0, 0, 0),         # smear longer than the block
+])
+def test_invalid_real_plans_are_rejected_before_device_work(args):
+    import paper_1503_01405_amd.pond as B
+    lib = B.lib()
+    assert not lib.pond_real_plan_create(*args)
+    assert lib.pond_create_status() == B.POND_EINVAL
 
 
 def test_library_shares_torchs_hip_runtime():

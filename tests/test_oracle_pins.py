@@ -479,3 +479,33 @@ def test_real_path_recovers_a_pulse_lsb():
     assert abs(int(np.argmax(prof)) - 32) <= 1
     r0 = O.run_real(raw, 326.5, 16.0, 2.0, 1 << 19, 64, period, sideband="usb", decim=32)
     assert prof.max() / np.median(prof) > 1.5 * r0["profiles"][0].max() / np.median(r0["profiles"][0])
+
+
+# ----------------------------------------- negative control: phase precision
+def test_float32_chirp_phase_is_far_outside_the_profile_bound():
+    """The chirp phase reaches about 3.7e5 turns at the band edge at DM 50,
+    where a float32 phase (turns evaluated in float32, not reduced in
+    float64) is off by hundredths of a turn: a dedispersion with it misses
+    the float64 result by far more than the 1e-4 profile bound, which is why
+    the phase is evaluated in float64 everywhere.  (The planted float32 phase
+    lives in this test only.)"""
+    nfft, dm = 1 << 16, 50.0
+    f = O.baseband_freqs_mhz(nfft, 16.0)
+    turns64 = O.chirp_turns(f, 326.5, dm)
+    assert np.abs(turns64).max() > 3e5
+    f32 = f.astype(np.float32)
+    turns32 = (np.float32(dm) * f32 * f32 / (np.float32(2.41e-10) * np.float32(326.5) ** 2
+                                               * (np.float32(326.5) + f32))).astype(np.float64)
+    c64 = np.exp(-2j * np.pi * turns64)
+    c32 = np.exp(-2j * np.pi * turns32)
+    assert np.abs(np.angle(c32 / c64)).max() > 1e-2
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=nfft) + 1j * rng.normal(size=nfft)
+    y64 = np.fft.ifft(np.fft.fft(x) * c64)
+    y32 = np.fft.ifft(np.fft.fft(x) * c32)
+    p64, p32 = np.abs(y64) ** 2, np.abs(y32) ** 2
+    series_err = np.linalg.norm(p32 - p64) / np.linalg.norm(p64)
+    assert series_err > 1e-2, series_err
+    # the float64 phase reduced mod 1 turn reproduces the unreduced one
+    frac = turns64 - np.rint(turns64)
+    assert np.allclose(np.exp(-2j * np.pi * frac), c64, atol=1e-9)
