@@ -489,14 +489,41 @@ __device__ __forceinline__ void stockham_stage(V (&v)[16], int j, V base, const 
     });
 }
 
+// The float16 twiddles of stage 1 of a transform of length >= 2^8 (radix
+// 16, NS = 16) come in 16 sets only (k = j mod 16).  A workgroup forms them
+// once (threads 0..15, with stage_tw_h) into an LDS table of 16 rows of 16
+// pairs at a stride of 20 pairs: the 16-byte reads of the 16 rows then fall
+// in distinct banks.  Every transform of the workgroup reads its row.
+constexpr int kS1Stride = 20;
+constexpr int kS1Pairs = 16 * kS1Stride;
+template <int LOG2L>
+constexpr bool kS1Tabled = LOG2L >= 8;
+template <int LOG2L>
+__device__ __forceinline__ void fill_stage1_table(h2* tab, const float2* __restrict__ tw, int tid) {
+    if constexpr (kS1Tabled<LOG2L>) {
+        if (tid < 16) {
+            h2 t[16];
+            stage_tw_h<LOG2L, 1>(tw[tid * ((1 << LOG2L) / 256)], t);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) tab[tid * kS1Stride + q] = t[q];
+        }
+        // keep the caller's first loads after the table work, so that their
+        // registers and the table's temporaries are not live together
+        asm volatile("" ::: "memory");
+    }
+}
+
 // Full length-L transform (DIR = -1 forward, +1 inverse, unnormalised) of
 // the vector held by thread j.  lds is the vector's LDS layout (ColLds or
 // PadLds); every thread of the workgroup must call this together
 // (it contains barriers).  With HALF_NORM (float16 forward transforms)
 // every even stage but the first scales its input by 1/16 (the caller
 // scales the first stage's input and applies the remaining 2^-kHalfRem).
-template <int LOG2L, int DIR, bool HALF_NORM = false, class V, class Lds>
-__device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L, V>& tb, const Lds& lds) {
+// Float16 transforms of length >= 2^8 with S1 read their stage-1 twiddles
+// from the table s1tab (fill_stage1_table).
+template <int LOG2L, int DIR, bool HALF_NORM = false, bool S1 = false, class V, class Lds>
+__device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L, V>& tb, const Lds& lds,
+                                       const h2* s1tab = nullptr) {
     using S = Sched<LOG2L>;
     constexpr int L = 1 << LOG2L;
     constexpr int TPV = L / 16;
@@ -511,7 +538,17 @@ __device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L
         h2 tw[16];
         if constexpr (HALF) {
             base = cone<V>();
-            if constexpr (NS > 1) {
+            if constexpr (S1 && s == 1 && kS1Tabled<LOG2L>) {
+                const uint4* row = reinterpret_cast<const uint4*>(s1tab + (j & 15) * kS1Stride);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint4 x = row[i];
+                    tw[4 * i] = __builtin_bit_cast(h2, x.x);
+                    tw[4 * i + 1] = __builtin_bit_cast(h2, x.y);
+                    tw[4 * i + 2] = __builtin_bit_cast(h2, x.z);
+                    tw[4 * i + 3] = __builtin_bit_cast(h2, x.w);
+                }
+            } else if constexpr (NS > 1) {
                 float2 b = tb.b[s];
                 asm volatile("" : "+v"(b.x), "+v"(b.y));  // recompute per use, not hoisted
                 stage_tw_h<LOG2L, s>(b, tw);

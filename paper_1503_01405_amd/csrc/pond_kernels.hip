@@ -107,6 +107,8 @@ __device__ __forceinline__ void st_h2(__half2* p, h2 v) { *reinterpret_cast<h2*>
 // AIP: the input is two real-sampled channels interleaved (A0 B0 A1 B1 ...);
 // element m packs the added-in-phase samples 2m and 2m+1 as (re, im), so a
 // block of 2N real samples is read as N complex elements of 4 bytes.
+// The packed-float16 tile (about 69 KB at n2 = 2^10) lets two workgroups
+// share a CU, if each thread stays within 64 registers.
 template <int LOG2N2, class T, int FORM, bool AIP = false>
 __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     constexpr int BPE = AIP ? 4 : 2;  // input bytes per element
@@ -299,6 +301,8 @@ k2_row(K2Args a) {
     T* dst = MODE == kRowInv ? reinterpret_cast<T*>(a.out) + rowbase : rows;
 
     if constexpr (F16) {
+        __shared__ h2 s1tab[kS1Pairs];
+        fill_stage1_table<LOG2N1>(s1tab, a.tw1, threadIdx.x);
         const uint2* tab = reinterpret_cast<const uint2*>(a.htable) + ((int64_t)row0 << LOG2N1);
         const h2* tw4 = reinterpret_cast<const h2*>(a.htw4) + ((int64_t)row0 << LOG2N1);
         const h2* chirp = reinterpret_cast<const h2*>(a.hchirp) + ((int64_t)row0 << LOG2N1);
@@ -315,7 +319,7 @@ k2_row(K2Args a) {
             if constexpr (MODE == kRowInv) v[e] = cmul(x, *at(chirp, i * 4u));
             else v[e] = cmul(x, tw_at(i));
         }
-        if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true>(v, j, tb, lrow);
+        if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true, true>(v, j, tb, lrow, s1tab);
         if constexpr (MODE == kRowFwd) {
             constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N1>::kHalfRem);
             if (valid) {
@@ -332,7 +336,7 @@ k2_row(K2Args a) {
             for (int e = 0; e < 16; ++e)
                 v[e] = cmul(v[e], __builtin_bit_cast(h2, at(tab, (to + TPV * e) * 8u)->y));
         }
-        fft_wg<LOG2N1, +1>(v, j, tb, lrow);
+        fft_wg<LOG2N1, +1, false, true>(v, j, tb, lrow, s1tab);
         asm volatile("" ::: "memory");
         to = opaque(toff);
         if (valid) {
@@ -582,6 +586,15 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     uint32_t flags = 0;
     StageBases<LOG2N2, LdsVal<FORM>> tb;
     tb.load(j, a.tw2);
+    // packed float16: the stage-1 twiddle table sits past the largest use of
+    // the buffer by the tile (16 L padded pairs) and the power rows
+    h2* s1tab = reinterpret_cast<h2*>(lds) + (sizeof(float2) * 16 * L / sizeof(h2) - kS1Pairs);
+    if constexpr (FORM == kFormF16) {
+        static_assert(PSTRIDE * L * sizeof(float) <= sizeof(float2) * 16 * L - kS1Pairs * sizeof(h2), "table clear");
+        static_assert(ColLds<h2, true>::kSlots(L) * sizeof(h2) <= sizeof(float2) * 16 * L - kS1Pairs * sizeof(h2),
+                      "table clear of the tile");
+        fill_stage1_table<LOG2N2>(s1tab, a.tw2, threadIdx.x);
+    }
 
     for (int item = xcd * chunk + local; item < it_end; item += per_xcd) {
         const int b = item / tiles_per_block;
@@ -602,7 +615,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             for (int e = 0; e < 16; ++e)
                 v[e] = ld_h2(at(in, (o0 + ((uint32_t)(j + TPV * e) << a.log2n1)) * (uint32_t)sizeof(T)));
             static_assert(ColLds<h2, true>::kSlots(L) * sizeof(h2) <= sizeof(float2) * 16 * L, "padded tile fits");
-            fft_wg<LOG2N2, +1>(v, j, tb, ColLds<h2, true>{lh + c});
+            fft_wg<LOG2N2, +1, false, true>(v, j, tb, ColLds<h2, true>{lh + c}, s1tab);
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
