@@ -794,7 +794,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
                 if (r == hipSuccess) r = launch_real_split(p->precision, rs, stream);
                 K2Args ai = a2;
                 ai.scale = 1.0f;
-                if (r == hipSuccess) r = launch_k2(p->precision, kRowInv, p->log2n1, ai, stream);
+                if (r == hipSuccess) r = launch_k2(p->precision, kRowInvPlain, p->log2n1, ai, stream);
                 return r;
             });
         } else {

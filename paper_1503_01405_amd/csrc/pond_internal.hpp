@@ -32,7 +32,9 @@ struct K1Args {
 
 // K2: four-step twiddle, forward row FFT (length n1), chirp, inverse row
 // FFT, conjugate twiddle.
-enum RowMode { kRowFull = 0, kRowFwd = 1, kRowInv = 2 };
+// kRowInvPlain: kRowInv with no filter (float32 arithmetic forms; the real
+// input path's longest rows, filtered by real_split before).
+enum RowMode { kRowFull = 0, kRowFwd = 1, kRowInv = 2, kRowInvPlain = 3 };
 
 struct K2Args {
     void* work;             // rows, in place (kRowFull, kRowFwd)

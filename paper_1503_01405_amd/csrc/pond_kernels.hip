@@ -262,6 +262,7 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 //                  spectrum, row k2 holding bins k2 + n2 k1 (float2 twiddle table).
 //   MODE kRowInv:  spectrum (in) times one trial's chirp (float2 table),
 //                  inverse FFT, conjugate twiddle, to `out`.
+//   MODE kRowInvPlain: kRowInv without the chirp (float32 arithmetic only).
 // F16: packed float16 arithmetic on float16 storage with float16 tables
 // (kRowFull: 4 halves per entry, twiddle/16 and chirp*2^-kHalfRem; split
 // modes: twiddle/16 and chirp).  The forward transform is normalised stage
@@ -297,8 +298,9 @@ k2_row(K2Args a) {
     const uint32_t toff = (uint32_t)(min(r, n2 - 1 - row0) << LOG2N1) + (uint32_t)j;
     const int64_t rowbase = (((int64_t)b << a.log2n2) + row0) << LOG2N1;
     T* rows = reinterpret_cast<T*>(a.work) + rowbase;
-    const T* src = MODE == kRowInv ? reinterpret_cast<const T*>(a.in) + rowbase : rows;
-    T* dst = MODE == kRowInv ? reinterpret_cast<T*>(a.out) + rowbase : rows;
+    constexpr bool INV = MODE == kRowInv || MODE == kRowInvPlain;
+    const T* src = INV ? reinterpret_cast<const T*>(a.in) + rowbase : rows;
+    T* dst = INV ? reinterpret_cast<T*>(a.out) + rowbase : rows;
 
     if constexpr (F16) {
         __shared__ h2 s1tab[kS1Pairs];
@@ -361,12 +363,13 @@ k2_row(K2Args a) {
                 v[e] = cmul(x, make_float2(t.x, t.y));
             } else if constexpr (MODE == kRowFwd) {
                 v[e] = cmul(x, *at(tw4, (to + TPV * e) * 8u));
+            } else if constexpr (MODE == kRowInv) {
+                v[e] = cmul(x, *at(chirp, (to + TPV * e) * 8u));
             } else {
-                // no chirp table: the filter was applied before (real input path)
-                v[e] = a.chirp ? cmul(x, *at(chirp, (to + TPV * e) * 8u)) : x;
+                v[e] = x;  // kRowInvPlain: the filter was applied before (real input path)
             }
         }
-        if constexpr (MODE != kRowInv) {
+        if constexpr (MODE != kRowInv && MODE != kRowInvPlain) {
             fft_wg<LOG2N1, -1>(v, j, tb, lrow);
         }
         if constexpr (MODE == kRowFull) {
@@ -1414,6 +1417,11 @@ hipError_t launch_k2(int prec, int mode, int log2n1, const K2Args& a, hipStream_
         case kRowFull: return k2_prec<kRowFull>(prec, log2n1, a, s);
         case kRowFwd: return k2_prec<kRowFwd>(prec, log2n1, a, s);
         case kRowInv: return k2_prec<kRowInv>(prec, log2n1, a, s);
+        case kRowInvPlain:
+            // float32 arithmetic forms only (the real input path)
+            if (prec == kFp32) return k2_dispatch<float2, kRowInvPlain, false>(log2n1, a, s);
+            if (prec == kMixedValu) return k2_dispatch<__half2, kRowInvPlain, false>(log2n1, a, s);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
