@@ -203,3 +203,37 @@ def test_real_api():
         P.pond_real_plan_create(F0, BW, 3.1, (1 << 20) + 2, 64, 3.3e-2, P.POND_FP32, 0, "lsb")
     with pytest.raises(P.PondError):
         P.pond_real_plan_create(F0, BW, 3.1, 1 << 20, 64, 3.3e-2, P.POND_FP32, 0, 7)
+
+
+def test_real_full_stream_sampled_blocks():
+    """The 60 s real stream as the benchmark times it (1.92e9 real samples,
+    real blocks of 2^24 at DM 50, one call): the series of the first,
+    a middle and the last block against the oracle's real path run on just
+    that block's input."""
+    import torch
+    import paper_1503_01405_amd as P
+    nfft, dm, nsamp, decim = 1 << 24, 50.0, 1_920_000_000, 32
+    print("case: real full stream 60 s", flush=True)
+    raw = synth.pulsed_stream_int8(2, nsamp, fs_hz=2 * BW * 1e6, sigma=synth.SIGMA / 2 ** 0.5)
+    x = torch.from_numpy(raw).to("cuda")
+    res = {}
+    for precision in ("mixed_valu", "fp32"):
+        plan = P.Plan(F0, BW, dm, nfft, 1024, 0.0891, precision=precision, subint_nsamp=320_000_000,
+                      decim=decim, sideband="lsb")
+        hop_r = plan.info()["hop"]
+        _, ser = plan.process(x)
+        plan.flush(device=x.device)
+        torch.cuda.synchronize()
+        res[precision] = ser.cpu().numpy()
+        plan.close()
+    del x
+    nb = (nsamp - nfft) // hop_r + 1
+    for b in (0, nb // 2, nb - 1):
+        r = O.run_real(raw[2 * b * hop_r:2 * (b * hop_r + nfft)], F0, BW, dm, nfft // 2, 1024, 0.0891,
+                       sideband="lsb", decim=decim)
+        want = r["series"]
+        for precision, ser in res.items():
+            got = ser[b * hop_r // decim:(b + 1) * hop_r // decim]
+            e = rel_l2(got, want)
+            print(f"block {b} {precision}: series rel-L2 {e:.3e}", flush=True)
+            assert e <= TOL[precision][1], (b, precision, e)
