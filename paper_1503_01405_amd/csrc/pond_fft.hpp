@@ -386,6 +386,48 @@ struct PadLds {
     __device__ __forceinline__ V get(int p0) const { return *addr<D>(p0); }
 };
 // For a last stage, whose outputs stay in registers.
+// Row layouts for float16 rows of 2^12 .. 2^14 (K2), chosen per stage so
+// that the stage's stores and the following reads (runs of 64 consecutive
+// positions per wave) both avoid bank conflicts (64 banks of 4 bytes):
+// stage 0 (stores 16 positions apart) at p + p/64, stage 1 (runs of 16
+// stores, 256 apart) at p + 16 (p/256), later stages (contiguous stores)
+// at p.  Each fits in L + L/16 slots.  Use: stage_view<s>(lds).
+template <class V>
+struct StageRowLds {
+    V* base;
+    template <int S>
+    struct At {
+        V* base;
+        static constexpr uint32_t idx(uint32_t p) { return S == 0 ? p + (p >> 6) : S == 1 ? p + 16 * (p >> 8) : p; }
+        // idx(p0 + D) = idx(p0) + idx(D) for D a multiple of the layout's
+        // period, and for the stage's own stores: stage 0 (AL: p0 a
+        // multiple of 16, D < 16) and stage 1 (p0 mod 256 < 16, D <= 240).
+        template <int D, bool AL = false>
+        __device__ __forceinline__ V* addr(int p0) const {
+            constexpr int period = S == 0 ? 64 : (S == 1 ? 256 : 1);
+            if constexpr (D % period == 0 || (S == 0 && AL && D < 16) || (S == 1 && D <= 240)) {
+                return base + idx((uint32_t)p0) + idx((uint32_t)D);
+            } else {
+                return base + idx((uint32_t)(p0 + D));
+            }
+        }
+        template <int D, bool AL = false>
+        __device__ __forceinline__ void put(int p0, V x) const { *addr<D, AL>(p0) = x; }
+        template <int D>
+        __device__ __forceinline__ V get(int p0) const { return *addr<D>(p0); }
+    };
+    template <int S>
+    __device__ __forceinline__ At<S> stage() const { return At<S>{base}; }
+};
+
+// The layout a stage uses: the accessor itself, or its per-stage view.
+template <int S, class Lds>
+__device__ __forceinline__ Lds stage_view(const Lds& l) { return l; }
+template <int S, class V>
+__device__ __forceinline__ typename StageRowLds<V>::template At<S> stage_view(const StageRowLds<V>& l) {
+    return l.template stage<S>();
+}
+
 template <class V>
 struct NoLds {
     template <int D, bool AL = false>
@@ -557,12 +599,13 @@ __device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L
             base = tb.b[s];
         }
         if constexpr (!LAST) {
+            const auto st = stage_view<s>(lds);
             __syncthreads();
-            stockham_stage<L, R, NS, DIR, false, SC>(v, j, base, lds, tw);
+            stockham_stage<L, R, NS, DIR, false, SC>(v, j, base, st, tw);
             __syncthreads();
             static_for<16>([&](auto ei) {
                 constexpr int e = decltype(ei)::value;
-                v[e] = lds.template get<TPV * e>(j);
+                v[e] = st.template get<TPV * e>(j);
             });
         } else {
             stockham_stage<L, R, NS, DIR, true, SC>(v, j, base, lds, tw);

@@ -287,7 +287,11 @@ k2_row(K2Args a) {
     const int j = threadIdx.x - r * TPV;
     const int row = rg * Sh::ROWS + r;
     const bool valid = row < n2;
-    const PadLds<V> lrow{lds + r * Sh::STRIDE};
+    // packed float16 rows of 2^12 and more: per-stage bank-conflict-free layouts
+    using RowL = std::conditional_t<F16 && LOG2N1 >= 12, StageRowLds<V>, PadLds<V>>;
+    const RowL lrow{lds + r * Sh::STRIDE};
+    static_assert(!(F16 && LOG2N1 >= 12) || (Sh::STRIDE >= (1 << LOG2N1) + 16 * ((1 << LOG2N1) >> 8)),
+                  "per-stage layouts fit the row");
 
     StageBases<LOG2N1, V> tb;
     tb.load(j, a.tw1);
