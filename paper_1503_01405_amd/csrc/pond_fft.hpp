@@ -562,10 +562,15 @@ __device__ __forceinline__ void fill_stage1_table(h2* tab, const float2* __restr
 // every even stage but the first scales its input by 1/16 (the caller
 // scales the first stage's input and applies the remaining 2^-kHalfRem).
 // Float16 transforms of length >= 2^8 with S1 read their stage-1 twiddles
-// from the table s1tab (fill_stage1_table).
-template <int LOG2L, int DIR, bool HALF_NORM = false, bool S1 = false, class V, class Lds>
+// from the table s1tab (fill_stage1_table).  hook() runs after the stores
+// of the last exchange, before its barrier: global loads issued there for
+// use after the transform wait out their latency behind the exchange.
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+template <int LOG2L, int DIR, bool HALF_NORM = false, bool S1 = false, class V, class Lds, class Hook = NoHook>
 __device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L, V>& tb, const Lds& lds,
-                                       const h2* s1tab = nullptr) {
+                                       const h2* s1tab = nullptr, const Hook& hook = Hook{}) {
     using S = Sched<LOG2L>;
     constexpr int L = 1 << LOG2L;
     constexpr int TPV = L / 16;
@@ -602,6 +607,7 @@ __device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L
             const auto st = stage_view<s>(lds);
             __syncthreads();
             stockham_stage<L, R, NS, DIR, false, SC>(v, j, base, st, tw);
+            if constexpr (s == S::kStages - 2) hook();
             __syncthreads();
             static_for<16>([&](auto ei) {
                 constexpr int e = decltype(ei)::value;

@@ -325,7 +325,16 @@ k2_row(K2Args a) {
             if constexpr (MODE == kRowInv) v[e] = cmul(x, *at(chirp, i * 4u));
             else v[e] = cmul(x, tw_at(i));
         }
-        if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true, true>(v, j, tb, lrow, s1tab);
+        // kRowFull: the chirp of each element is fetched during the forward
+        // transform's last exchange.
+        h2 ch[16];
+        auto fetch_chirp = [&] {
+            const uint32_t t2 = opaque(toff);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) ch[e] = __builtin_bit_cast(h2, at(tab, (t2 + TPV * e) * 8u)->y);
+        };
+        if constexpr (MODE == kRowFull) fft_wg<LOG2N1, -1, true, true>(v, j, tb, lrow, s1tab, fetch_chirp);
+        else if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true, true>(v, j, tb, lrow, s1tab);
         if constexpr (MODE == kRowFwd) {
             constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N1>::kHalfRem);
             if (valid) {
@@ -336,21 +345,24 @@ k2_row(K2Args a) {
             return;
         }
         if constexpr (MODE == kRowFull) {
-            asm volatile("" ::: "memory");
-            to = opaque(toff);
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                v[e] = cmul(v[e], __builtin_bit_cast(h2, at(tab, (to + TPV * e) * 8u)->y));
+            for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], ch[e]);
         }
-        fft_wg<LOG2N1, +1, false, true>(v, j, tb, lrow, s1tab);
+        // the output twiddles are fetched during the inverse transform's
+        // last exchange (rather than one dependent load per store)
+        h2 wo[16];
+        auto fetch_tw = [&] {
+            const uint32_t t2 = opaque(toff);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) wo[e] = tw_at(t2 + TPV * e);
+        };
+        fft_wg<LOG2N1, +1, false, true>(v, j, tb, lrow, s1tab, fetch_tw);
         asm volatile("" ::: "memory");
         to = opaque(toff);
         if (valid) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t i = to + TPV * e;
-                st_h2(at(dst, i * (uint32_t)sizeof(T)), cmulc(v[e], tw_at(i)));
-            }
+            for (int e = 0; e < 16; ++e)
+                st_h2(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cmulc(v[e], wo[e]));
         }
         return;
     } else {
@@ -373,19 +385,23 @@ k2_row(K2Args a) {
                 v[e] = x;  // kRowInvPlain: the filter was applied before (real input path)
             }
         }
-        if constexpr (MODE != kRowInv && MODE != kRowInvPlain) {
-            fft_wg<LOG2N1, -1>(v, j, tb, lrow);
-        }
-        if constexpr (MODE == kRowFull) {
-            // Re-read the table (from L2) rather than keep it live across the
-            // transforms: registers are the occupancy limit of this kernel.
-            asm volatile("" ::: "memory");
-            to = opaque(toff);
+        // kRowFull: the chirp is fetched again (from L2) during the forward
+        // transform's last exchange rather than kept live across it.
+        float2 ch[16];
+        auto fetch_chirp = [&] {
+            const uint32_t t2 = opaque(toff);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const float4 t = *at(tab, (to + TPV * e) * 16u);
-                v[e] = cmul(v[e], make_float2(t.z, t.w));
+                const float4 t = *at(tab, (t2 + TPV * e) * 16u);
+                ch[e] = make_float2(t.z, t.w);
             }
+        };
+        if constexpr (MODE == kRowFull) {
+            fft_wg<LOG2N1, -1>(v, j, tb, lrow, nullptr, fetch_chirp);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], ch[e]);
+        } else if constexpr (MODE != kRowInv && MODE != kRowInvPlain) {
+            fft_wg<LOG2N1, -1>(v, j, tb, lrow);
         }
         if constexpr (MODE == kRowFwd) {
             if (valid) {
@@ -395,21 +411,27 @@ k2_row(K2Args a) {
             }
             return;
         }
-        fft_wg<LOG2N1, +1>(v, j, tb, lrow);
+        // output twiddles fetched during the inverse transform's last exchange
+        float2 wo[16];
+        auto fetch_tw = [&] {
+            const uint32_t t2 = opaque(toff);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                if constexpr (MODE == kRowFull) {
+                    const float4 t = *at(tab, (t2 + TPV * e) * 16u);
+                    wo[e] = make_float2(t.x, t.y);
+                } else {
+                    wo[e] = *at(tw4, (t2 + TPV * e) * 8u);
+                }
+            }
+        };
+        fft_wg<LOG2N1, +1>(v, j, tb, lrow, nullptr, fetch_tw);
         asm volatile("" ::: "memory");
         to = opaque(toff);
         if (valid) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                float2 w;
-                if constexpr (MODE == kRowFull) {
-                    const float4 t = *at(tab, (to + TPV * e) * 16u);
-                    w = make_float2(t.x, t.y);
-                } else {
-                    w = *at(tw4, (to + TPV * e) * 8u);
-                }
-                Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(cmulc(v[e], w), a.scale));
-            }
+            for (int e = 0; e < 16; ++e)
+                Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(cmulc(v[e], wo[e]), a.scale));
         }
     }
 }
@@ -1065,15 +1087,23 @@ __global__ void __launch_bounds__(K2PairShape<LOG2N1>::THREADS) k2_real_pair(Rea
         const float2 o2 = cmulc(cscale(csub(yk, ync), 0.5f), w);
         v[e] = make_float2(e2.x - o2.y, e2.y + o2.x);
     });
-    fft_wg<LOG2N1, +1>(v, j, tb, lrow);
+    // output twiddles fetched during the inverse transform's last exchange
+    float2 wo[16];
+    auto fetch_tw = [&] {
+        const uint32_t t2 = opaque(rowoff + (uint32_t)j);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float4 t = *at(tab, (t2 + TPV * e) * 16u);
+            wo[e] = make_float2(t.x, t.y);
+        }
+    };
+    fft_wg<LOG2N1, +1>(v, j, tb, lrow, nullptr, fetch_tw);
     asm volatile("" ::: "memory");
     to = opaque(rowoff + (uint32_t)j);
     if (valid) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const float4 t = *at(tab, (to + TPV * e) * 16u);
-            Elem<T>::store(at(data, (to + TPV * e) * (uint32_t)sizeof(T)), cmulc(v[e], make_float2(t.x, t.y)));
-        }
+        for (int e = 0; e < 16; ++e)
+            Elem<T>::store(at(data, (to + TPV * e) * (uint32_t)sizeof(T)), cmulc(v[e], wo[e]));
     }
 }
 
