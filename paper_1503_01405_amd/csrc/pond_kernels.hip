@@ -1046,7 +1046,18 @@ __global__ void __launch_bounds__(K2PairShape<LOG2N1>::THREADS) k2_real_pair(Rea
         const float4 t = *at(tab, (to + TPV * e) * 16u);
         v[e] = cmul(x, make_float2(t.x, t.y));
     }
-    fft_wg<LOG2N1, -1>(v, j, tb, lrow);
+    // this element's filter value, fetched while the forward transform's
+    // last exchange is under way
+    float2 mkp[16];
+    auto fetch_m = [&] {
+        const uint32_t t2 = opaque(rowoff + (uint32_t)j);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float4 t = *at(tab, (t2 + TPV * e) * 16u);
+            mkp[e] = make_float2(t.z, t.w);
+        }
+    };
+    fft_wg<LOG2N1, -1>(v, j, tb, lrow, nullptr, fetch_m);
 
     // The pair's spectra (scaled) to LDS, then each element reads its partner.
     __syncthreads();
@@ -1070,9 +1081,8 @@ __global__ void __launch_bounds__(K2PairShape<LOG2N1>::THREADS) k2_real_pair(Rea
         const int kp = (row == 0) ? ((L - k1) & (L - 1)) : (L - 1 - k1);
         const float2 A = lrow.template get<TPV * e>(j);
         const float2 B = *prow.template addr<0>(kp);
-        const float4 tk = *at(tab, (to + TPV * e) * 16u);
         const float4 tn = *at(tab, (prowoff + (uint32_t)kp) * 16u);
-        const float2 mk = make_float2(tk.z, tk.w);
+        const float2 mk = mkp[e];
         const float2 mn = (row == 0 && k1 == 0) ? make_float2(m_nyq, 0.f) : make_float2(tn.z, tn.w);
         const float2 w = cmul(wr, a.wk[n2 + k1]);
         const float2 E = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));
