@@ -13,7 +13,8 @@
  *   - bw_mhz is the complex bandwidth, equal to the complex sample rate in
  *     Msps; baseband frequency f maps to sky frequency f0 + f.
  *   - Input is single-polarisation complex int8: I then Q per sample,
- *     interleaved, in DEVICE memory, 2-byte aligned.
+ *     interleaved, in DEVICE memory, 2-byte aligned (the real two-channel
+ *     input of the pond_real_* calls is described with them).
  *   - Block b of the stream covers input samples [b*hop, b*hop + nfft).
  *     Its kept outputs are outputs m = b*hop + j, j in [0, hop); output m
  *     is input sample m + n_front, referred to arrival at f0.  Only fully
@@ -23,7 +24,8 @@
  *     turns_k = dm f_k^2 / (2.41e-10 f0^2 (f0 + f_k)), the inverse of the
  *     ISM response of Eq. (4) with the dispersion constant of Eq. (1).
  *     The phase is evaluated and reduced mod 1 turn in float64.
- *   - Forward transform unnormalised, inverse with 1/nfft; no taper.
+ *   - Forward transform unnormalised, inverse with 1/nfft; unit taper
+ *     unless one is set with pond_plan_set_taper.
  *   - Fold: x = (m + n_front) * inv_pfs with inv_pfs = 1/(period_s * fs),
  *     bin = min(floor((x - floor(x)) * nbins), nbins - 1), in float64.
  *     Sub-integration s holds outputs m in [s*S, (s+1)*S) for S =
