@@ -50,6 +50,15 @@ template <class T>
 __device__ __forceinline__ T* at(T* base, uint32_t byte_off) {
     return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
 }
+// A pointer that is the same in every lane, moved to scalar registers, so
+// that bases derived from it stay scalar.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
 // Hide a value from the optimiser so that expressions depending on it are
 // recomputed where used instead of being hoisted and kept in registers.
 __device__ __forceinline__ uint32_t opaque(uint32_t x) {
@@ -128,28 +137,46 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     const int col = 16 * t + c;
 
     // Block samples [0, split) come from the carried tail, the rest from
-    // this call's input; both bases are uniform, offsets are 32-bit.
+    // this call's input; both bases are uniform, offsets are 32-bit.  Every
+    // block but the one that straddles the tail's end reads one buffer
+    // only (UNI: no per-sample choice of base).
     const int64_t bstart = (a.block0 + b) * a.hop;
     const int64_t split64 = a.in_start - bstart;
     const uint32_t split = split64 <= 0 ? 0u : (uint32_t)min(split64, (int64_t)1 << (a.log2n1 + LOG2N2));
     const int8_t* tbase = a.tail + BPE * (bstart - a.tail_start);
     const int8_t* ibase = a.in + BPE * (bstart - a.in_start);
+    const bool one_src = split == 0 || split == (uint32_t)1 << (a.log2n1 + LOG2N2);
+    const int8_t* ubase = uniform_ptr(split == 0 ? ibase : tbase);
     const uint32_t o0 = opaque((uint32_t)col);
-    auto load_raw = [&](int pos) {
+    // Address of value e (position j + TPV e) of the thread; UNI: a uniform
+    // base advanced by whole rows, plus the thread's own 32-bit offset.
+    const uint32_t uoff = BPE * (o0 + ((uint32_t)j << a.log2n1));
+    auto src_pos = [&](int pos) -> const int8_t* {
         const uint32_t off = o0 + ((uint32_t)pos << a.log2n1);
-        const int8_t* p = off < split ? tbase + 2 * off : ibase + 2 * off;
-        return *reinterpret_cast<const short*>(p);
+        return off < split ? tbase + BPE * off : ibase + BPE * off;
     };
-    auto load_in = [&](int pos) {
+    auto src = [&](int e, auto uni) -> const int8_t* {
+        if constexpr (decltype(uni)::value) return at(ubase + ((int64_t)(BPE * TPV * e) << a.log2n1), uoff);
+        else return src_pos(j + TPV * e);
+    };
+    auto cvt_in = [](const int8_t* p) {
         if constexpr (AIP) {
-            const uint32_t off = o0 + ((uint32_t)pos << a.log2n1);
-            const int8_t* p = off < split ? tbase + 4 * off : ibase + 4 * off;
             const int w = *reinterpret_cast<const int*>(p);
             return make_float2((float)((int)(int8_t)(w & 0xff) + (int)(int8_t)((w >> 8) & 0xff)),
                                (float)((int)(int8_t)((w >> 16) & 0xff) + (int)(int8_t)(w >> 24)));
         } else {
-            const short s = load_raw(pos);
+            const short s = *reinterpret_cast<const short*>(p);
             return make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)(s >> 8));
+        }
+    };
+    // Loads of the 16 values of the thread, with or without the choice.
+    auto load_all = [&](auto&& each) {
+        if (one_src) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) each(e, std::true_type{});
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) each(e, std::false_type{});
         }
     };
     T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
@@ -160,21 +187,22 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
         // exceeds 16x the input bound.
         StageBases<LOG2N2, h2> tb;
         tb.load(j, a.tw2);
+        // int8 pair -> float16 pair / 16, exactly: the bytes, sign bit
+        // flipped, become the low mantissa bits of 1024 (1152 + x), and
+        // (1152 + x) / 16 - 72 = x / 16 is representable.
         h2 v[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const short s = load_raw(j + TPV * e);
-            const h2 x = {(_Float16)(int8_t)(s & 0xff), (_Float16)(int8_t)(s >> 8)};
-            v[e] = x * (_Float16)0.0625f;
-        }
+        load_all([&](int e, auto uni) {
+            const uint32_t s = *reinterpret_cast<const uint16_t*>(src(e, uni));
+            const uint32_t w = ((s & 0xffu) | ((s & 0xff00u) << 8)) ^ 0x64806480u;
+            v[e] = __builtin_elementwise_fma(__builtin_bit_cast(h2, w), h2{(_Float16)0.0625f, (_Float16)0.0625f},
+                                             h2{(_Float16)-72.0f, (_Float16)-72.0f});
+        });
         fft_wg<LOG2N2, -1, true>(v, j, tb, ColLds<h2, true>{lds + c});
         constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N2>::kHalfRem);
-        const uint32_t w0 = opaque((uint32_t)col);
+        const uint32_t woff = (opaque((uint32_t)col) + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
+        T* const ob = uniform_ptr(out);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const uint32_t k2 = j + TPV * e;
-            st_h2(at(out, (w0 + (k2 << a.log2n1)) * (uint32_t)sizeof(T)), v[e] * (_Float16)osc);
-        }
+        for (int e = 0; e < 16; ++e) st_h2(at(ob + ((int64_t)(TPV * e) << a.log2n1), woff), v[e] * (_Float16)osc);
     } else {
         StageBases<LOG2N2> tb;
         tb.load(j, a.tw2);
@@ -183,22 +211,21 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
             // the DFT matrix): no float16 value can exceed the input range.
             const uint32_t w0 = opaque((uint32_t)col);
             colfft_mfma<LOG2N2, -1, false>(
-                c, j, a.tw2, tb, 1.0f / 16.0f, 1.0f / (float)Sched<LOG2N2>::kRem, load_in,
+                c, j, a.tw2, tb, 1.0f / 16.0f, 1.0f / (float)Sched<LOG2N2>::kRem,
+                [&](int pos) { return cvt_in(src_pos(pos)); },
                 [&](int pos) -> float2& { return lds[pos * 16 + c]; },
                 [&](int pos, float2 y) {
                     Elem<T>::store(at(out, (w0 + ((uint32_t)pos << a.log2n1)) * (uint32_t)sizeof(T)), y);
                 });
         } else {
             float2 v[16];
-#pragma unroll
-            for (int e = 0; e < 16; ++e) v[e] = load_in(j + TPV * e);
+            load_all([&](int e, auto uni) { v[e] = cvt_in(src(e, uni)); });
             fft_wg<LOG2N2, -1>(v, j, tb, ColLds<float2, true>{lds + c});
-            const uint32_t w0 = opaque((uint32_t)col);
+            const uint32_t woff = (opaque((uint32_t)col) + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
+            T* const ob = uniform_ptr(out);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t k2 = j + TPV * e;
-                Elem<T>::store(at(out, (w0 + (k2 << a.log2n1)) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
-            }
+            for (int e = 0; e < 16; ++e)
+                Elem<T>::store(at(ob + ((int64_t)(TPV * e) << a.log2n1), woff), cscale(v[e], a.scale));
         }
     }
 }
@@ -594,10 +621,11 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     const int c = threadIdx.x & 15;
     const int j = threadIdx.x >> 4;
     const int n1 = 1 << a.log2n1;
-    const int tiles_per_block = n1 >> 4;
-    const int items = a.nblocks * tiles_per_block;
+    const int log2tiles = a.log2n1 - 4;  // tiles of 16 columns per block
+    const int items = a.nblocks << log2tiles;
     const int r0 = (int)(a.n_front & 15);
     const double inv_s = a.subint > 0 ? 1.0 / (double)a.subint : 0.0;
+    const int log2d = __builtin_ctz((unsigned)a.decim);  // decim is a power of two
 
     if (!a.global_mode) {
         for (int i = threadIdx.x; i < a.entries; i += blockDim.x) {
@@ -626,8 +654,8 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     }
 
     for (int item = xcd * chunk + local; item < it_end; item += per_xcd) {
-        const int b = item / tiles_per_block;
-        const int t = item - b * tiles_per_block;
+        const int b = item >> log2tiles;
+        const int t = item & ((1 << log2tiles) - 1);
         const int col = (r0 + 16 * t + c) & (n1 - 1);
 
         const T* in = reinterpret_cast<const T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
@@ -640,9 +668,10 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             // power in float32 from the float16 pair (exact products).
             h2* lh = reinterpret_cast<h2*>(lds);
             h2 v[16];
+            const T* const ib = uniform_ptr(in);
+            const uint32_t ioff = (o0 + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                v[e] = ld_h2(at(in, (o0 + ((uint32_t)(j + TPV * e) << a.log2n1)) * (uint32_t)sizeof(T)));
+            for (int e = 0; e < 16; ++e) v[e] = ld_h2(at(ib + ((int64_t)(TPV * e) << a.log2n1), ioff));
             static_assert(ColLds<h2, true>::kSlots(L) * sizeof(h2) <= sizeof(float2) * 16 * L, "padded tile fits");
             fft_wg<LOG2N2, +1, false, true>(v, j, tb, ColLds<h2, true>{lh + c}, s1tab);
             __syncthreads();
@@ -663,8 +692,10 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             __syncthreads();
         } else {
             float2 v[16];
+            const T* const ib = uniform_ptr(in);
+            const uint32_t ioff = (o0 + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) v[e] = load_in(j + TPV * e);
+            for (int e = 0; e < 16; ++e) v[e] = Elem<T>::load(at(ib + ((int64_t)(TPV * e) << a.log2n1), ioff));
             fft_wg<LOG2N2, +1>(v, j, tb, ColLds<float2>{lds + c});
 
             // Detected powers to LDS, one row of 16 columns per output row.
@@ -741,7 +772,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         const float s16 = s8[0] + s8[1];
         const int64_t m0 = (a.block0 + b) * a.hop + off;  // first output of the group
         if (a.series) {
-            float* sp = a.series + (m0 / a.decim - a.series_base);
+            float* sp = a.series + ((m0 >> log2d) - a.series_base);
             if (a.decim == 16) {
                 sp[0] = s16;
             } else if (a.decim == 8) {
@@ -770,8 +801,9 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         const int bin15 = fold_bin(f0i + G - 1, fnf, a.inv_pfs, a.nbins, &t15);
         const int64_t d0 = m0 - a.s_base * a.subint;
         const int64_t sub0 = a.subint > 0 ? subint_rel(d0, a.subint, inv_s) : 0;
-        const int64_t sub15 = a.subint > 0 ? subint_rel(d0 + 15, a.subint, inv_s) : 0;
-        if (bin0 == bin15 && t0 == t15 && sub0 == sub15) {
+        // the group's 16 outputs share sub0 unless it ends within them
+        const bool one_sub = a.subint <= 0 || d0 - sub0 * a.subint + 15 < a.subint;
+        if (bin0 == bin15 && t0 == t15 && one_sub) {
             fold_add(a, hsum, hcnt, sub0, bin0, s16, G, flags);
             continue;
         }
@@ -781,7 +813,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         // group is one cell, add two partial sums; otherwise (a bin shorter
         // than the group, or a sub-integration edge) one add per sample.
         int hi = G - 1;
-        bool two = sub0 == sub15;
+        bool two = one_sub;
         if (two) {
             int lo = 0;
             while (hi - lo > 1) {
