@@ -861,7 +861,9 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 // ------------------------------------------------------ fold reduction
 // Sum the per-workgroup partial histograms (integer, so order-free) and
 // add them to the accumulators.  Grid: x over entries, y over part chunks.
-constexpr int kReduceChunk = 32;
+// The partials were just written and sit in cache: a full chunk issues all
+// its loads at once, so a call costs about one load latency, not a chain.
+constexpr int kReduceChunk = 8;
 __global__ void __launch_bounds__(256) fold_reduce(const uint64_t* __restrict__ ps, const uint32_t* __restrict__ pc,
                                                    int nparts, int entries, uint64_t* acc_sum, uint64_t* acc_cnt,
                                                    int64_t acc_off) {
@@ -870,9 +872,24 @@ __global__ void __launch_bounds__(256) fold_reduce(const uint64_t* __restrict__ 
     const int p0 = blockIdx.y * kReduceChunk;
     const int p1 = min(nparts, p0 + kReduceChunk);
     uint64_t s = 0, n = 0;
-    for (int q = p0; q < p1; ++q) {
-        s += ps[(int64_t)q * entries + i];
-        n += pc[(int64_t)q * entries + i];
+    if (p1 - p0 == kReduceChunk) {
+        uint64_t sv[kReduceChunk];
+        uint32_t nv[kReduceChunk];
+#pragma unroll
+        for (int k = 0; k < kReduceChunk; ++k) {
+            sv[k] = ps[(int64_t)(p0 + k) * entries + i];
+            nv[k] = pc[(int64_t)(p0 + k) * entries + i];
+        }
+#pragma unroll
+        for (int k = 0; k < kReduceChunk; ++k) {
+            s += sv[k];
+            n += nv[k];
+        }
+    } else {
+        for (int q = p0; q < p1; ++q) {
+            s += ps[(int64_t)q * entries + i];
+            n += pc[(int64_t)q * entries + i];
+        }
     }
     if (n) {
         atomicAdd((unsigned long long*)&acc_sum[acc_off + i], (unsigned long long)s);
