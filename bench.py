@@ -197,6 +197,20 @@ def run_form(precision, x, steps, warmup, graph=False):
     return res
 
 
+def host_cpu():
+    """The host the CPU baseline ran on: logical CPUs and the processor model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(host_cpus=os.cpu_count(), cpu_model=model)
+
+
 def cpu_baseline(iq_np, nblocks):
     """The FP64 oracle, as it stands, on the first `nblocks` blocks."""
     import oracle as O
@@ -208,7 +222,7 @@ def cpu_baseline(iq_np, nblocks):
     r = O.run(sub, F0, BW, DM, NFFT, NBINS, PERIOD, subint_nsamp=SUBINT, decim=DECIM, workers=workers)
     dt = time.perf_counter() - t0
     msps = r["n_out"] / dt / 1e6
-    return dict(value=round(msps, 3), unit="Msamples/s", cores=workers, kind="oracle",
+    return dict(value=round(msps, 3), unit="Msamples/s", cores=workers, kind="oracle", **host_cpu(),
                 sample=f"first {nblocks} of 227 overlap-save blocks ({r['n_out']} outputs, "
                        f"{r['n_out'] / 16e6:.2f} s of data) of the same stream, {dt:.1f} s of CPU work",
                 xrealtime=round(msps / 16.0, 3))
@@ -282,7 +296,7 @@ def search_cpu_baseline(iq_np, dms):
     O.search(sub, F0, BW, pick, SEARCH_NBINS, PERIOD, workers=workers)
     dt = time.perf_counter() - t0
     v = len(pick) * n_in / dt / 1e6
-    return dict(value=round(v, 3), unit="Msamples/s", cores=workers, kind="oracle",
+    return dict(value=round(v, 3), unit="Msamples/s", cores=workers, kind="oracle", **host_cpu(),
                 sample=f"{len(pick)} trials (DM {', '.join(str(d) for d in pick)}: one per FFT length) over the "
                        f"first {n_in} samples, {dt:.1f} s of CPU work")
 
@@ -491,7 +505,7 @@ def aid_cpu_baseline(iq_np):
     t0 = time.perf_counter()
     O.aid_run(iq_np[:2 * n], F0, BW, DM, AID_NCHAN, AID_NINT, NBINS, PERIOD)
     dt = time.perf_counter() - t0
-    return dict(value=round(n / dt / 1e6, 3), unit="Msamples/s", cores=1, kind="oracle",
+    return dict(value=round(n / dt / 1e6, 3), unit="Msamples/s", cores=1, kind="oracle", **host_cpu(),
                 sample=f"first {n} samples ({n / 16e6:.1f} s) of the same stream, {dt:.1f} s of CPU work (numpy FFTs, one thread)")
 
 
@@ -580,7 +594,7 @@ def real_cpu_baseline(raw_np, sideband, nblocks):
     t0 = time.perf_counter()
     r = O.run_real(raw_np[:2 * n], F0, BW, DM, NFFT, NBINS, PERIOD, sideband=sideband, decim=REAL_DECIM)
     dt = time.perf_counter() - t0
-    return dict(value=round(r["n_out"] / dt / 1e6, 3), unit="Msamples/s", cores=1, kind="oracle",
+    return dict(value=round(r["n_out"] / dt / 1e6, 3), unit="Msamples/s", cores=1, kind="oracle", **host_cpu(),
                 sample=f"first {nblocks} blocks ({n} real samples) of the same stream, {dt:.1f} s of CPU work "
                        f"(scipy real FFTs, one thread)")
 
