@@ -653,6 +653,27 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         fill_stage1_table<LOG2N2>(s1tab, a.tw2, threadIdx.x);
     }
 
+    // Float16 storage with VALU arithmetic, columns of 2^9 and 2^10: the
+    // next item's column tile is loaded (as float16 pairs) while this one
+    // is transformed and folded, so its latency is not exposed once per
+    // item (the 16 registers are free there: the LDS already limits the
+    // kernel to four waves per SIMD).
+    constexpr bool kPrefetch = (FORM == kFormF16 || (FORM == kFormF32 && std::is_same<T, __half2>::value)) &&
+                               (LOG2N2 == 10 || (LOG2N2 == 9 && !REAL));  // (else past 128 registers)
+    h2 nxt[16];
+    auto load_tile = [&](int it, h2(&dst)[16]) {
+        const int bb = it >> log2tiles;
+        const int tt = it & ((1 << log2tiles) - 1);
+        const uint32_t cc = opaque((uint32_t)((r0 + 16 * tt + c) & (n1 - 1)));
+        const __half2* const ib =
+            uniform_ptr(reinterpret_cast<const __half2*>(a.work) + ((int64_t)bb << (a.log2n1 + LOG2N2)));
+        const uint32_t ioff = (cc + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(__half2);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) dst[e] = ld_h2(at(ib + ((int64_t)(TPV * e) << a.log2n1), ioff));
+    };
+    if constexpr (kPrefetch) {
+        if (xcd * chunk + local < it_end) load_tile(xcd * chunk + local, nxt);
+    }
     for (int item = xcd * chunk + local; item < it_end; item += per_xcd) {
         const int b = item >> log2tiles;
         const int t = item & ((1 << log2tiles) - 1);
@@ -668,10 +689,13 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             // power in float32 from the float16 pair (exact products).
             h2* lh = reinterpret_cast<h2*>(lds);
             h2 v[16];
-            const T* const ib = uniform_ptr(in);
-            const uint32_t ioff = (o0 + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
+            if constexpr (kPrefetch) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) v[e] = ld_h2(at(ib + ((int64_t)(TPV * e) << a.log2n1), ioff));
+                for (int e = 0; e < 16; ++e) v[e] = nxt[e];
+                if (item + per_xcd < it_end) load_tile(item + per_xcd, nxt);
+            } else {
+                load_tile(item, v);
+            }
             static_assert(ColLds<h2, true>::kSlots(L) * sizeof(h2) <= sizeof(float2) * 16 * L, "padded tile fits");
             fft_wg<LOG2N2, +1, false, true>(v, j, tb, ColLds<h2, true>{lh + c}, s1tab);
             __syncthreads();
@@ -692,10 +716,16 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             __syncthreads();
         } else {
             float2 v[16];
-            const T* const ib = uniform_ptr(in);
-            const uint32_t ioff = (o0 + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
+            if constexpr (kPrefetch) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) v[e] = Elem<T>::load(at(ib + ((int64_t)(TPV * e) << a.log2n1), ioff));
+                for (int e = 0; e < 16; ++e) v[e] = to_f2(nxt[e]);
+                if (item + per_xcd < it_end) load_tile(item + per_xcd, nxt);
+            } else {
+                const T* const ib = uniform_ptr(in);
+                const uint32_t ioff = (o0 + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) v[e] = Elem<T>::load(at(ib + ((int64_t)(TPV * e) << a.log2n1), ioff));
+            }
             fft_wg<LOG2N2, +1>(v, j, tb, ColLds<float2>{lds + c});
 
             // Detected powers to LDS, one row of 16 columns per output row.
