@@ -407,7 +407,7 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     p->elem = precision == POND_FP32 ? 8 : 4;
     p->max_batch = max_batch = default_max_batch(nfft, precision, max_batch);
 
-    p->hist_cap = hist_capacity(p->log2n2);
+    p->hist_cap = hist_capacity(p->log2n2, p->precision);
     // Packed float16: the middle pass leaves 1/16 of the value (its twiddle
     // table carries the first stage's 1/16), so power x 256, divided by the
     // gain of the float16 stage twiddles of the four transforms.
@@ -830,7 +830,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a3.acc_s0 = s_open;
         a3.status = reinterpret_cast<uint32_t*>(p->status);
         const size_t dyn = global_mode ? 0 : (size_t)entries * 12;
-        const int grid = k3_grid(n2log, dyn, nb * (n1 / 16), entries, global_mode);
+        const int grid = k3_grid(n2log, p->precision, dyn, nb * (n1 / 16), entries, global_mode);
         e = timed(2, nb, [&] {
             return real ? launch_k3_real(p->precision, n2log, a3, (int)grid, dyn, stream)
                         : launch_k3(p->precision, n2log, a3, (int)grid, dyn, stream);

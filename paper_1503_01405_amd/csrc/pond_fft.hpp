@@ -562,13 +562,16 @@ __device__ __forceinline__ void fill_stage1_table(h2* tab, const float2* __restr
 // every even stage but the first scales its input by 1/16 (the caller
 // scales the first stage's input and applies the remaining 2^-kHalfRem).
 // Float16 transforms of length >= 2^8 with S1 read their stage-1 twiddles
-// from the table s1tab (fill_stage1_table).  hook() runs after the stores
+// from the table s1tab (fill_stage1_table).  Without LEAD the caller
+// guarantees that no thread still reads the vector's LDS, and the barrier
+// before the first exchange's stores is left out.  hook() runs after the stores
 // of the last exchange, before its barrier: global loads issued there for
 // use after the transform wait out their latency behind the exchange.
 struct NoHook {
     __device__ __forceinline__ void operator()() const {}
 };
-template <int LOG2L, int DIR, bool HALF_NORM = false, bool S1 = false, class V, class Lds, class Hook = NoHook>
+template <int LOG2L, int DIR, bool HALF_NORM = false, bool S1 = false, bool LEAD = true, class V, class Lds,
+          class Hook = NoHook>
 __device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L, V>& tb, const Lds& lds,
                                        const h2* s1tab = nullptr, const Hook& hook = Hook{}) {
     using S = Sched<LOG2L>;
@@ -605,7 +608,7 @@ __device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L
         }
         if constexpr (!LAST) {
             const auto st = stage_view<s>(lds);
-            __syncthreads();
+            if constexpr (s > 0 || LEAD) __syncthreads();
             stockham_stage<L, R, NS, DIR, false, SC>(v, j, base, st, tw);
             if constexpr (s == S::kStages - 2) hook();
             __syncthreads();

@@ -163,11 +163,11 @@ hipError_t launch_fold_profiles(const uint64_t* acc_sum, const uint64_t* acc_cnt
 // Workgroups of a K3 launch: enough to fill the chip at the occupancy the
 // LDS allows, at most one per item, a multiple of 8, and within the
 // partial-histogram budget.
-int k3_grid(int log2n2, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode);
+int k3_grid(int log2n2, int prec, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode);
 constexpr int64_t kPartEntries = 1 << 21;  // per-workgroup fold partials: grid * entries <= this
 constexpr int64_t kHistCapMax = 8192;      // fold histogram entries held in LDS
 constexpr size_t kLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
-int64_t hist_capacity(int log2n2);
+int64_t hist_capacity(int log2n2, int prec);
 
 // Device bytes pond_plan_create_ex allocates for these arguments, and the
 // blocks per launch it picks (max_batch <= 0: the default).
@@ -177,7 +177,7 @@ int plan_max_batch(int64_t nfft, int32_t precision, int32_t max_batch);
 double half_twiddle_gain(int log2l);
 
 // Static LDS bytes of the K3 tile for a column length 2^log2n2.
-size_t k3_static_lds(int log2n2);
+size_t k3_static_lds(int log2n2, int prec);
 // Threads per workgroup of each kernel.
 int k1_threads(int log2n2);
 int k2_threads(int log2n1);

@@ -549,13 +549,30 @@ __global__ void __launch_bounds__(256) k2_build_split_tables(float2* __restrict_
 }
 
 // ------------------------------------------------------------------- K3
+// Static LDS.  Float32 arithmetic: one float2 tile of 16 columns, reused for
+// the detected powers.  Packed float16: the padded float16 tile, a power
+// buffer of its own (16 floats per row) and the stage-1 twiddle table, so
+// that an item's powers are written without a barrier after the transform
+// and the next item's transform starts without one before its first
+// exchange.
 template <int LOG2N2>
 struct K3Shape {
     static constexpr int L = 1 << LOG2N2;
     static constexpr int TPV = L / 16;
     static constexpr int THREADS = L;
     static constexpr size_t LDS = sizeof(float2) * 16 * L;
+    static constexpr size_t kHalfTile = ColLds<h2, true>::kSlots(L) * sizeof(h2);
+    static constexpr size_t kHalfPf = 16 * L * sizeof(float);
+    static constexpr size_t LDS_HALF = kHalfTile + kHalfPf + kS1Pairs * sizeof(h2);
+    static constexpr size_t lds(int form) { return form == kFormF16 ? LDS_HALF : LDS; }
 };
+// Power buffer of the packed-float16 K3: row-major, 16 floats per row, the
+// four float4 quarters of a row rotated by (row / 4) mod 4, so that the
+// epilogue's float4 reads of 16 consecutive rows (one per lane) and the
+// detection's writes of four rows per wave use every bank once.
+__device__ __forceinline__ int k3h_pidx(int row, int col) {
+    return row * 16 + ((((col >> 2) + (row >> 2)) & 3) << 2) + (col & 3);
+}
 
 // Fold phase of output m (float64, as specified): x = (m + n_front) * inv_pfs,
 // bin = min(floor(frac(x) * nbins), nbins - 1); also returns floor(x), the
@@ -612,11 +629,12 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     // reads of the epilogue spread over the banks
     constexpr int PSTRIDE = REAL ? 32 : 20;
     auto rot = [](int row, int x) { return (x + 4 * (row & 7)) & 31; };
-    __shared__ float2 lds[16 * L];
+    __shared__ __align__(16) char lds_raw[Sh::lds(FORM)];
     extern __shared__ uint64_t dyn_u64[];
     uint64_t* hsum = dyn_u64;
     uint32_t* hcnt = reinterpret_cast<uint32_t*>(dyn_u64 + (a.global_mode ? 0 : a.entries));
-    float* pf = reinterpret_cast<float*>(lds);
+    float2* lds = reinterpret_cast<float2*>(lds_raw);
+    float* pf = reinterpret_cast<float*>(lds_raw + (FORM == kFormF16 ? Sh::kHalfTile : 0));
 
     const int c = threadIdx.x & 15;
     const int j = threadIdx.x >> 4;
@@ -643,15 +661,9 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     uint32_t flags = 0;
     StageBases<LOG2N2, LdsVal<FORM>> tb;
     tb.load(j, a.tw2);
-    // packed float16: the stage-1 twiddle table sits past the largest use of
-    // the buffer by the tile (16 L padded pairs) and the power rows
-    h2* s1tab = reinterpret_cast<h2*>(lds) + (sizeof(float2) * 16 * L / sizeof(h2) - kS1Pairs);
-    if constexpr (FORM == kFormF16) {
-        static_assert(PSTRIDE * L * sizeof(float) <= sizeof(float2) * 16 * L - kS1Pairs * sizeof(h2), "table clear");
-        static_assert(ColLds<h2, true>::kSlots(L) * sizeof(h2) <= sizeof(float2) * 16 * L - kS1Pairs * sizeof(h2),
-                      "table clear of the tile");
-        fill_stage1_table<LOG2N2>(s1tab, a.tw2, threadIdx.x);
-    }
+    // packed float16: the stage-1 twiddle table follows the power buffer
+    h2* s1tab = reinterpret_cast<h2*>(lds_raw + Sh::kHalfTile + Sh::kHalfPf);
+    if constexpr (FORM == kFormF16) fill_stage1_table<LOG2N2>(s1tab, a.tw2, threadIdx.x);
 
     // Float16 storage with VALU arithmetic, columns of 2^9 and 2^10: the
     // next item's column tile is loaded (as float16 pairs) while this one
@@ -696,13 +708,13 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             } else {
                 load_tile(item, v);
             }
-            static_assert(ColLds<h2, true>::kSlots(L) * sizeof(h2) <= sizeof(float2) * 16 * L, "padded tile fits");
-            fft_wg<LOG2N2, +1, false, true>(v, j, tb, ColLds<h2, true>{lh + c}, s1tab);
-            __syncthreads();
+            // no barrier before the first exchange: every wave has left the
+            // previous item's transform (the barrier after its powers)
+            fft_wg<LOG2N2, +1, false, true, false>(v, j, tb, ColLds<h2, true>{lh + c}, s1tab);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const float yx = (float)v[e].x, yy = (float)v[e].y;
-                pf[(j + TPV * e) * PSTRIDE + c] = fmaf(yx, yx, yy * yy) * a.pscale;
+                pf[k3h_pidx(j + TPV * e, c)] = fmaf(yx, yx, yy * yy) * a.pscale;
             }
             __syncthreads();
         } else if constexpr (FORM == kFormMfma && LOG2N2 >= 6) {
@@ -772,10 +784,10 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) p[i] = pr[2 * i] + pr[2 * i + 1];
         } else if (r0 + 16 * t + 15 < n1) {
-            const float4* row = reinterpret_cast<const float4*>(pf + q * PSTRIDE);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float4 x4 = row[i];
+                const float4 x4 = *reinterpret_cast<const float4*>(
+                    pf + (FORM == kFormF16 ? k3h_pidx(q, 4 * i) : q * PSTRIDE + 4 * i));
                 p[4 * i] = x4.x;
                 p[4 * i + 1] = x4.y;
                 p[4 * i + 2] = x4.z;
@@ -785,7 +797,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int rsrc = q + ((r0 + 16 * t + i) >> a.log2n1);
-                p[i] = rsrc < L ? pf[rsrc * PSTRIDE + i] : 0.f;
+                p[i] = rsrc < L ? pf[FORM == kFormF16 ? k3h_pidx(rsrc, i) : rsrc * PSTRIDE + i] : 0.f;
             }
         }
         if (off < 0 || off >= a.hop) continue;
@@ -1578,7 +1590,7 @@ template <class T, int FORM, int LOG2N2>
 static hipError_t k3_one(const K3Args& a, int grid, size_t dyn, hipStream_t s) {
     static const hipError_t attr = hipFuncSetAttribute(
         reinterpret_cast<const void*>(&k3_colinv_detect_fold<LOG2N2, T, FORM>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - K3Shape<LOG2N2>::LDS));
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - K3Shape<LOG2N2>::lds(FORM)));
     if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k3_colinv_detect_fold<LOG2N2, T, FORM>), dim3(grid), dim3(1 << LOG2N2), dyn, s, a);
     return hipGetLastError();
@@ -1682,13 +1694,13 @@ hipError_t launch_fold_profiles(const uint64_t* acc_sum, const uint64_t* acc_cnt
     return hipGetLastError();
 }
 
-int64_t hist_capacity(int log2n2) {
-    const int64_t cap = (int64_t)((kLdsBytes - k3_static_lds(log2n2)) / 12);
+int64_t hist_capacity(int log2n2, int prec) {
+    const int64_t cap = (int64_t)((kLdsBytes - k3_static_lds(log2n2, prec)) / 12);
     return cap < kHistCapMax ? cap : kHistCapMax;
 }
 
-int k3_grid(int log2n2, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode) {
-    const size_t lds = k3_static_lds(log2n2) + dyn_lds;
+int k3_grid(int log2n2, int prec, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode) {
+    const size_t lds = k3_static_lds(log2n2, prec) + dyn_lds;
     int per_cu = (int)(kLdsBytes / lds);
     per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
     int64_t grid = 256 * per_cu;
@@ -1700,7 +1712,12 @@ int k3_grid(int log2n2, size_t dyn_lds, int64_t items, int64_t entries, bool glo
     return (int)grid;
 }
 
-size_t k3_static_lds(int log2n2) { return sizeof(float2) * 16 * ((size_t)1 << log2n2); }
+size_t k3_static_lds(int log2n2, int prec) {
+    const size_t l = (size_t)1 << log2n2;
+    if (prec == kHalf) return (16 * l + l) * sizeof(h2) + 16 * l * sizeof(float) + kS1Pairs * sizeof(h2);
+    return sizeof(float2) * 16 * l;
+}
+static_assert(K3Shape<10>::LDS_HALF == (16 * 1024 + 1024) * 4 + 16 * 1024 * 4 + kS1Pairs * 4, "host copy of the K3 layout");
 int k1_threads(int log2n2) { return 1 << log2n2; }
 int k3_threads(int log2n2) { return 1 << log2n2; }
 int k2_threads(int log2n1) {

@@ -269,7 +269,7 @@ int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* 
     for (auto& g : s->groups) {
         const int64_t nb_total = nsamp < g.nfft ? 0 : (nsamp - g.nfft) / g.hop + 1;
         const int64_t n1 = (int64_t)1 << g.log2n1;
-        const int64_t cap = hist_capacity(g.log2n2);
+        const int64_t cap = hist_capacity(g.log2n2, s->precision);
         const bool global_mode = nbins > cap;
         for (int64_t b = 0; b < nb_total; b += g.max_batch) {
             const int nb = (int)(nb_total - b < g.max_batch ? nb_total - b : g.max_batch);
@@ -338,7 +338,7 @@ int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* 
                 a3.acc_s0 = 0;
                 a3.status = reinterpret_cast<uint32_t*>(s->status);
                 const size_t dyn = global_mode ? 0 : (size_t)nbins * 12;
-                const int grid = k3_grid(g.log2n2, dyn, (int64_t)nb * (n1 / 16), nbins, global_mode);
+                const int grid = k3_grid(g.log2n2, s->precision, dyn, (int64_t)nb * (n1 / 16), nbins, global_mode);
                 e = launch_k3(s->precision, g.log2n2, a3, grid, dyn, stream);
                 if (e != hipSuccess) return fail();
                 if (!global_mode) {
