@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
             v[e] = __builtin_elementwise_fma(__builtin_bit_cast(h2, w), h2{(_Float16)0.0625f, (_Float16)0.0625f},
                                              h2{(_Float16)-72.0f, (_Float16)-72.0f});
         });
-        fft_wg<LOG2N2, -1, true>(v, j, tb, ColLds<h2, true>{lds + c});
+        fft_wg<LOG2N2, -1, true, false, false>(v, j, tb, ColLds<h2, true>{lds + c});  // first LDS use: no lead barrier
         constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N2>::kHalfRem);
         const uint32_t woff = (opaque((uint32_t)col) + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
         T* const ob = uniform_ptr(out);
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
         } else {
             float2 v[16];
             load_all([&](int e, auto uni) { v[e] = cvt_in(src(e, uni)); });
-            fft_wg<LOG2N2, -1>(v, j, tb, ColLds<float2, true>{lds + c});
+            fft_wg<LOG2N2, -1, false, false, false>(v, j, tb, ColLds<float2, true>{lds + c});  // first LDS use
             const uint32_t woff = (opaque((uint32_t)col) + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
             T* const ob = uniform_ptr(out);
 #pragma unroll
@@ -1148,7 +1148,7 @@ __global__ void __launch_bounds__(K2PairShape<LOG2N1>::THREADS) k2_real_pair(Rea
             mkp[e] = make_float2(t.z, t.w);
         }
     };
-    fft_wg<LOG2N1, -1>(v, j, tb, lrow, nullptr, fetch_m);
+    fft_wg<LOG2N1, -1, false, false, false>(v, j, tb, lrow, nullptr, fetch_m);  // first LDS use
 
     // The pair's spectra (scaled) to LDS, then each element reads its partner.
     __syncthreads();
