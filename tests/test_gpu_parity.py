@@ -125,6 +125,23 @@ def test_histogram_too_big_for_lds_uses_global_accumulators():
     assert rel_l2(ser, oser) <= 1e-5
 
 
+@pytest.mark.parametrize("nbins", [2282, 2283])
+def test_half_histogram_at_lds_capacity(nbins):
+    """Packed-float16 K3 at 2^10 columns: its static LDS (tile, power
+    buffer, stage-1 table: 136,448 B) leaves room for 2,282 histogram
+    entries of 12 B; 2,282 bins fold in LDS, 2,283 in the device
+    accumulators.  Both match the oracle."""
+    nfft, dm, period, nsamp = 1 << 20, 5.0, 0.0891, 2_500_003
+    print(f"case: half histogram capacity nbins={nbins}", flush=True)
+    iq = synth.white_stream_int8(71, nsamp)
+    oprof, oser, r = oracle_run(iq, dm, nfft, nbins, period, subint=0)
+    prof, ser = gpu_run(iq, dm, nfft, nbins, period, precision="half")
+    ep, es = profile_rel_l2(prof, oprof), rel_l2(ser, oser)
+    tp = profile_tol("half", r["n_out"], 0, nbins)
+    print(f"half: profile rel-L2 {ep:.3e} (tol {tp:.1e}) series rel-L2 {es:.3e}")
+    assert ep <= tp and es <= TOL["half"][1]
+
+
 @pytest.mark.parametrize("precision", FORMS)
 def test_chunking_invariance_is_bitwise(precision):
     """Any split of one stream into calls gives bit-identical outputs."""
