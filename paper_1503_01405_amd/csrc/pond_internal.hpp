@@ -1,5 +1,6 @@
 // Internal interface between the host runtime (pond_api.cpp) and the HIP
-// kernels (pond_kernels.hip).  Plain structs of pointers and sizes.
+// kernels (pond_k1/k2/k3/fold/real/aid_kernels.hip).  Plain structs of
+// pointers and sizes.
 #pragma once
 
 #include <hip/hip_runtime.h>

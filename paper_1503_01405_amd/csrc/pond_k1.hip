@@ -1,0 +1,190 @@
+// K1: int8 unpack and forward column FFTs of the four-step transform
+// (length n2, stride n1), written as rows [k2][n1].
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "pond_device.hpp"
+
+namespace pond {
+
+// AIP: the input is two real-sampled channels interleaved (A0 B0 A1 B1 ...);
+// element m packs the added-in-phase samples 2m and 2m+1 as (re, im), so a
+// block of 2N real samples is read as N complex elements of 4 bytes.
+// The packed-float16 tile (about 69 KB at n2 = 2^10) lets two workgroups
+// share a CU, if each thread stays within 64 registers.
+template <int LOG2N2, class T, int FORM, bool AIP = false>
+__global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
+    constexpr int BPE = AIP ? 4 : 2;  // input bytes per element
+    constexpr int L = 1 << LOG2N2;
+    constexpr int TPV = L / 16;
+    __shared__ LdsVal<FORM> lds[ColLds<LdsVal<FORM>, true>::kSlots(L)];
+
+    const int n1 = 1 << a.log2n1;
+    const int tiles_per_block = n1 >> 4;
+    const int ntiles = a.nblocks * tiles_per_block;
+    const int tile = xcd_logical(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int b = tile / tiles_per_block;
+    const int t = tile - b * tiles_per_block;
+    const int c = threadIdx.x & 15;
+    const int j = threadIdx.x >> 4;
+    const int col = 16 * t + c;
+
+    // Block samples [0, split) come from the carried tail, the rest from
+    // this call's input; both bases are uniform, offsets are 32-bit.  Every
+    // block but the one that straddles the tail's end reads one buffer
+    // only (UNI: no per-sample choice of base).
+    const int64_t bstart = (a.block0 + b) * a.hop;
+    const int64_t split64 = a.in_start - bstart;
+    const uint32_t split = split64 <= 0 ? 0u : (uint32_t)min(split64, (int64_t)1 << (a.log2n1 + LOG2N2));
+    const int8_t* tbase = a.tail + BPE * (bstart - a.tail_start);
+    const int8_t* ibase = a.in + BPE * (bstart - a.in_start);
+    const bool one_src = split == 0 || split == (uint32_t)1 << (a.log2n1 + LOG2N2);
+    const int8_t* ubase = uniform_ptr(split == 0 ? ibase : tbase);
+    const uint32_t o0 = opaque((uint32_t)col);
+    // Address of value e (position j + TPV e) of the thread; UNI: a uniform
+    // base advanced by whole rows, plus the thread's own 32-bit offset.
+    const uint32_t uoff = BPE * (o0 + ((uint32_t)j << a.log2n1));
+    auto src_pos = [&](int pos) -> const int8_t* {
+        const uint32_t off = o0 + ((uint32_t)pos << a.log2n1);
+        return off < split ? tbase + BPE * off : ibase + BPE * off;
+    };
+    auto src = [&](int e, auto uni) -> const int8_t* {
+        if constexpr (decltype(uni)::value) return at(ubase + ((int64_t)(BPE * TPV * e) << a.log2n1), uoff);
+        else return src_pos(j + TPV * e);
+    };
+    auto cvt_in = [](const int8_t* p) {
+        if constexpr (AIP) {
+            const int w = *reinterpret_cast<const int*>(p);
+            return make_float2((float)((int)(int8_t)(w & 0xff) + (int)(int8_t)((w >> 8) & 0xff)),
+                               (float)((int)(int8_t)((w >> 16) & 0xff) + (int)(int8_t)(w >> 24)));
+        } else {
+            const short s = *reinterpret_cast<const short*>(p);
+            return make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)(s >> 8));
+        }
+    };
+    // Loads of the 16 values of the thread, with or without the choice.
+    auto load_all = [&](auto&& each) {
+        if (one_src) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) each(e, std::true_type{});
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) each(e, std::false_type{});
+        }
+    };
+    T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
+    if constexpr (FORM == kFormF16) {
+        // Packed float16: int8 is exact in float16; the first stage's 1/16
+        // is applied here, the even stages scale themselves, and the rest
+        // of the 1/n2 normalisation is applied on output, so no value
+        // exceeds 16x the input bound.
+        StageBases<LOG2N2, h2> tb;
+        tb.load(j, a.tw2);
+        // int8 pair -> float16 pair / 16, exactly: the bytes, sign bit
+        // flipped, become the low mantissa bits of 1024 (1152 + x), and
+        // (1152 + x) / 16 - 72 = x / 16 is representable.
+        h2 v[16];
+        load_all([&](int e, auto uni) {
+            const uint32_t s = *reinterpret_cast<const uint16_t*>(src(e, uni));
+            const uint32_t w = ((s & 0xffu) | ((s & 0xff00u) << 8)) ^ 0x64806480u;
+            v[e] = __builtin_elementwise_fma(__builtin_bit_cast(h2, w), h2{(_Float16)0.0625f, (_Float16)0.0625f},
+                                             h2{(_Float16)-72.0f, (_Float16)-72.0f});
+        });
+        fft_wg<LOG2N2, -1, true, false, false>(v, j, tb, ColLds<h2, true>{lds + c});  // first LDS use: no lead barrier
+        constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N2>::kHalfRem);
+        const uint32_t woff = (opaque((uint32_t)col) + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
+        T* const ob = uniform_ptr(out);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) st_h2(at(ob + ((int64_t)(TPV * e) << a.log2n1), woff), v[e] * (_Float16)osc);
+    } else {
+        StageBases<LOG2N2> tb;
+        tb.load(j, a.tw2);
+        if constexpr (FORM == kFormMfma && LOG2N2 >= 6) {
+            // Normalised forward pass (1/16 per radix-16 stage, folded into
+            // the DFT matrix): no float16 value can exceed the input range.
+            const uint32_t w0 = opaque((uint32_t)col);
+            colfft_mfma<LOG2N2, -1, false>(
+                c, j, a.tw2, tb, 1.0f / 16.0f, 1.0f / (float)Sched<LOG2N2>::kRem,
+                [&](int pos) { return cvt_in(src_pos(pos)); },
+                [&](int pos) -> float2& { return lds[pos * 16 + c]; },
+                [&](int pos, float2 y) {
+                    Elem<T>::store(at(out, (w0 + ((uint32_t)pos << a.log2n1)) * (uint32_t)sizeof(T)), y);
+                });
+        } else {
+            float2 v[16];
+            load_all([&](int e, auto uni) { v[e] = cvt_in(src(e, uni)); });
+            fft_wg<LOG2N2, -1, false, false, false>(v, j, tb, ColLds<float2, true>{lds + c});  // first LDS use
+            const uint32_t woff = (opaque((uint32_t)col) + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
+            T* const ob = uniform_ptr(out);
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                Elem<T>::store(at(ob + ((int64_t)(TPV * e) << a.log2n1), woff), cscale(v[e], a.scale));
+        }
+    }
+}
+
+// ---------------------------------------------------------- launchers
+template <class T, int FORM, int LOG2N2>
+static hipError_t k1_one(const K1Args& a, hipStream_t s) {
+    const int ntiles = a.nblocks * ((1 << a.log2n1) >> 4);
+    const int grid = (ntiles + 7) & ~7;
+    hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, FORM>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T, int FORM>
+static hipError_t k1_dispatch(int log2n2, const K1Args& a, hipStream_t s) {
+    switch (log2n2) {
+        case 5: return k1_one<T, FORM, 5>(a, s);
+        case 6: return k1_one<T, FORM, 6>(a, s);
+        case 7: return k1_one<T, FORM, 7>(a, s);
+        case 8: return k1_one<T, FORM, 8>(a, s);
+        case 9: return k1_one<T, FORM, 9>(a, s);
+        case 10: return k1_one<T, FORM, 10>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T, int LOG2N2>
+static hipError_t k1_aip_one(const K1Args& a, hipStream_t s) {
+    const int ntiles = a.nblocks * ((1 << a.log2n1) >> 4);
+    const int grid = (ntiles + 7) & ~7;
+    hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, kFormF32, true>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t k1_aip_dispatch(int log2n2, const K1Args& a, hipStream_t s) {
+    switch (log2n2) {
+        case 5: return k1_aip_one<T, 5>(a, s);
+        case 6: return k1_aip_one<T, 6>(a, s);
+        case 7: return k1_aip_one<T, 7>(a, s);
+        case 8: return k1_aip_one<T, 8>(a, s);
+        case 9: return k1_aip_one<T, 9>(a, s);
+        case 10: return k1_aip_one<T, 10>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_k1_aip(int prec, int log2n2, const K1Args& a, hipStream_t s) {
+    switch (prec) {
+        case kFp32: return k1_aip_dispatch<float2>(log2n2, a, s);
+        case kMixedValu: return k1_aip_dispatch<__half2>(log2n2, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s) {
+    switch (prec) {
+        case kMixed: return k1_dispatch<__half2, kFormMfma>(log2n2, a, s);
+        case kMixedValu: return k1_dispatch<__half2, kFormF32>(log2n2, a, s);
+        case kHalf: return k1_dispatch<__half2, kFormF16>(log2n2, a, s);
+        default: return k1_dispatch<float2, kFormF32>(log2n2, a, s);
+    }
+}
+
+}  // namespace pond

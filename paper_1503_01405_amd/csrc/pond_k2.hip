@@ -1,0 +1,393 @@
+// K2: the middle (row) pass of the four-step transform: four-step
+// twiddle, forward row FFT, inverse ISM response, inverse row FFT,
+// conjugate twiddle; and the tables it reads.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "pond_device.hpp"
+
+namespace pond {
+
+// Row table of the middle pass, one float4 per (k2, k1):
+//   (x, y) = W_n^(k1 k2) = exp(-2 pi i (k1 k2 mod n) / n), the four-step twiddle
+//   (z, w) = exp(-2 pi i turns_k), k = k2 + n2 k1, the inverse ISM response
+//            of Sec. 3.7 / Eq. (4); turns_k and its reduction mod 1 are float64.
+// Built once per plan; every block reads the same table.
+__global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, int log2n1, int log2n2,
+                                                       double chirp_a, double f0, double df, double taper) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
+    const int64_t n = 1ll << log2n;
+    if (i >= n) return;
+    const int64_t k2 = i >> log2n1;
+    const int64_t k1 = i & ((1ll << log2n1) - 1);
+    const int64_t r = (k1 * k2) & (n - 1);
+    double s, c;
+    sincospi(2.0 * (double)r / (double)n, &s, &c);
+    const int64_t k = k2 + (k1 << log2n2);
+    const int64_t kk = k < (n >> 1) ? k : k - n;
+    const double f = (double)kk * df;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double cs, cc;
+    sincospi(2.0 * frac, &cs, &cc);
+    const double w = taper_w(f, df * (double)n, taper);
+    tab[i] = make_float4((float)c, (float)-s, (float)(cc * w), (float)(-cs * w));
+}
+
+// One workgroup takes row k2 (ROWS rows for short rows) of one block.  The
+// workgroups of one row for all blocks of the launch get consecutive logical
+// indices on one XCD, so they run together and share the row's table entries
+// through that XCD's L2 (the table is then fetched from HBM about once per
+// launch).
+//   MODE kRowFull: twiddle, forward FFT, chirp, inverse FFT, conjugate
+//                  twiddle, in place (float4 table: twiddle, chirp).
+//   MODE kRowFwd:  twiddle and forward FFT only, in place: leaves the block's
+//                  spectrum, row k2 holding bins k2 + n2 k1 (float2 twiddle table).
+//   MODE kRowInv:  spectrum (in) times one trial's chirp (float2 table),
+//                  inverse FFT, conjugate twiddle, to `out`.
+//   MODE kRowInvPlain: kRowInv without the chirp (float32 arithmetic only).
+// F16: packed float16 arithmetic on float16 storage with float16 tables
+// (kRowFull: 4 halves per entry, twiddle/16 and chirp*2^-kHalfRem; split
+// modes: twiddle/16 and chirp).  The forward transform is normalised stage
+// by stage (1/16 of the first stage in the twiddle table), so the spectrum
+// is the block's spectrum / n; the output is 1/16 of the float32 forms'.
+template <int LOG2N1, class T, int MODE, bool F16>
+__global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+k2_row(K2Args a) {
+    using Sh = K2Shape<LOG2N1>;
+    using V = std::conditional_t<F16, h2, float2>;
+    constexpr int TPV = Sh::TPV;
+    __shared__ V lds[Sh::ROWS * Sh::STRIDE];
+
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    const int n2 = 1 << a.log2n2;
+    const int row_groups = (n2 + Sh::ROWS - 1) / Sh::ROWS;
+    if (logical >= row_groups * a.nblocks) return;
+    const int rg = logical / a.nblocks;
+    const int b = logical - rg * a.nblocks;
+
+    const int r = threadIdx.x / TPV;
+    const int j = threadIdx.x - r * TPV;
+    const int row = rg * Sh::ROWS + r;
+    const bool valid = row < n2;
+    // packed float16 rows of 2^12 and more: per-stage bank-conflict-free layouts
+    using RowL = std::conditional_t<F16 && LOG2N1 >= 12, StageRowLds<V>, PadLds<V>>;
+    const RowL lrow{lds + r * Sh::STRIDE};
+    static_assert(!(F16 && LOG2N1 >= 12) || (Sh::STRIDE >= (1 << LOG2N1) + 16 * ((1 << LOG2N1) >> 8)),
+                  "per-stage layouts fit the row");
+
+    StageBases<LOG2N1, V> tb;
+    tb.load(j, a.tw1);
+    // Uniform base pointers plus 32-bit per-thread offsets (rows beyond n2,
+    // possible only for the shortest rows, re-read the last row and never
+    // store).
+    const int row0 = min(rg * Sh::ROWS, n2 - 1);
+    const uint32_t toff = (uint32_t)(min(r, n2 - 1 - row0) << LOG2N1) + (uint32_t)j;
+    const int64_t rowbase = (((int64_t)b << a.log2n2) + row0) << LOG2N1;
+    T* rows = reinterpret_cast<T*>(a.work) + rowbase;
+    constexpr bool INV = MODE == kRowInv || MODE == kRowInvPlain;
+    const T* src = INV ? reinterpret_cast<const T*>(a.in) + rowbase : rows;
+    T* dst = INV ? reinterpret_cast<T*>(a.out) + rowbase : rows;
+
+    if constexpr (F16) {
+        __shared__ h2 s1tab[kS1Pairs];
+        fill_stage1_table<LOG2N1>(s1tab, a.tw1, threadIdx.x);
+        const uint2* tab = reinterpret_cast<const uint2*>(a.htable) + ((int64_t)row0 << LOG2N1);
+        const h2* tw4 = reinterpret_cast<const h2*>(a.htw4) + ((int64_t)row0 << LOG2N1);
+        const h2* chirp = reinterpret_cast<const h2*>(a.hchirp) + ((int64_t)row0 << LOG2N1);
+        auto tw_at = [&](uint32_t i) {
+            if constexpr (MODE == kRowFull) return __builtin_bit_cast(h2, at(tab, i * 8u)->x);
+            else return *at(tw4, i * 4u);
+        };
+        h2 v[16];
+        uint32_t to = opaque(toff);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const uint32_t i = to + TPV * e;
+            const h2 x = ld_h2(at(src, i * (uint32_t)sizeof(T)));
+            if constexpr (MODE == kRowInv) v[e] = cmul(x, *at(chirp, i * 4u));
+            else v[e] = cmul(x, tw_at(i));
+        }
+        // kRowFull: the chirp of each element is fetched during the forward
+        // transform's last exchange.
+        h2 ch[16];
+        auto fetch_chirp = [&] {
+            const uint32_t t2 = opaque(toff);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) ch[e] = __builtin_bit_cast(h2, at(tab, (t2 + TPV * e) * 8u)->y);
+        };
+        if constexpr (MODE == kRowFull) fft_wg<LOG2N1, -1, true, true>(v, j, tb, lrow, s1tab, fetch_chirp);
+        else if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true, true>(v, j, tb, lrow, s1tab);
+        if constexpr (MODE == kRowFwd) {
+            constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N1>::kHalfRem);
+            if (valid) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    st_h2(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), v[e] * (_Float16)osc);
+            }
+            return;
+        }
+        if constexpr (MODE == kRowFull) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], ch[e]);
+        }
+        // the output twiddles are fetched during the inverse transform's
+        // last exchange (rather than one dependent load per store)
+        h2 wo[16];
+        auto fetch_tw = [&] {
+            const uint32_t t2 = opaque(toff);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) wo[e] = tw_at(t2 + TPV * e);
+        };
+        fft_wg<LOG2N1, +1, false, true>(v, j, tb, lrow, s1tab, fetch_tw);
+        asm volatile("" ::: "memory");
+        to = opaque(toff);
+        if (valid) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                st_h2(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cmulc(v[e], wo[e]));
+        }
+        return;
+    } else {
+        const float4* tab = a.table + ((int64_t)row0 << LOG2N1);
+        const float2* tw4 = a.tw4 + ((int64_t)row0 << LOG2N1);
+        const float2* chirp = a.chirp + ((int64_t)row0 << LOG2N1);
+        float2 v[16];
+        uint32_t to = opaque(toff);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float2 x = Elem<T>::load(at(src, (to + TPV * e) * (uint32_t)sizeof(T)));
+            if constexpr (MODE == kRowFull) {
+                const float4 t = *at(tab, (to + TPV * e) * 16u);
+                v[e] = cmul(x, make_float2(t.x, t.y));
+            } else if constexpr (MODE == kRowFwd) {
+                v[e] = cmul(x, *at(tw4, (to + TPV * e) * 8u));
+            } else if constexpr (MODE == kRowInv) {
+                v[e] = cmul(x, *at(chirp, (to + TPV * e) * 8u));
+            } else {
+                v[e] = x;  // kRowInvPlain: the filter was applied before (real input path)
+            }
+        }
+        // kRowFull: the chirp is fetched again (from L2) during the forward
+        // transform's last exchange rather than kept live across it.
+        float2 ch[16];
+        auto fetch_chirp = [&] {
+            const uint32_t t2 = opaque(toff);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const float4 t = *at(tab, (t2 + TPV * e) * 16u);
+                ch[e] = make_float2(t.z, t.w);
+            }
+        };
+        if constexpr (MODE == kRowFull) {
+            fft_wg<LOG2N1, -1>(v, j, tb, lrow, nullptr, fetch_chirp);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], ch[e]);
+        } else if constexpr (MODE != kRowInv && MODE != kRowInvPlain) {
+            fft_wg<LOG2N1, -1>(v, j, tb, lrow);
+        }
+        if constexpr (MODE == kRowFwd) {
+            if (valid) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+            }
+            return;
+        }
+        // output twiddles fetched during the inverse transform's last exchange
+        float2 wo[16];
+        auto fetch_tw = [&] {
+            const uint32_t t2 = opaque(toff);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                if constexpr (MODE == kRowFull) {
+                    const float4 t = *at(tab, (t2 + TPV * e) * 16u);
+                    wo[e] = make_float2(t.x, t.y);
+                } else {
+                    wo[e] = *at(tw4, (t2 + TPV * e) * 8u);
+                }
+            }
+        };
+        fft_wg<LOG2N1, +1>(v, j, tb, lrow, nullptr, fetch_tw);
+        asm volatile("" ::: "memory");
+        to = opaque(toff);
+        if (valid) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(cmulc(v[e], wo[e]), a.scale));
+        }
+    }
+}
+
+// Float16 table of the middle pass for the packed-float16 form, 8 bytes per
+// (k2, k1): the four-step twiddle / 16 and the inverse ISM response times
+// 2^-rem (rem: the part of the row normalisation not applied by the
+// transform's stages), both evaluated in float64 as in k2_build_table.
+__global__ void __launch_bounds__(256) k2_build_table_h(uint2* __restrict__ tab, int log2n1, int log2n2,
+                                                         double chirp_a, double f0, double df, double chirp_scale,
+                                                         double taper) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
+    const int64_t n = 1ll << log2n;
+    if (i >= n) return;
+    const int64_t k2 = i >> log2n1;
+    const int64_t k1 = i & ((1ll << log2n1) - 1);
+    const int64_t r = (k1 * k2) & (n - 1);
+    double s, c;
+    sincospi(2.0 * (double)r / (double)n, &s, &c);
+    const int64_t k = k2 + (k1 << log2n2);
+    const int64_t kk = k < (n >> 1) ? k : k - n;
+    const double f = (double)kk * df;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double cs, cc;
+    sincospi(2.0 * frac, &cs, &cc);
+    const h2 tw = f16_unit(c / 16.0, -s / 16.0, 1.0 / 16.0);
+    const double m = chirp_scale * taper_w(f, df * (double)n, taper);
+    const h2 ch = f16_unit(cc * m, -cs * m, m);
+    tab[i] = make_uint2(__builtin_bit_cast(uint32_t, tw), __builtin_bit_cast(uint32_t, ch));
+}
+
+// Float16 tables of the split middle pass: twiddle / 16 (tw) and, per trial
+// DM, the inverse ISM response (chirp).
+__global__ void __launch_bounds__(256) k2_build_split_tables_h(h2* __restrict__ tw, h2* __restrict__ chirp,
+                                                                int log2n1, int log2n2, double chirp_a, double f0,
+                                                                double df) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
+    const int64_t n = 1ll << log2n;
+    if (i >= n) return;
+    const int64_t k2 = i >> log2n1;
+    const int64_t k1 = i & ((1ll << log2n1) - 1);
+    if (tw) {
+        const int64_t r = (k1 * k2) & (n - 1);
+        double s, c;
+        sincospi(2.0 * (double)r / (double)n, &s, &c);
+        tw[i] = f16_unit(c / 16.0, -s / 16.0, 1.0 / 16.0);
+    }
+    const int64_t k = k2 + (k1 << log2n2);
+    const int64_t kk = k < (n >> 1) ? k : k - n;
+    const double f = (double)kk * df;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double cs, cc;
+    sincospi(2.0 * frac, &cs, &cc);
+    chirp[i] = f16_unit(cc, -cs, 1.0);
+}
+
+// Tables of the split middle pass: tw[i] = W_n^(k1 k2) for i = k2 n1 + k1;
+// per trial DM, chirp[i] = exp(-2 pi i turns_k), k = k2 + n2 k1, turns in
+// float64 reduced mod 1 (Sec. 3.7 / Eq. (4)).
+__global__ void __launch_bounds__(256) k2_build_split_tables(float2* __restrict__ tw, float2* __restrict__ chirp,
+                                                              int log2n1, int log2n2, double chirp_a, double f0,
+                                                              double df) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int log2n = log2n1 + log2n2;
+    const int64_t n = 1ll << log2n;
+    if (i >= n) return;
+    const int64_t k2 = i >> log2n1;
+    const int64_t k1 = i & ((1ll << log2n1) - 1);
+    if (tw) {
+        const int64_t r = (k1 * k2) & (n - 1);
+        double s, c;
+        sincospi(2.0 * (double)r / (double)n, &s, &c);
+        tw[i] = make_float2((float)c, (float)-s);
+    }
+    if (!chirp) return;
+    const int64_t k = k2 + (k1 << log2n2);
+    const int64_t kk = k < (n >> 1) ? k : k - n;
+    const double f = (double)kk * df;
+    const double turns = chirp_a * (f * f) / (f0 + f);
+    const double frac = turns - rint(turns);
+    double cs, cc;
+    sincospi(2.0 * frac, &cs, &cc);
+    chirp[i] = make_float2((float)cc, (float)-cs);
+}
+
+template <class T, int MODE, bool F16, int LOG2N1>
+static hipError_t k2_one(const K2Args& a, hipStream_t s) {
+    using Sh = K2Shape<LOG2N1>;
+    const int groups = ((1 << a.log2n2) + Sh::ROWS - 1) / Sh::ROWS * a.nblocks;
+    const int grid = (groups + 7) & ~7;
+    hipLaunchKernelGGL((k2_row<LOG2N1, T, MODE, F16>), dim3(grid), dim3(Sh::THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T, int MODE, bool F16>
+static hipError_t k2_dispatch(int log2n1, const K2Args& a, hipStream_t s) {
+    switch (log2n1) {
+        case 5: return k2_one<T, MODE, F16, 5>(a, s);
+        case 6: return k2_one<T, MODE, F16, 6>(a, s);
+        case 7: return k2_one<T, MODE, F16, 7>(a, s);
+        case 8: return k2_one<T, MODE, F16, 8>(a, s);
+        case 9: return k2_one<T, MODE, F16, 9>(a, s);
+        case 10: return k2_one<T, MODE, F16, 10>(a, s);
+        case 11: return k2_one<T, MODE, F16, 11>(a, s);
+        case 12: return k2_one<T, MODE, F16, 12>(a, s);
+        case 13: return k2_one<T, MODE, F16, 13>(a, s);
+        case 14: return k2_one<T, MODE, F16, 14>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int MODE>
+static hipError_t k2_prec(int prec, int log2n1, const K2Args& a, hipStream_t s) {
+    switch (prec) {
+        case kFp32: return k2_dispatch<float2, MODE, false>(log2n1, a, s);
+        case kHalf: return k2_dispatch<__half2, MODE, true>(log2n1, a, s);
+        default: return k2_dispatch<__half2, MODE, false>(log2n1, a, s);
+    }
+}
+
+hipError_t launch_k2(int prec, int mode, int log2n1, const K2Args& a, hipStream_t s) {
+    switch (mode) {
+        case kRowFull: return k2_prec<kRowFull>(prec, log2n1, a, s);
+        case kRowFwd: return k2_prec<kRowFwd>(prec, log2n1, a, s);
+        case kRowInv: return k2_prec<kRowInv>(prec, log2n1, a, s);
+        case kRowInvPlain:
+            // float32 arithmetic forms only (the real input path)
+            if (prec == kFp32) return k2_dispatch<float2, kRowInvPlain, false>(log2n1, a, s);
+            if (prec == kMixedValu) return k2_dispatch<__half2, kRowInvPlain, false>(log2n1, a, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_k2_build_split_tables(float2* tw, float2* chirp, int log2n1, int log2n2, double chirp_a, double f0,
+                                        double df, hipStream_t s) {
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    hipLaunchKernelGGL(k2_build_split_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tw, chirp, log2n1,
+                       log2n2, chirp_a, f0, df);
+    return hipGetLastError();
+}
+
+hipError_t launch_k2_build_split_tables_h(void* tw, void* chirp, int log2n1, int log2n2, double chirp_a, double f0,
+                                          double df, hipStream_t s) {
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    hipLaunchKernelGGL(k2_build_split_tables_h, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<h2*>(tw), reinterpret_cast<h2*>(chirp), log2n1, log2n2, chirp_a, f0, df);
+    return hipGetLastError();
+}
+
+hipError_t launch_k2_build_table_h(void* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
+                                   double taper, hipStream_t s) {
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    const double chirp_scale = std::ldexp(1.0, -half_row_rem(log2n1));
+    hipLaunchKernelGGL(k2_build_table_h, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<uint2*>(tab), log2n1, log2n2, chirp_a, f0, df, chirp_scale, taper);
+    return hipGetLastError();
+}
+
+hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
+                                 double taper, hipStream_t s) {
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    hipLaunchKernelGGL(k2_build_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n1, log2n2,
+                       chirp_a, f0, df, taper);
+    return hipGetLastError();
+}
+
+}  // namespace pond
