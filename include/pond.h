@@ -95,6 +95,9 @@ typedef struct pond_info {
     int32_t precision;     /* POND_FP32, POND_MIXED, POND_MIXED_VALU or POND_HALF  */
     uint32_t status;       /* POND_STATUS_* bits (read synchronously)              */
     int32_t input_kind;    /* POND_INPUT_*                                         */
+    double  power_gain;    /* POND_HALF: measured power gain of the plan's float16 */
+                           /* arithmetic, divided out of every detected power     */
+                           /* (1.0 in the other forms)                            */
 } pond_info;
 
 /* Input kinds of a plan (pond_info.input_kind).  For a real-input plan the

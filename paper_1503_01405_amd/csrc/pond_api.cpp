@@ -62,6 +62,11 @@ struct pond_plan {
     float4* table = nullptr;    // float32 forms
     void* htable = nullptr;     // packed float16 form (8 bytes per entry)
     float pscale = 1.0f;        // detected-power scale applied in K3
+    // Packed float16: the middle pass leaves 1/16 of the value (its twiddle
+    // table carries the first stage's 1/16), so the power scale is 256
+    // divided by half_gain, the measured power gain of the float16
+    // arithmetic (half_power_gain).
+    double half_gain = 1.0;
     double taper = 0.0;         // Tukey edge fraction of the inverse filter (0: unit taper)
     uint64_t* acc_sum = nullptr;
     uint64_t* acc_cnt = nullptr;
@@ -185,90 +190,93 @@ int64_t n_blocks_for(int64_t nsamp, int64_t nfft, int64_t hop) {
 namespace pond {
 
 namespace {
-float2 h_cmul(float2 a, float2 b) {
-    return make_float2(std::fma(a.x, b.x, -(a.y * b.y)), std::fma(a.x, b.y, a.y * b.x));
-}
-// The device's float32 power tree (powers<R>) and W16 products (mul_w16,
-// forward direction), replicated in the same float32 operations.
-void h_powers(float2 w, int R, float2* p) {
-    p[0] = make_float2(1.f, 0.f);
-    if (R > 1) p[1] = w;
-    if (R > 2) p[2] = h_cmul(w, w);
-    if (R > 3) p[3] = h_cmul(p[2], w);
-    if (R > 4) {
-        p[4] = h_cmul(p[2], p[2]);
-        p[5] = h_cmul(p[4], w);
-        p[6] = h_cmul(p[4], p[2]);
-        p[7] = h_cmul(p[4], p[3]);
-    }
-    if (R > 8) {
-        p[8] = h_cmul(p[4], p[4]);
-        for (int q = 9; q < 16; ++q) p[q] = h_cmul(p[8], p[q - 8]);
-    }
-}
-float2 h_mul_w16(int u, float2 a) {
-    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
-    auto cs = [&](float c, float s) { return make_float2(std::fma(a.x, c, a.y * s), std::fma(a.y, c, -(a.x * s))); };
-    switch (u & 15) {
-        case 0: return a;
-        case 4: return make_float2(a.y, -a.x);
-        case 8: return make_float2(-a.x, -a.y);
-        case 12: return make_float2(-a.y, a.x);
-        case 2: return make_float2((a.x + a.y) * h, (a.y - a.x) * h);
-        case 6: return make_float2((a.y - a.x) * h, -(a.x + a.y) * h);
-        case 10: return make_float2(-(a.x + a.y) * h, (a.x - a.y) * h);
-        case 14: return make_float2((a.x - a.y) * h, (a.x + a.y) * h);
-        case 1: return cs(c1, s1);
-        case 3: return cs(s1, c1);
-        case 5: return cs(-s1, c1);
-        case 7: return cs(-c1, s1);
-        case 9: return cs(-c1, -s1);
-        case 11: return cs(-s1, -c1);
-        case 13: return cs(s1, -c1);
-        default: return cs(c1, -s1);
-    }
-}
-double h_f16sq(float2 v) {
-    const double x = (double)(_Float16)v.x, y = (double)(_Float16)v.y;
-    return x * x + y * y;
+// splitmix64 (Steele, Lea & Flood 2014): the calibration noise generator.
+uint64_t splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
 }
 }  // namespace
 
-// Mean power gain of the float16 stage twiddles of a length-2^log2l
-// transform in the packed-float16 form: each stage multiplies its inputs by
-// float16 roundings of exact powers, and the mean of |w|^2 over a stage's
-// fixed set of twiddles is not exactly 1 (a few 1e-5); for white input a
-// stage scales the mean power by that mean.  Summed over the stages.
-double half_twiddle_gain(int log2l) {
-    const int64_t L = (int64_t)1 << log2l;
-    const std::vector<float2> tw = twiddles(L, L, 1);
-    const int full = log2l / 4, rem = 1 << (log2l % 4);
-    const int nst = full + (rem > 1 ? 1 : 0);
-    double total = 0;
-    int64_t ns = 1;
-    for (int st = 0; st < nst; ++st) {
-        const int R = st < full ? 16 : rem;
-        if (ns > 1) {
-            double acc = 0;
-            int64_t cnt = 0;
-            float2 p[16];
-            if (R == 16) {
-                for (int64_t k = 0; k < ns; ++k) {
-                    h_powers(tw[(size_t)(k * (L / (16 * ns)))], 16, p);
-                    for (int q = 0; q < 16; ++q, ++cnt) acc += h_f16sq(p[q]);
-                }
-            } else {
-                for (int64_t j = 0; j < L / 16; ++j)
-                    for (int u = 0; u < 16 / R; ++u) {
-                        h_powers(h_mul_w16(u, tw[(size_t)j]), R, p);
-                        for (int q = 0; q < R; ++q, ++cnt) acc += h_f16sq(p[q]);
-                    }
-            }
-            total += acc / (double)cnt - 1.0;
+hipError_t half_power_gain(const HalfCal& c, const std::function<hipError_t(int, const void**)>& middle,
+                           double* gain) {
+    const int log2n = c.log2n1 + c.log2n2;
+    const int64_t n = (int64_t)1 << log2n;
+    const int64_t nblk = n >= ((int64_t)1 << 22) ? 1 : ((int64_t)1 << 22) / n;
+    const int64_t nsamp = nblk * n;
+    std::vector<int8_t> iq((size_t)(2 * nsamp));
+    int64_t energy = 0;
+    for (int64_t i = 0; i < nsamp; i += 4) {
+        const uint64_t h = splitmix64((uint64_t)i);
+        for (int k = 0; k < 8; ++k) {
+            const int8_t v = (int8_t)((h >> (8 * k)) & 0xff);
+            iq[(size_t)(2 * i + k)] = v;
+            energy += (int64_t)v * v;
         }
-        ns *= R;
     }
-    return total;
+    int8_t* d_iq = nullptr;
+    float* d_ser = nullptr;
+    uint64_t* d_part = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d_iq), iq.size());
+    const int64_t nser = nsamp / 16;
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_ser), (size_t)nser * sizeof(float));
+    // per-workgroup partials of a one-bin fold (unused) and the status word
+    constexpr int64_t kParts = 4096;
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_part), (size_t)kParts * 12 + 8);
+    if (e == hipSuccess) e = hipMemcpy(d_iq, iq.data(), iq.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d_part, 0, (size_t)kParts * 12 + 8);
+    for (int64_t b = 0; b < nblk && e == hipSuccess; b += c.max_batch) {
+        const int nb = (int)(nblk - b < c.max_batch ? nblk - b : c.max_batch);
+        K1Args a1{};
+        a1.tail = d_iq;
+        a1.in = d_iq;
+        a1.hop = n;
+        a1.block0 = b;
+        a1.nblocks = nb;
+        a1.log2n1 = c.log2n1;
+        a1.work = c.work;
+        a1.tw2 = c.tw2;
+        e = launch_k1(kHalf, c.log2n2, a1, nullptr);
+        const void* mid = nullptr;
+        if (e == hipSuccess) e = middle(nb, &mid);
+        if (e != hipSuccess) break;
+        K3Args a3{};
+        a3.work = mid;
+        a3.nblocks = nb;
+        a3.log2n1 = c.log2n1;
+        a3.hop = n;
+        a3.n_front = 0;
+        a3.block0 = b;
+        a3.tw2 = c.tw2;
+        a3.scale = 1.0f;
+        a3.pscale = 256.0f;
+        a3.series = d_ser;
+        a3.series_base = 0;
+        a3.decim = 16;
+        a3.nbins = 1;
+        a3.inv_pfs = 1.0 / (double)n;
+        a3.subint = 0;
+        a3.entries = 1;
+        a3.part_sum = d_part;
+        a3.part_cnt = reinterpret_cast<uint32_t*>(d_part + kParts);
+        a3.status = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_part) + kParts * 12);
+        const int64_t items = (int64_t)nb << (c.log2n1 - 4);
+        int grid = k3_grid(c.log2n2, kHalf, 12, items, 1, false);
+        if (grid > kParts) grid = (int)kParts;
+        e = launch_k3(kHalf, c.log2n2, a3, grid, 12, nullptr);
+    }
+    std::vector<float> ser((size_t)nser);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e == hipSuccess) e = hipMemcpy(ser.data(), d_ser, (size_t)nser * sizeof(float), hipMemcpyDeviceToHost);
+    if (d_iq) (void)hipFree(d_iq);
+    if (d_ser) (void)hipFree(d_ser);
+    if (d_part) (void)hipFree(d_part);
+    if (e != hipSuccess) return e;
+    double power = 0.0;
+    for (float v : ser) power += (double)v;
+    *gain = power / (double)energy;
+    return std::isfinite(*gain) && *gain > 0.5 && *gain < 2.0 ? hipSuccess : hipErrorInvalidValue;
 }
 
 // Device bytes a plan allocates in pond_plan_create_ex (the accumulator
@@ -408,11 +416,6 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     p->max_batch = max_batch = default_max_batch(nfft, precision, max_batch);
 
     p->hist_cap = hist_capacity(p->log2n2, p->precision);
-    // Packed float16: the middle pass leaves 1/16 of the value (its twiddle
-    // table carries the first stage's 1/16), so power x 256, divided by the
-    // gain of the float16 stage twiddles of the four transforms.
-    if (precision == POND_HALF)
-        p->pscale = (float)(256.0 / (1.0 + 2.0 * half_twiddle_gain(p->log2n2) + 2.0 * half_twiddle_gain(p->log2n1)));
 
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) {
@@ -440,6 +443,32 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
         chk(hipMalloc(reinterpret_cast<void**>(&p->table), (size_t)nfft * sizeof(float4)));
     }
     if (e == hipSuccess) chk(build_filter(p, 0.0));
+    // Packed float16: the power scale is 256 over the measured gain of the
+    // plan's float16 arithmetic (the unit-taper table just built).
+    if (e == hipSuccess && precision == POND_HALF && kind == POND_INPUT_COMPLEX) {
+        HalfCal cal;
+        cal.log2n1 = p->log2n1;
+        cal.log2n2 = p->log2n2;
+        cal.tw2 = p->tw2;
+        cal.work = p->work;
+        cal.max_batch = p->max_batch;
+        double g = 1.0;
+        chk(half_power_gain(
+            cal,
+            [&](int nb, const void** res) {
+                K2Args a2{};
+                a2.work = p->work;
+                a2.nblocks = nb;
+                a2.log2n2 = p->log2n2;
+                a2.tw1 = p->tw1;
+                a2.htable = p->htable;
+                *res = p->work;
+                return launch_k2(POND_HALF, kRowFull, p->log2n1, a2, nullptr);
+            },
+            &g));
+        p->half_gain = g;
+        p->pscale = (float)(256.0 / g);
+    }
     p->acc_slots = 4;
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_sum), (size_t)p->acc_slots * nbins * 8));
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_cnt), (size_t)p->acc_slots * nbins * 8));
@@ -537,6 +566,7 @@ int32_t pond_plan_query(pond_plan* p, pond_info* out) {
     out->inv_pfs = p->inv_pfs;
     out->nbins = p->nbins;
     out->precision = p->precision;
+    out->power_gain = p->half_gain;
     if (p->sticky) return POND_EDEVICE;
     DeviceGuard g(p->device);
     uint64_t st = 0;

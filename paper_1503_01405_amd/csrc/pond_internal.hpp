@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 namespace pond {
 
 // Fixed-point scale of the fold accumulators: a power p is accumulated as
@@ -174,8 +176,24 @@ int64_t hist_capacity(int log2n2, int prec);
 // blocks per launch it picks (max_batch <= 0: the default).
 int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t max_batch);
 int plan_max_batch(int64_t nfft, int32_t precision, int32_t max_batch);
-// Mean power gain of the packed-float16 stage twiddles of a 2^log2l transform.
-double half_twiddle_gain(int log2l);
+// Power gain of a packed-float16 path, measured.  White int8 noise of at
+// least 2^22 samples, cut into blocks of n = 2^(log2n1 + log2n2), is pushed
+// through K1, the caller's middle pass and K3 with the whole block kept
+// (n_front 0, hop n) and detected at scale 256; since the transform pair and
+// every filter the path applies are all-pass, the exact output power is the
+// input power (Parseval), and the ratio of the two is the gain of the
+// float16 arithmetic (rounded twiddles, constants, table entries and
+// roundings), to about 1e-6.  middle(nb, &result) runs the middle pass on nb
+// blocks in `work` and names the buffer K3 reads.  Synchronous; runs on the
+// null stream.
+struct HalfCal {
+    int log2n1 = 0, log2n2 = 0;
+    const float2* tw2 = nullptr;  // exp(-2 pi i t / n2)
+    void* work = nullptr;         // max_batch blocks of float16 pairs
+    int max_batch = 1;
+};
+hipError_t half_power_gain(const HalfCal& c, const std::function<hipError_t(int, const void**)>& middle,
+                           double* gain);
 
 // Static LDS bytes of the K3 tile for a column length 2^log2n2.
 size_t k3_static_lds(int log2n2, int prec);

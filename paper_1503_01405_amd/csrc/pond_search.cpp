@@ -191,11 +191,7 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
         chk(hipMalloc(&g.spec, (size_t)g.max_batch * g.nfft * s->elem));
         chk(hipMalloc(&g.out, (size_t)g.max_batch * g.nfft * s->elem));
         const bool half = precision == POND_HALF;
-        if (half)
-            g.pscale = (float)(256.0 / (1.0 + 2.0 * half_twiddle_gain(g.log2n2) + 2.0 * half_twiddle_gain(g.log2n1)));
-        if (half) {
-            chk(hipMalloc(&g.htw4, g.nfft * 4));
-        }
+        if (half) chk(hipMalloc(&g.htw4, g.nfft * 4));
         else chk(hipMalloc(reinterpret_cast<void**>(&g.tw4), g.nfft * sizeof(float2)));
         g.chirp.assign(g.trials.size(), nullptr);
         g.hchirp.assign(g.trials.size(), nullptr);
@@ -213,6 +209,38 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
                     chk(launch_k2_build_split_tables(i == 0 ? g.tw4 : nullptr, g.chirp[i], g.log2n1, g.log2n2, a,
                                                      f0_mhz, df, nullptr));
             }
+        }
+        // Packed float16: power scale 256 over the measured gain of the
+        // group's float16 path (forward rows, then the inverse rows of the
+        // group's first trial; every trial's table rounds alike).
+        if (half && e == hipSuccess) {
+            HalfCal cal;
+            cal.log2n1 = g.log2n1;
+            cal.log2n2 = g.log2n2;
+            cal.tw2 = g.tw2;
+            cal.work = g.spec;
+            cal.max_batch = g.max_batch;
+            double gain = 1.0;
+            chk(half_power_gain(
+                cal,
+                [&](int nb, const void** res) {
+                    K2Args f{};
+                    f.work = g.spec;
+                    f.nblocks = nb;
+                    f.log2n2 = g.log2n2;
+                    f.tw1 = g.tw1;
+                    f.htw4 = g.htw4;
+                    hipError_t r = launch_k2(POND_HALF, kRowFwd, g.log2n1, f, nullptr);
+                    K2Args v = f;
+                    v.in = g.spec;
+                    v.out = g.out;
+                    v.hchirp = g.hchirp[0];
+                    if (r == hipSuccess) r = launch_k2(POND_HALF, kRowInv, g.log2n1, v, nullptr);
+                    *res = g.out;
+                    return r;
+                },
+                &gain));
+            g.pscale = (float)(256.0 / gain);
         }
     }
     chk(hipMalloc(reinterpret_cast<void**>(&s->acc_sum), (size_t)ntrials * nbins * 8));

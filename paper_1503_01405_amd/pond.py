@@ -69,6 +69,7 @@ class pond_info(ctypes.Structure):
         ("delta_hi_s", ctypes.c_double), ("inv_pfs", ctypes.c_double),
         ("nbins", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("status", ctypes.c_uint32), ("input_kind", ctypes.c_int32),
+        ("power_gain", ctypes.c_double),
     ]
 
 

@@ -84,3 +84,24 @@ def profile_rel_l2(a, b):
     """Maximum over sub-integrations of the per-profile relative L2 error."""
     assert a.shape == b.shape, (a.shape, b.shape)
     return max((rel_l2(a[i], b[i]) for i in range(a.shape[0])), default=0.0)
+
+
+EPS_HALF = 5e-3     # bound on the per-sample relative error of a float16-form detected power
+BIAS_TOL = 2e-5     # systematic power gain allowed in any form
+
+
+def power_gain(prof, oprof, cnts):
+    """Total folded power of the GPU profiles over the oracle's: each bin's
+    mean weighted by its count (the oracle's), summed over every profile.
+    A systematic gain of the arithmetic shows here undiluted, while
+    zero-mean rounding noise averages out over all outputs."""
+    prof = np.asarray(prof, np.float64)
+    oprof = np.asarray(oprof, np.float64)
+    cnts = np.asarray(cnts, np.float64)[:prof.shape[0]]
+    return float((prof * cnts).sum() / (oprof * cnts).sum())
+
+
+def bias_tol(n_out):
+    """Allowed |power gain - 1| over n_out outputs: BIAS_TOL plus three
+    standard deviations of the float16 rounding noise of their mean."""
+    return BIAS_TOL + 3 * EPS_HALF / np.sqrt(max(1, n_out))
