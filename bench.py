@@ -358,9 +358,10 @@ SERVE_METRIC = "serving: aggregate Msamples/s of 16 concurrent streams (1 s bloc
 def serve_streams(seed=4):
     """The 16 stream descriptions: DM log-uniform in [0.5, 200], period
     uniform in [2 ms, 2 s], FFT length the smallest power of two in
-    [2^16, 2^24] whose half holds the smear's discard (2^24 otherwise)."""
+    [2^16, 2^24] whose half holds the smear's discard (2^24 otherwise),
+    with the geometry from the library (pond_geometry)."""
     import numpy as np
-    import oracle as O
+    import paper_1503_01405_amd as P
     rng = np.random.default_rng(seed)
     out = []
     for i in range(SERVE_STREAMS):
@@ -368,24 +369,23 @@ def serve_streams(seed=4):
         period = float(rng.uniform(2e-3, 2.0))
         n = 1 << 16
         while n < (1 << 24):
-            try:
-                if O.plan_geometry(F0, BW, dm, n)["discard"] <= n // 2:
-                    break
-            except ValueError:   # smear longer than n
-                pass
+            g = P.pond_geometry(F0, BW, dm, n)
+            if g is not None and g[1] <= n // 2:
+                break
             n *= 2
         out.append(dict(dm=round(dm, 3), period_s=round(period, 6), nfft=n))
     return out
 
 
 def serve_bytes(streams, blocks_per_stream, elem):
-    """Pass-model bytes of every overlap-save block the streams complete."""
-    import oracle as O
+    """Pass-model bytes of every overlap-save block the streams complete
+    (hop from the library's geometry)."""
+    import paper_1503_01405_amd as P
     total = 0
     for s in streams:
-        g = O.plan_geometry(F0, BW, s["dm"], s["nfft"])
+        hop = P.pond_geometry(F0, BW, s["dm"], s["nfft"])[2]
         nsamp = blocks_per_stream * SERVE_BLOCK
-        nb = 0 if nsamp < s["nfft"] else (nsamp - s["nfft"]) // g["hop"] + 1
+        nb = 0 if nsamp < s["nfft"] else (nsamp - s["nfft"]) // hop + 1
         total += nb * s["nfft"] * (2 + 4 * elem)
     return total
 

@@ -58,7 +58,10 @@ typedef struct pond_plan pond_plan;
 #define POND_EINVAL   (-1)  /* bad argument or call sequence; plan state untouched   */
 #define POND_ENOMEM   (-2)  /* device allocation failed; plan state untouched        */
 #define POND_EDEVICE  (-3)  /* HIP runtime error; sticky: only destroy is valid after */
-#define POND_EBUSY    (-4)  /* server: the stream does not fit the budget right now  */
+#define POND_EBUSY    (-4)  /* server: the stream can never fit the budget, or the    */
+                            /* stream cap is reached                                 */
+#define POND_ECANCELED (-5) /* server: a queued block of a stream closed before it    */
+                            /* was admitted; the block never ran                     */
 
 /* Precision forms. */
 #define POND_FP32   0  /* float32 storage and arithmetic                                   */
@@ -99,6 +102,15 @@ typedef struct pond_info {
                            /* arithmetic, divided out of every detected power     */
                            /* (1.0 in the other forms)                            */
 } pond_info;
+
+/*
+ * The overlap-save geometry pond_plan_create would use, without creating a
+ * plan (host arithmetic only): n_front, discard and hop of a block of nfft
+ * samples (rule above; any output pointer may be NULL).  POND_EINVAL for
+ * invalid arguments or when hop would not be positive.
+ */
+int32_t pond_geometry(double f0_mhz, double bw_mhz, double dm, int64_t nfft,
+                      int64_t* n_front, int64_t* discard, int64_t* hop);
 
 /* Input kinds of a plan (pond_info.input_kind).  For a real-input plan the
    counts of pond_info are in real samples (nfft, n_front, discard, hop,
@@ -160,7 +172,8 @@ int64_t pond_dedisperse_fold(pond_plan* p, const int8_t* iq, int64_t nsamp,
 /*
  * pond_dedisperse_fold plus, in the same pass, the detected series summed
  * over decim consecutive outputs (decim in {1, 2, 4, 8, 16}; decim <= 0
- * means 16, i.e. 1 us at 16 Msps).  Group i covers outputs
+ * means round(bw_mhz) outputs, i.e. 1 us (Sec. 4), which must then be one
+ * of those values, else POND_EINVAL).  Group i covers outputs
  * [decim*i, decim*i + decim); every group completed by this call is
  * written in order to series (device, capacity series_cap floats) and the
  * count to *n_series_out (host; may be NULL).  series may be NULL only if
@@ -269,7 +282,8 @@ pond_plan* pond_real_plan_create(double f0_mhz, double bw_mhz, double dm, int64_
  * Append nsamp real samples (raw: device, 2*nsamp int8 A/B pairs; nsamp
  * even) and fold every newly completed output, as pond_dedisperse_series:
  * subint_nsamp (even, fixed for the stream) and decim (2, 4, 8, 16 or 32;
- * <= 0 means 32, 1 us at 32 Msps) in real samples; series NULL: fold only.
+ * <= 0 means round(2 bw_mhz), 1 us of real samples, which must then be one
+ * of those values) in real samples; series NULL: fold only.
  * raw == NULL with nsamp == 0 ends the stream.  Returns the number of
  * profiles written or an error code; only for real-input plans (the
  * complex entry points refuse them, and this one refuses complex plans).
@@ -365,13 +379,28 @@ pond_server* pond_server_create(int64_t hbm_budget_bytes, int32_t max_streams);
    blocks per launch), or POND_EINVAL. */
 int64_t pond_server_stream_bytes(const pond_stream_desc* d);
 
-/* Admit a stream: returns its id (>= 0), POND_EBUSY if it does not fit the
-   budget (with fewer blocks per launch tried first) or the stream cap now,
-   POND_EINVAL for an invalid description, POND_ENOMEM / POND_EDEVICE. */
+/* Open a stream: returns its id (>= 0).  The stream is admitted at once if
+   it fits the budget left (with fewer blocks per launch tried first);
+   otherwise it waits, first come first, and is admitted by a later open,
+   poll or close once enough memory has been returned (its admission is
+   then reported by poll() as a completion with ticket POND_TICKET_ADMITTED).
+   Blocks may be submitted to a waiting stream; they run after admission.
+   POND_EBUSY if the stream would not fit even an empty server or the cap on
+   open plus waiting streams is reached, POND_EINVAL for an invalid
+   description, POND_ENOMEM / POND_EDEVICE if its admission failed. */
 int32_t pond_server_open(pond_server* s, const pond_stream_desc* d);
 
+#define POND_TICKET_ADMITTED (-1)  /* pond_completion.ticket of an admission       */
+#define POND_STREAM_WAITING 0      /* opened, waiting for budget                   */
+#define POND_STREAM_OPEN    1      /* admitted: plan and slots on the device       */
+#define POND_STREAM_CLOSED  2      /* closed (or its admission failed)             */
+
+/* State of a stream id (POND_STREAM_*), or POND_EINVAL. */
+int32_t pond_server_stream_state(const pond_server* s, int32_t stream);
+
 /* Submit the stream's next block (host_iq: 2*nsamp int8, 0 < nsamp <=
-   max_block_nsamp).  Returns a ticket (>= 0) or an error. */
+   max_block_nsamp) to an open or waiting stream.  Returns a ticket (>= 0)
+   or an error. */
 int64_t pond_server_submit(pond_server* s, int32_t stream, const int8_t* host_iq, int64_t nsamp);
 
 /* Report completed blocks (up to max_out, in completion order per stream)
@@ -386,9 +415,11 @@ int32_t pond_server_poll(pond_server* s, pond_completion* out, int32_t max_out, 
 int64_t pond_server_take_profiles(pond_server* s, int32_t stream, float* host_out, int64_t max_profiles);
 
 /* End a stream: run its queued blocks, append the open sub-integration as
-   its last profile, free its device memory and return it to the budget.
-   Completions seen meanwhile are reported by the next poll().  Returns
-   POND_OK or the error that ended the stream. */
+   its last profile, free its device memory and return it to the budget
+   (which may admit waiting streams).  A stream still waiting for admission
+   is dropped: its queued blocks complete with POND_ECANCELED.  Completions
+   seen meanwhile are reported by the next poll().  Returns POND_OK or the
+   error that ended the stream. */
 int32_t pond_server_close(pond_server* s, int32_t stream);
 
 /* Budget in use, budget, open streams and blocks queued or on the device. */

@@ -22,11 +22,45 @@ thread_local int32_t g_create_status = POND_OK;
 constexpr int64_t kMinLog2N = 10;
 constexpr int64_t kMaxLog2N = 24;
 constexpr int kMaxLog2N2 = 10;          // column length cap (K1/K3 tile = 16 columns in LDS)
+constexpr int64_t kDefaultAccSlots = 4; // sub-integrations the accumulator ring holds at creation
 
 int ilog2(int64_t v) {
     int r = 0;
     while ((int64_t(1) << r) < v) ++r;
     return r;
+}
+
+struct Geometry {
+    double delta_lo = 0, delta_hi = 0;
+    int64_t n_front = 0, discard = 0, hop = 0;
+};
+
+// Overlap-save geometry of a block of nfft samples (Sec. 3.7: the filter is
+// longer than the smear, the cyclic edges are dropped), float64: the delays
+// of the band edges relative to f0 (the constant of Eq. (1)), n_front =
+// ceil(delta_hi fs), s = n_front + ceil(delta_lo fs), discard =
+// next_pow2(max(s, 16)) if that is <= nfft / 2, else s rounded up to 16 (0
+// when s = 0), hop = nfft - discard.  False if hop would not be positive.
+bool plan_geometry(double f0_mhz, double bw_mhz, double dm, int64_t nfft, Geometry* g) {
+    const double fs = bw_mhz * 1e6;
+    const double k_dm = 1.0 / 2.41e-4;  // s MHz^2 per unit DM, the constant of Eq. (1)
+    const double f_lo = f0_mhz - bw_mhz / 2;
+    const double f_hi = f0_mhz + bw_mhz / 2;
+    g->delta_lo = k_dm * dm * (1.0 / (f_lo * f_lo) - 1.0 / (f0_mhz * f0_mhz));
+    g->delta_hi = k_dm * dm * (1.0 / (f0_mhz * f0_mhz) - 1.0 / (f_hi * f_hi));
+    const double front_d = std::ceil(g->delta_hi * fs);
+    const double back_d = std::ceil(g->delta_lo * fs);
+    if (!(front_d + back_d < (double)nfft)) return false;
+    g->n_front = (int64_t)front_d;
+    const int64_t s = g->n_front + (int64_t)back_d;
+    g->discard = 0;
+    if (s > 0) {
+        int64_t p2 = 16;
+        while (p2 < s) p2 <<= 1;
+        g->discard = p2 <= nfft / 2 ? p2 : ((s + 15) / 16) * 16;
+    }
+    g->hop = nfft - g->discard;
+    return g->hop > 0;
 }
 
 }  // namespace
@@ -156,24 +190,6 @@ void free_plan_memory(pond_plan* p) {
         if (q) (void)hipFree(q);
 }
 
-// exp(-2 pi i t / n) for t in [t0, t0 + count) with stride, float64 then float32
-std::vector<float2> twiddles(int64_t n, int64_t count, int64_t stride) {
-    std::vector<float2> w((size_t)count);
-    for (int64_t i = 0; i < count; ++i) {
-        const int64_t t = (i * stride) % n;
-        const double a = 2.0 * M_PI * (double)t / (double)n;
-        w[(size_t)i] = make_float2((float)std::cos(a), (float)-std::sin(a));
-    }
-    return w;
-}
-
-template <class T>
-hipError_t upload(T** dst, const std::vector<T>& v) {
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T));
-    if (e != hipSuccess) return e;
-    return hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
-}
-
 int default_max_batch(int64_t nfft, int32_t precision, int32_t max_batch) {
     if (max_batch > 0) return max_batch;
     const int64_t elem = precision == POND_FP32 ? 8 : 4;
@@ -280,16 +296,17 @@ hipError_t half_power_gain(const HalfCal& c, const std::function<hipError_t(int,
 }
 
 // Device bytes a plan allocates in pond_plan_create_ex (the accumulator
-// ring counted at its initial 4 sub-integrations; it grows only for calls
-// that span more).
-int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t max_batch) {
+// ring at acc_slots sub-integrations, at least the default 4; it grows only
+// for calls that span more).
+int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t max_batch, int64_t acc_slots) {
     const int log2n = ilog2(nfft);
     const int log2n2 = log2n / 2 < kMaxLog2N2 ? log2n / 2 : kMaxLog2N2;
     const int64_t n1 = (int64_t)1 << (log2n - log2n2), n2 = (int64_t)1 << log2n2;
     const int64_t elem = precision == POND_FP32 ? 8 : 4;
     const int64_t mb = default_max_batch(nfft, precision, max_batch);
     const int64_t table = precision == POND_HALF ? 8 : 16;
-    return mb * nfft * elem + 2 * nfft * 2 + (n1 + n2) * 8 + nfft * table + 2 * 4 * (int64_t)nbins * 8 +
+    const int64_t slots = acc_slots > kDefaultAccSlots ? acc_slots : kDefaultAccSlots;
+    return mb * nfft * elem + 2 * nfft * 2 + (n1 + n2) * 8 + nfft * table + 2 * slots * (int64_t)nbins * 8 +
            kPartEntries * 12 + 8;
 }
 
@@ -315,13 +332,27 @@ int32_t pond_copy_device(void* dst, const void* src, int64_t bytes, void* hip_st
     return POND_OK;
 }
 
+int32_t pond_geometry(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int64_t* n_front, int64_t* discard,
+                      int64_t* hop) {
+    if (!std::isfinite(f0_mhz) || !std::isfinite(bw_mhz) || !std::isfinite(dm)) return POND_EINVAL;
+    if (!(bw_mhz > 0) || !(f0_mhz - bw_mhz / 2 > 0) || !(dm >= 0)) return POND_EINVAL;
+    if (nfft <= 0 || (nfft & (nfft - 1)) != 0) return POND_EINVAL;
+    Geometry g;
+    if (!plan_geometry(f0_mhz, bw_mhz, dm, nfft, &g)) return POND_EINVAL;
+    if (n_front) *n_front = g.n_front;
+    if (discard) *discard = g.discard;
+    if (hop) *hop = g.hop;
+    return POND_OK;
+}
+
 const char* pond_strerror(int64_t code) {
     switch (code) {
         case POND_OK: return "ok";
         case POND_EINVAL: return "invalid argument or call sequence";
         case POND_ENOMEM: return "device allocation failed";
         case POND_EDEVICE: return "HIP runtime error (plan unusable)";
-        case POND_EBUSY: return "does not fit the device-memory budget now";
+        case POND_EBUSY: return "can never fit the device-memory budget, or too many streams";
+        case POND_ECANCELED: return "cancelled: its stream was closed before admission";
         default: return code > 0 ? "ok" : "unknown error";
     }
 }
@@ -344,7 +375,7 @@ hipError_t build_filter(pond_plan* p, double alpha) {
 }
 
 pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins, double period_s,
-                       int32_t precision, int32_t max_batch, int32_t kind) {
+                       int32_t precision, int32_t max_batch, int32_t kind, int64_t acc_slots = 0) {
     g_create_status = POND_EINVAL;
     if (kind != POND_INPUT_COMPLEX && precision != POND_FP32 && precision != POND_MIXED_VALU) return nullptr;
     if (!std::isfinite(f0_mhz) || !std::isfinite(bw_mhz) || !std::isfinite(dm) || !std::isfinite(period_s))
@@ -359,25 +390,10 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     const double fs = bw_mhz * 1e6;
     if (!(period_s > 0) || !(period_s * fs >= 1.0)) return nullptr;
 
-    // Geometry (Sec. 3.7: filter longer than the smear, cyclic edges dropped).
-    const double k_dm = 1.0 / 2.41e-4;  // s MHz^2 per unit DM, the constant of Eq. (1)
-    const double f_lo = f0_mhz - bw_mhz / 2;
-    const double f_hi = f0_mhz + bw_mhz / 2;
-    const double delta_lo = k_dm * dm * (1.0 / (f_lo * f_lo) - 1.0 / (f0_mhz * f0_mhz));
-    const double delta_hi = k_dm * dm * (1.0 / (f0_mhz * f0_mhz) - 1.0 / (f_hi * f_hi));
-    const double front_d = std::ceil(delta_hi * fs);
-    const double back_d = std::ceil(delta_lo * fs);
-    if (!(front_d + back_d < (double)nfft)) return nullptr;
-    const int64_t n_front = (int64_t)front_d;
-    const int64_t s = n_front + (int64_t)back_d;
-    int64_t discard = 0;
-    if (s > 0) {
-        int64_t p2 = 16;
-        while (p2 < s) p2 <<= 1;
-        discard = p2 <= nfft / 2 ? p2 : ((s + 15) / 16) * 16;
-    }
-    const int64_t hop = nfft - discard;
-    if (hop <= 0) return nullptr;
+    Geometry geo;
+    if (!plan_geometry(f0_mhz, bw_mhz, dm, nfft, &geo)) return nullptr;
+    const double delta_lo = geo.delta_lo, delta_hi = geo.delta_hi;
+    const int64_t n_front = geo.n_front, discard = geo.discard, hop = geo.hop;
 
     pond_plan* p = new (std::nothrow) pond_plan();
     if (!p) {
@@ -425,8 +441,10 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     chk(hipMalloc(reinterpret_cast<void**>(&p->tail[0]), (size_t)nfft * p->bpe));
     chk(hipMalloc(reinterpret_cast<void**>(&p->tail[1]), (size_t)nfft * p->bpe));
     const int64_t n1 = (int64_t)1 << p->log2n1, n2 = (int64_t)1 << p->log2n2;
-    if (e == hipSuccess) chk(upload(&p->tw1, twiddles(n1, n1, 1)));
-    if (e == hipSuccess) chk(upload(&p->tw2, twiddles(n2, n2, 1)));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->tw1), (size_t)n1 * sizeof(float2)));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->tw2), (size_t)n2 * sizeof(float2)));
+    if (e == hipSuccess) chk(launch_stage_twiddles(p->tw1, n1, nullptr));
+    if (e == hipSuccess) chk(launch_stage_twiddles(p->tw2, n2, nullptr));
     if (kind != POND_INPUT_COMPLEX) {
         p->real_fused = p->log2n1 <= kRealPairMaxLog2N1;
         chk(hipMalloc(reinterpret_cast<void**>(&p->rtab), (size_t)(nfft + 1) * sizeof(float4)));
@@ -469,7 +487,7 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
         p->half_gain = g;
         p->pscale = (float)(256.0 / g);
     }
-    p->acc_slots = 4;
+    p->acc_slots = acc_slots > kDefaultAccSlots ? acc_slots : kDefaultAccSlots;
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_sum), (size_t)p->acc_slots * nbins * 8));
     chk(hipMalloc(reinterpret_cast<void**>(&p->acc_cnt), (size_t)p->acc_slots * nbins * 8));
     chk(hipMalloc(reinterpret_cast<void**>(&p->part_sum), (size_t)kPartEntries * 8));
@@ -492,6 +510,14 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
 }
 
 }  // namespace
+
+namespace pond {
+pond_plan* plan_create_slots(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins, double period_s,
+                             int32_t precision, int32_t max_batch, int64_t acc_slots) {
+    return create_plan(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision, max_batch, POND_INPUT_COMPLEX,
+                       acc_slots);
+}
+}  // namespace pond
 
 extern "C" {
 
@@ -666,7 +692,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
     }
     if (subint < 0 || max_profiles < 0) return POND_EINVAL;
     if (p->subint >= 0 && subint != p->subint) return POND_EINVAL;
-    if (decim <= 0) decim = 16;
+    if (decim <= 0) decim = (int32_t)std::lround(p->bw);  // 1 us (bw_mhz samples)
     if (decim != 1 && decim != 2 && decim != 4 && decim != 8 && decim != 16) return POND_EINVAL;
     if (want_series && series_cap < 0) return POND_EINVAL;
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
@@ -733,25 +759,40 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
     const int64_t groups = (m_after - m_before) / decim;
     if (want_series && (groups > series_cap || (groups > 0 && !series))) return POND_EINVAL;
 
-    // Grow the accumulator ring if this call touches more sub-integrations.
+    // Grow the accumulator ring if this call touches more sub-integrations
+    // than it holds: never while the stream is being captured into a graph
+    // (the graph would own the new memory), otherwise with plain
+    // allocations once the plan's work has finished.  Slot 0 (the open
+    // sub-integration) carries over; the rest start at zero.
     if (n_touched > p->acc_slots) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return fail(hipErrorUnknown);
+        if (cs != hipStreamCaptureStatusNone) return POND_EINVAL;
         int64_t slots = p->acc_slots;
         while (slots < n_touched) slots *= 2;
+        const size_t bytes = (size_t)slots * nbins * 8;
+        e = hipStreamSynchronize(stream);
+        if (e == hipSuccess && p->last_stream != stream) e = hipStreamSynchronize(p->last_stream);
+        if (e != hipSuccess) return fail(e);
         uint64_t *ns = nullptr, *nc = nullptr;
-        e = hipMallocAsync(reinterpret_cast<void**>(&ns), (size_t)slots * nbins * 8, stream);
-        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&nc), (size_t)slots * nbins * 8, stream);
+        e = hipMalloc(reinterpret_cast<void**>(&ns), bytes);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&nc), bytes);
         if (e != hipSuccess) {
-            if (ns) (void)hipFreeAsync(ns, stream);
+            if (ns) (void)hipFree(ns);
             (void)hipGetLastError();
             return POND_ENOMEM;
         }
-        e = launch_zero_u64(ns, slots * nbins, stream);
-        if (e == hipSuccess) e = launch_zero_u64(nc, slots * nbins, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(ns, p->acc_sum, (size_t)nbins * 8, hipMemcpyDeviceToDevice, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(nc, p->acc_cnt, (size_t)nbins * 8, hipMemcpyDeviceToDevice, stream);
-        if (e == hipSuccess) e = hipFreeAsync(p->acc_sum, stream);
-        if (e == hipSuccess) e = hipFreeAsync(p->acc_cnt, stream);
-        if (e != hipSuccess) return fail(e);
+        e = hipMemset(ns, 0, bytes);
+        if (e == hipSuccess) e = hipMemset(nc, 0, bytes);
+        if (e == hipSuccess) e = hipMemcpy(ns, p->acc_sum, (size_t)nbins * 8, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(nc, p->acc_cnt, (size_t)nbins * 8, hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(ns);
+            (void)hipFree(nc);
+            return fail(e);
+        }
+        (void)hipFree(p->acc_sum);
+        (void)hipFree(p->acc_cnt);
         p->acc_sum = ns;
         p->acc_cnt = nc;
         p->acc_slots = slots;
@@ -937,7 +978,7 @@ int64_t pond_real_dedisperse(pond_plan* p, const int8_t* raw, int64_t nsamp, int
     if (n_series_out) *n_series_out = 0;
     if (!p || p->kind == POND_INPUT_COMPLEX) return POND_EINVAL;
     if ((nsamp & 1) || (subint_nsamp & 1)) return POND_EINVAL;
-    if (decim <= 0) decim = 32;
+    if (decim <= 0) decim = (int32_t)std::lround(2.0 * p->bw);  // 1 us of real samples
     if (decim != 2 && decim != 4 && decim != 8 && decim != 16 && decim != 32) return POND_EINVAL;
     return run_call(p, raw, nsamp / 2, subint_nsamp / 2, profiles, max_profiles, decim / 2, series, series_cap,
                     n_series_out, series != nullptr, hip_stream);

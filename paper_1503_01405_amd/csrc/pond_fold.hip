@@ -107,6 +107,16 @@ __global__ void __launch_bounds__(256) copy_u128(u32x4* __restrict__ dst, const 
     }
 }
 
+// Stage twiddles of a length-n transform: w[t] = exp(-2 pi i t / n),
+// float64 sine and cosine rounded to float32.
+__global__ void __launch_bounds__(256) stage_twiddles(float2* w, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double sn, cs;
+    sincospi(2.0 * (double)t / (double)n, &sn, &cs);
+    w[t] = make_float2((float)cs, (float)-sn);
+}
+
 __global__ void __launch_bounds__(256) zero_u64(uint64_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -132,6 +142,12 @@ hipError_t launch_copy_u128(void* dst, const void* src, int64_t n16, hipStream_t
     const unsigned grid = (unsigned)(chunks < 16384 ? chunks : 16384);
     hipLaunchKernelGGL(copy_u128, dim3(grid), dim3(256), 0, s, reinterpret_cast<u32x4*>(dst),
                        reinterpret_cast<const u32x4*>(src), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_twiddles(float2* w, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stage_twiddles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n);
     return hipGetLastError();
 }
 

@@ -8,6 +8,8 @@
 
 #include <functional>
 
+struct pond_plan;
+
 namespace pond {
 
 // Fixed-point scale of the fold accumulators: a power p is accumulated as
@@ -145,6 +147,8 @@ hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins,
                                 float* profiles, hipStream_t s);
 hipError_t launch_copy_u128(void* dst, const void* src, int64_t n16, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s);
+// w[t] = exp(-2 pi i t / n) for t < n, float64 sine/cosine rounded to float32.
+hipError_t launch_stage_twiddles(float2* w, int64_t n, hipStream_t s);
 hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
                                  double taper, hipStream_t s);
 hipError_t launch_k2_build_split_tables(float2* tw, float2* chirp, int log2n1, int log2n2, double chirp_a, double f0,
@@ -163,18 +167,24 @@ constexpr int half_row_rem(int log2n1) {
 hipError_t launch_fold_profiles(const uint64_t* acc_sum, const uint64_t* acc_cnt, int64_t n, float* profiles,
                                 hipStream_t s);
 
+constexpr int64_t kPartEntries = 1 << 21;  // per-workgroup fold partials: grid * entries <= this
 // Workgroups of a K3 launch: enough to fill the chip at the occupancy the
 // LDS allows, at most one per item, a multiple of 8, and within the
 // partial-histogram budget.
-int k3_grid(int log2n2, int prec, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode);
-constexpr int64_t kPartEntries = 1 << 21;  // per-workgroup fold partials: grid * entries <= this
+int k3_grid(int log2n2, int prec, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode,
+            int64_t part_entries = kPartEntries);
 constexpr int64_t kHistCapMax = 8192;      // fold histogram entries held in LDS
 constexpr size_t kLdsBytes = 160 * 1024;   // gfx950 LDS per workgroup
 int64_t hist_capacity(int log2n2, int prec);
 
-// Device bytes pond_plan_create_ex allocates for these arguments, and the
+// Device bytes pond_plan_create_ex allocates for these arguments (with an
+// accumulator ring of acc_slots sub-integrations, at least 4), and the
 // blocks per launch it picks (max_batch <= 0: the default).
-int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t max_batch);
+int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t max_batch, int64_t acc_slots);
+// pond_plan_create_ex with an accumulator ring of at least acc_slots
+// sub-integrations from the start (callers that know their largest call).
+pond_plan* plan_create_slots(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins, double period_s,
+                             int32_t precision, int32_t max_batch, int64_t acc_slots);
 int plan_max_batch(int64_t nfft, int32_t precision, int32_t max_batch);
 // Power gain of a packed-float16 path, measured.  White int8 noise of at
 // least 2^22 samples, cut into blocks of n = 2^(log2n1 + log2n2), is pushed

@@ -374,12 +374,13 @@ int64_t hist_capacity(int log2n2, int prec) {
     return cap < kHistCapMax ? cap : kHistCapMax;
 }
 
-int k3_grid(int log2n2, int prec, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode) {
+int k3_grid(int log2n2, int prec, size_t dyn_lds, int64_t items, int64_t entries, bool global_mode,
+            int64_t part_entries) {
     const size_t lds = k3_static_lds(log2n2, prec) + dyn_lds;
     int per_cu = (int)(kLdsBytes / lds);
     per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
     int64_t grid = 256 * per_cu;
-    if (!global_mode && grid * entries > kPartEntries) grid = kPartEntries / entries;
+    if (!global_mode && grid * entries > part_entries) grid = part_entries / entries;
     const int64_t items8 = (items + 7) & ~int64_t(7);
     if (grid > items8) grid = items8;
     grid &= ~int64_t(7);

@@ -40,15 +40,6 @@ struct Group {
     void* out = nullptr;      // max_batch blocks of one trial's row-inverse output
 };
 
-std::vector<float2> stage_twiddles(int64_t n) {
-    std::vector<float2> w((size_t)n);
-    for (int64_t t = 0; t < n; ++t) {
-        const double a = 2.0 * M_PI * (double)t / (double)n;
-        w[(size_t)t] = make_float2((float)std::cos(a), (float)-std::sin(a));
-    }
-    return w;
-}
-
 int ilog2(int64_t v) {
     int r = 0;
     while ((int64_t(1) << r) < v) ++r;
@@ -183,11 +174,10 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
     };
     for (auto& g : s->groups) {
         const int64_t n1 = (int64_t)1 << g.log2n1, n2 = (int64_t)1 << g.log2n2;
-        const std::vector<float2> t1 = stage_twiddles(n1), t2 = stage_twiddles(n2);
         chk(hipMalloc(reinterpret_cast<void**>(&g.tw1), n1 * sizeof(float2)));
         chk(hipMalloc(reinterpret_cast<void**>(&g.tw2), n2 * sizeof(float2)));
-        if (e == hipSuccess) chk(hipMemcpy(g.tw1, t1.data(), n1 * sizeof(float2), hipMemcpyHostToDevice));
-        if (e == hipSuccess) chk(hipMemcpy(g.tw2, t2.data(), n2 * sizeof(float2), hipMemcpyHostToDevice));
+        if (e == hipSuccess) chk(launch_stage_twiddles(g.tw1, n1, nullptr));
+        if (e == hipSuccess) chk(launch_stage_twiddles(g.tw2, n2, nullptr));
         chk(hipMalloc(&g.spec, (size_t)g.max_batch * g.nfft * s->elem));
         chk(hipMalloc(&g.out, (size_t)g.max_batch * g.nfft * s->elem));
         const bool half = precision == POND_HALF;

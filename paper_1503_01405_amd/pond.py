@@ -18,6 +18,12 @@ POND_EINVAL = -1
 POND_ENOMEM = -2
 POND_EDEVICE = -3
 POND_EBUSY = -4
+POND_ECANCELED = -5
+
+POND_TICKET_ADMITTED = -1
+POND_STREAM_WAITING = 0
+POND_STREAM_OPEN = 1
+POND_STREAM_CLOSED = 2
 
 POND_FP32 = 0
 POND_MIXED = 1
@@ -43,10 +49,10 @@ EXPORTS = (
     "pond_search_create", "pond_search_run", "pond_search_trial", "pond_search_destroy",
     "pond_server_create", "pond_server_stream_bytes", "pond_server_open", "pond_server_submit",
     "pond_server_poll", "pond_server_take_profiles", "pond_server_close", "pond_server_query",
-    "pond_server_destroy",
+    "pond_server_destroy", "pond_server_stream_state",
     "pond_aid_create", "pond_aid_geometry", "pond_aid_run", "pond_aid_destroy",
     "pond_real_plan_create", "pond_real_dedisperse", "pond_real_expect",
-    "pond_copy_device",
+    "pond_copy_device", "pond_geometry",
 )
 KERNEL_NAMES = ("k1_unpack_colfft", "k2_row", "k3_colinv_detect_fold", "fold_reduce", "fold_finalize")
 
@@ -149,6 +155,11 @@ def _load():
     lib.pond_server_take_profiles.restype = i64
     lib.pond_server_close.argtypes = [P, i32]
     lib.pond_server_close.restype = i32
+    lib.pond_geometry.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, i64,
+                                  ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.pond_geometry.restype = i32
+    lib.pond_server_stream_state.argtypes = [P, i32]
+    lib.pond_server_stream_state.restype = i32
     lib.pond_server_query.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
                                       ctypes.POINTER(i64)]
     lib.pond_server_query.restype = i32
@@ -383,6 +394,19 @@ def pond_server_take_profiles(server, stream, nbins, max_profiles=1 << 20):
 
 def pond_server_close(server, stream):
     return _lib.pond_server_close(server, int(stream))
+
+
+def pond_geometry(f0_mhz, bw_mhz, dm, nfft):
+    """(n_front, discard, hop) of a plan with these arguments, or None if
+    no plan can be made (hop would not be positive, or bad arguments)."""
+    nf, d, h = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    r = _lib.pond_geometry(float(f0_mhz), float(bw_mhz), float(dm), int(nfft), ctypes.byref(nf), ctypes.byref(d),
+                           ctypes.byref(h))
+    return (nf.value, d.value, h.value) if r == POND_OK else None
+
+
+def pond_server_stream_state(server, stream):
+    return _lib.pond_server_stream_state(server, int(stream))
 
 
 def pond_server_query(server):

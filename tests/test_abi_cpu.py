@@ -102,3 +102,27 @@ def test_library_shares_torchs_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.splitlines()[0] == "1", out.stdout
+
+
+@pytest.mark.parametrize("dm,nfft", [(0.0, 1 << 10), (0.003, 1 << 10), (1.0, 1 << 18), (50.0, 1 << 23),
+                                     (130.0, 1 << 24), (200.0, 1 << 24), (200.0, 1 << 23), (37.2, 1 << 20)])
+def test_library_geometry_equals_the_oracle_rule(dm, nfft):
+    """pond_geometry (host arithmetic of the plan) against the oracle's
+    geometry of the same block: identical n_front, discard and hop, and
+    both refuse a block shorter than the smear."""
+    import oracle as O
+    import paper_1503_01405_amd.pond as B
+    got = B.pond_geometry(326.5, 16.0, dm, nfft)
+    try:
+        g = O.plan_geometry(326.5, 16.0, dm, nfft)
+        want = (g["n_front"], g["discard"], g["hop"])
+    except ValueError:
+        want = None
+    assert got == want
+
+
+def test_library_geometry_rejects_bad_arguments():
+    import paper_1503_01405_amd.pond as B
+    assert B.pond_geometry(326.5, 16.0, 1.0, 3000) is None
+    assert B.pond_geometry(326.5, -1.0, 1.0, 1 << 18) is None
+    assert B.pond_geometry(326.5, 16.0, -0.5, 1 << 18) is None

@@ -163,14 +163,15 @@ def test_admission_by_budget():
     srv = P.pond_server_create(need + need // 2, 8)
     try:
         a = P.pond_server_open(srv, d)
-        assert a >= 0
+        assert a >= 0 and P.pond_server_stream_state(srv, a) == P.POND_STREAM_OPEN
         q = P.pond_server_query(srv)
         assert 0 < q["used_bytes"] <= need
-        # a second such stream only fits with fewer blocks per launch, if at all
+        # a second such stream is admitted with fewer blocks per launch, or waits
         b = P.pond_server_open(srv, d)
-        if b >= 0:
+        assert b >= 0
+        if P.pond_server_stream_state(srv, b) == P.POND_STREAM_OPEN:
             assert P.pond_server_query(srv)["used_bytes"] <= need + need // 2
-            assert P.pond_server_close(srv, b) == P.POND_OK
+        assert P.pond_server_close(srv, b) == P.POND_OK
         c = P.pond_server_open(srv, _desc(P, STREAMS[4], max_block=need))  # staging alone exceeds it
         assert c == P.POND_EBUSY
         assert P.pond_server_close(srv, a) == P.POND_OK
@@ -180,3 +181,73 @@ def test_admission_by_budget():
         assert P.pond_server_close(srv, a2) == P.POND_OK
     finally:
         P.pond_server_destroy(srv)
+
+
+@pytest.mark.gpu
+def test_deferred_admission_runs_after_budget_frees():
+    """Continuous batching under a budget: stream B does not fit while A is
+    open, so it waits with the blocks submitted to it; closing A returns A's
+    memory, B is admitted (reported by poll as an admission), its queued
+    blocks run, and both streams' profiles equal the same blocks run alone.
+    A third stream closed before its admission has its blocks cancelled."""
+    import paper_1503_01405_amd as P
+    import torch
+    print("case: serve deferred admission", flush=True)
+    torch.cuda.init()
+    sa, sb = STREAMS[4], STREAMS[2]
+    da, db = _desc(P, sa), _desc(P, sb)
+    need_a, need_b = P.pond_server_stream_bytes(da), P.pond_server_stream_bytes(db)
+    srv = P.pond_server_create(need_a + need_b // 4, 8)
+    try:
+        a = P.pond_server_open(srv, da)
+        b = P.pond_server_open(srv, db)
+        c = P.pond_server_open(srv, db)
+        assert P.pond_server_stream_state(srv, a) == P.POND_STREAM_OPEN
+        assert P.pond_server_stream_state(srv, b) == P.POND_STREAM_WAITING
+        assert P.pond_server_stream_state(srv, c) == P.POND_STREAM_WAITING
+        data = {a: synth.white_stream_int8(60, NSAMP), b: synth.white_stream_int8(61, NSAMP)}
+        sizes = {a: _blocks(160, NSAMP), b: _blocks(161, NSAMP)}
+        pinned = {k: _pinned(v) for k, v in data.items()}
+        tickets = {a: [], b: []}
+        for k in (a, b):
+            pos = 0
+            for n in sizes[k]:
+                t = P.pond_server_submit(srv, k, pinned[k][2 * pos:], n)
+                assert t >= 0, t
+                tickets[k].append(t)
+                pos += n
+        cz = P.pond_server_submit(srv, c, pinned[b], 1000)
+        assert cz >= 0
+        done = []
+        while True:
+            got = P.pond_server_poll(srv, wait=True)
+            if not got:
+                break
+            done += got
+        # all of A's blocks ran; none of B's, which still waits
+        assert sorted(x["ticket"] for x in done if x["stream"] == a) == tickets[a]
+        assert not [x for x in done if x["stream"] == b]
+        assert P.pond_server_stream_state(srv, b) == P.POND_STREAM_WAITING
+        assert P.pond_server_close(srv, a) == P.POND_OK      # frees A's memory: B is admitted
+        assert P.pond_server_stream_state(srv, b) == P.POND_STREAM_OPEN
+        assert P.pond_server_stream_state(srv, c) == P.POND_STREAM_WAITING
+        assert P.pond_server_close(srv, c) == P.POND_OK      # never admitted: cancelled
+        while True:
+            got = P.pond_server_poll(srv, wait=True)
+            if not got:
+                break
+            done += got
+        adm = [x for x in done if x["ticket"] == P.POND_TICKET_ADMITTED]
+        assert [(x["stream"], x["status"]) for x in adm] == [(b, P.POND_OK)]
+        assert sorted(x["ticket"] for x in done if x["stream"] == b and x["ticket"] >= 0) == tickets[b]
+        assert all(x["status"] == P.POND_OK for x in done if x["stream"] in (a, b))
+        assert [(x["ticket"], x["status"]) for x in done if x["stream"] == c] == [(cz, P.POND_ECANCELED)]
+        assert P.pond_server_close(srv, b) == P.POND_OK
+        profs = {k: P.pond_server_take_profiles(srv, k, s[2]) for k, s in ((a, sa), (b, sb))}
+        assert P.pond_server_query(srv)["used_bytes"] == 0
+    finally:
+        P.pond_server_destroy(srv)
+    for k, s in ((a, sa), (b, sb)):
+        want = _alone(P, s, data[k], sizes[k])
+        assert profs[k].shape == want.shape
+        np.testing.assert_array_equal(profs[k], want, err_msg=f"stream {k}")
