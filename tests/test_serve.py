@@ -228,10 +228,11 @@ def test_deferred_admission_runs_after_budget_frees():
         assert sorted(x["ticket"] for x in done if x["stream"] == a) == tickets[a]
         assert not [x for x in done if x["stream"] == b]
         assert P.pond_server_stream_state(srv, b) == P.POND_STREAM_WAITING
+        assert P.pond_server_close(srv, c) == P.POND_OK      # never admitted: cancelled
+        assert P.pond_server_stream_state(srv, c) == P.POND_STREAM_CLOSED
+        assert P.pond_server_stream_state(srv, b) == P.POND_STREAM_WAITING
         assert P.pond_server_close(srv, a) == P.POND_OK      # frees A's memory: B is admitted
         assert P.pond_server_stream_state(srv, b) == P.POND_STREAM_OPEN
-        assert P.pond_server_stream_state(srv, c) == P.POND_STREAM_WAITING
-        assert P.pond_server_close(srv, c) == P.POND_OK      # never admitted: cancelled
         while True:
             got = P.pond_server_poll(srv, wait=True)
             if not got:
