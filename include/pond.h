@@ -112,6 +112,39 @@ typedef struct pond_info {
 int32_t pond_geometry(double f0_mhz, double bw_mhz, double dm, int64_t nfft,
                       int64_t* n_front, int64_t* discard, int64_t* hop);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the whole
+ * path of pond_plan_create_ex + pond_dedisperse_series + the end-of-stream
+ * call, with subint_nsamp = 0, over ONE resident segment, allocating
+ * nothing.  Every buffer the kernels need beyond the arguments (stage
+ * twiddles, the middle-pass table, block work area, fold partials,
+ * accumulators, status) lives in a static device array of
+ * POND_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends.  All calls on one GPU share that array: calls that
+ * overlap on one GPU race (serialise them, e.g. on one stream).
+ *   iq        device, 2*nsamp int8 (I, Q), the whole segment
+ *   precision POND_FP32, POND_MIXED or POND_MIXED_VALU (POND_HALF needs a
+ *             per-plan gain measurement, which allocates)
+ *   nfft      power of two in [2^10, 2^POND_NOALLOC_MAX_LOG2N]
+ *   nbins     [1, POND_NOALLOC_MAX_BINS]
+ *   decim     as pond_dedisperse_series
+ *   profile   device, nbins float32: mean power per bin of every output
+ *   series    device, series_cap floats (NULL only if no group completes)
+ * Outputs cover every fully covered overlap-save block (Sec. 3.7), as the
+ * plan would.  Returns the number of series values written (outputs /
+ * decim), or POND_EINVAL (arguments, sizes beyond the limits) /
+ * POND_EDEVICE.  Asynchronous on hip_stream; no host synchronisation.
+ */
+#define POND_NOALLOC_SCRATCH_BYTES (64ll << 20)
+#define POND_NOALLOC_MAX_LOG2N 20
+#define POND_NOALLOC_MAX_BINS 8192
+int64_t pond_dedisperse_segment_noalloc(double f0_mhz, double bw_mhz, double dm, int64_t nfft,
+                                        int32_t nbins, double period_s, int32_t precision,
+                                        const int8_t* iq, int64_t nsamp, int32_t decim,
+                                        float* profile, float* series, int64_t series_cap,
+                                        void* hip_stream);
+
 /* Input kinds of a plan (pond_info.input_kind).  For a real-input plan the
    counts of pond_info are in real samples (nfft, n_front, discard, hop,
    samples_in, outputs_done), fs_hz is the real sample rate 2 bw, and

@@ -52,7 +52,7 @@ EXPORTS = (
     "pond_server_destroy", "pond_server_stream_state",
     "pond_aid_create", "pond_aid_geometry", "pond_aid_run", "pond_aid_destroy",
     "pond_real_plan_create", "pond_real_dedisperse", "pond_real_expect",
-    "pond_copy_device", "pond_geometry",
+    "pond_copy_device", "pond_geometry", "pond_dedisperse_segment_noalloc",
 )
 KERNEL_NAMES = ("k1_unpack_colfft", "k2_row", "k3_colinv_detect_fold", "fold_reduce", "fold_finalize")
 
@@ -155,6 +155,8 @@ def _load():
     lib.pond_server_take_profiles.restype = i64
     lib.pond_server_close.argtypes = [P, i32]
     lib.pond_server_close.restype = i32
+    lib.pond_dedisperse_segment_noalloc.argtypes = [dbl, dbl, dbl, i64, i32, dbl, i32, P, i64, i32, P, P, i64, P]
+    lib.pond_dedisperse_segment_noalloc.restype = i64
     lib.pond_geometry.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, i64,
                                   ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.pond_geometry.restype = i32
@@ -394,6 +396,17 @@ def pond_server_take_profiles(server, stream, nbins, max_profiles=1 << 20):
 
 def pond_server_close(server, stream):
     return _lib.pond_server_close(server, int(stream))
+
+
+def pond_dedisperse_segment_noalloc(f0_mhz, bw_mhz, dm, nfft, nbins, period_s, precision, iq, nsamp, decim,
+                                    profile, series, series_cap, stream=None):
+    """One resident segment through the whole path with no device
+    allocation (the library's static scratch); returns the series count or
+    a negative error code."""
+    return _lib.pond_dedisperse_segment_noalloc(float(f0_mhz), float(bw_mhz), float(dm), int(nfft), int(nbins),
+                                                float(period_s), int(precision), _ptr(iq), int(nsamp),
+                                                int(decim), _ptr(profile), _ptr(series), int(series_cap),
+                                                _stream(stream))
 
 
 def pond_geometry(f0_mhz, bw_mhz, dm, nfft):
