@@ -65,10 +65,13 @@ typedef struct pond_plan pond_plan;
 
 /* Precision forms. */
 #define POND_FP32   0  /* float32 storage and arithmetic                                   */
-#define POND_MIXED  1  /* float16 storage between passes; the radix-16 stages of the column
-                          passes run as 16-point DFT matrix products on the matrix cores
-                          (float16 operands, float32 accumulation, power-of-two stage
-                          scaling); chirp and fold phases stay float64                      */
+#define POND_MIXED  1  /* float16 storage and twiddles as POND_HALF, with every radix-16
+                          butterfly of the transforms of 64 points and more (columns) and
+                          1024 points and more (rows) computed as a 16-point DFT matrix
+                          product on the matrix cores (float16 operands, float32
+                          accumulation, rounded once to float16); the same power-of-two
+                          stage scaling and measured power gain as POND_HALF; chirp and
+                          fold phases float64                                              */
 #define POND_MIXED_VALU 2  /* float16 storage between passes, every butterfly in float32
                               vector arithmetic                                            */
 #define POND_HALF   3  /* float16 storage and packed float16 vector arithmetic (two halves per
@@ -124,8 +127,8 @@ int32_t pond_geometry(double f0_mhz, double bw_mhz, double dm, int64_t nfft,
  * the process ends.  All calls on one GPU share that array: calls that
  * overlap on one GPU race (serialise them, e.g. on one stream).
  *   iq        device, 2*nsamp int8 (I, Q), the whole segment
- *   precision POND_FP32, POND_MIXED or POND_MIXED_VALU (POND_HALF needs a
- *             per-plan gain measurement, which allocates)
+ *   precision POND_FP32 or POND_MIXED_VALU (the float16-arithmetic forms
+ *             need a per-plan gain measurement, which allocates)
  *   nfft      power of two in [2^10, 2^POND_NOALLOC_MAX_LOG2N]
  *   nbins     [1, POND_NOALLOC_MAX_BINS]
  *   decim     as pond_dedisperse_series

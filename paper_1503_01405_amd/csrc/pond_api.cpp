@@ -253,7 +253,7 @@ hipError_t half_power_gain(const HalfCal& c, const std::function<hipError_t(int,
         a1.log2n1 = c.log2n1;
         a1.work = c.work;
         a1.tw2 = c.tw2;
-        e = launch_k1(kHalf, c.log2n2, a1, nullptr);
+        e = launch_k1(c.prec, c.log2n2, a1, nullptr);
         const void* mid = nullptr;
         if (e == hipSuccess) e = middle(nb, &mid);
         if (e != hipSuccess) break;
@@ -278,9 +278,9 @@ hipError_t half_power_gain(const HalfCal& c, const std::function<hipError_t(int,
         a3.part_cnt = reinterpret_cast<uint32_t*>(d_part + kParts);
         a3.status = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_part) + kParts * 12);
         const int64_t items = (int64_t)nb << (c.log2n1 - 4);
-        int grid = k3_grid(c.log2n2, kHalf, 12, items, 1, false);
+        int grid = k3_grid(c.log2n2, c.prec, 12, items, 1, false);
         if (grid > kParts) grid = (int)kParts;
-        e = launch_k3(kHalf, c.log2n2, a3, grid, 12, nullptr);
+        e = launch_k3(c.prec, c.log2n2, a3, grid, 12, nullptr);
     }
     std::vector<float> ser((size_t)nser);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -304,7 +304,7 @@ int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t m
     const int64_t n1 = (int64_t)1 << (log2n - log2n2), n2 = (int64_t)1 << log2n2;
     const int64_t elem = precision == POND_FP32 ? 8 : 4;
     const int64_t mb = default_max_batch(nfft, precision, max_batch);
-    const int64_t table = precision == POND_HALF ? 8 : 16;
+    const int64_t table = f16_arith(precision) ? 8 : 16;
     const int64_t slots = acc_slots > kDefaultAccSlots ? acc_slots : kDefaultAccSlots;
     return mb * nfft * elem + 2 * nfft * 2 + (n1 + n2) * 8 + nfft * table + 2 * slots * (int64_t)nbins * 8 +
            kPartEntries * 12 + 8;
@@ -369,7 +369,7 @@ hipError_t build_filter(pond_plan* p, double alpha) {
                                             alpha, nullptr);
     if (p->kind != POND_INPUT_COMPLEX)
         return launch_real_build_table(p->rtab, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->bw, lsb, alpha, nullptr);
-    if (p->precision == POND_HALF)
+    if (f16_arith(p->precision))
         return launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
     return launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
 }
@@ -455,16 +455,18 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
             if (e == hipSuccess)
                 chk(launch_k2_build_split_tables(p->tw4, nullptr, p->log2n1, p->log2n2, 0.0, p->f0, p->df, nullptr));
         }
-    } else if (precision == POND_HALF) {
+    } else if (f16_arith(precision)) {
         chk(hipMalloc(&p->htable, (size_t)nfft * 8));
     } else {
         chk(hipMalloc(reinterpret_cast<void**>(&p->table), (size_t)nfft * sizeof(float4)));
     }
     if (e == hipSuccess) chk(build_filter(p, 0.0));
-    // Packed float16: the power scale is 256 over the measured gain of the
-    // plan's float16 arithmetic (the unit-taper table just built).
-    if (e == hipSuccess && precision == POND_HALF && kind == POND_INPUT_COMPLEX) {
+    // Float16 arithmetic (packed float16 and matrix-core forms): the power
+    // scale is 256 over the measured gain of the plan's float16 arithmetic
+    // (the unit-taper table just built).
+    if (e == hipSuccess && f16_arith(precision) && kind == POND_INPUT_COMPLEX) {
         HalfCal cal;
+        cal.prec = precision;
         cal.log2n1 = p->log2n1;
         cal.log2n2 = p->log2n2;
         cal.tw2 = p->tw2;
@@ -481,7 +483,7 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
                 a2.tw1 = p->tw1;
                 a2.htable = p->htable;
                 *res = p->work;
-                return launch_k2(POND_HALF, kRowFull, p->log2n1, a2, nullptr);
+                return launch_k2(precision, kRowFull, p->log2n1, a2, nullptr);
             },
             &g));
         p->half_gain = g;

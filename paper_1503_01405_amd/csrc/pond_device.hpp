@@ -59,7 +59,7 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
 constexpr int kFormF32 = 0, kFormMfma = 1, kFormF16 = 2;
 
 template <int FORM>
-using LdsVal = std::conditional_t<FORM == kFormF16, h2, float2>;
+using LdsVal = std::conditional_t<FORM == kFormF16 || FORM == kFormMfma, h2, float2>;
 
 // Float16 pair for the complex value (c, s) of magnitude m (float64 in):
 // among the neighbouring float16 values of each component, the pair whose
@@ -122,7 +122,7 @@ __device__ __forceinline__ double taper_w(double f, double bw, double alpha) {
 // ------------------------------------------------------------------- K3
 // Static LDS.  Float32 arithmetic: one float2 tile of 16 columns, reused for
 // the detected powers.  Packed float16: the padded float16 tile, a power
-// buffer of its own (16 floats per row) and the stage-1 twiddle table, so
+// buffer of its own (16 floats per row) and the twiddle tables, so
 // that an item's powers are written without a barrier after the transform
 // and the next item's transform starts without one before its first
 // exchange.
@@ -134,8 +134,8 @@ struct K3Shape {
     static constexpr size_t LDS = sizeof(float2) * 16 * L;
     static constexpr size_t kHalfTile = ColLds<h2, true>::kSlots(L) * sizeof(h2);
     static constexpr size_t kHalfPf = 16 * L * sizeof(float);
-    static constexpr size_t LDS_HALF = kHalfTile + kHalfPf + kS1Pairs * sizeof(h2);
-    static constexpr size_t lds(int form) { return form == kFormF16 ? LDS_HALF : LDS; }
+    static constexpr size_t LDS_HALF = kHalfTile + kHalfPf + ((TwTab<LOG2N2>::kSize + 3) & ~3) * sizeof(h2);
+    static constexpr size_t lds(int form) { return form == kFormF16 || form == kFormMfma ? LDS_HALF : LDS; }
 };
 
 // Fold phase of output m (float64, as specified): x = (m + n_front) * inv_pfs,

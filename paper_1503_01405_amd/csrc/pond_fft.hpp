@@ -531,27 +531,165 @@ __device__ __forceinline__ void stockham_stage(V (&v)[16], int j, V base, const 
     });
 }
 
-// The float16 twiddles of stage 1 of a transform of length >= 2^8 (radix
-// 16, NS = 16) come in 16 sets only (k = j mod 16).  A workgroup forms them
-// once (threads 0..15, with stage_tw_h) into an LDS table of 16 rows of 16
-// pairs at a stride of 20 pairs: the 16-byte reads of the 16 rows then fall
-// in distinct banks.  Every transform of the workgroup reads its row.
-constexpr int kS1Stride = 20;
-constexpr int kS1Pairs = 16 * kS1Stride;
+// LDS twiddle tables of a packed-float16 transform.  Stage s (radix R,
+// NS > 1) multiplies input q of the butterfly with index k by
+//   w_q(k) = exp(-2 pi i q k / (R NS)),
+// and k = hi F + lo factors it as A_q(hi) B_q(lo), with
+//   A_q(hi) = exp(-2 pi i q hi F / (R NS)),  B_q(lo) = exp(-2 pi i q lo / (R NS)),
+// each a float16 rounding of a float32 value of the stage-twiddle array.
+// The stage then costs one float16 complex product per twiddle (A B) in
+// place of a float32 power chain and its conversions.  Layouts:
+//   R = 16 (NS = 16 or 256, F = 16): rows of 16 pairs (q = 0..15) at a
+//     stride of 20 pairs, so that 16-byte reads of 16 different rows fall
+//     in distinct banks; B has 16 rows, A has NS / 16 rows (none if 1);
+//   R < 16 (the last stage, NS = L / R, k = j + TPV u): F = min(64, TPV),
+//     q-major, B[q-1][lo] over F entries and A[q-1][hi] over NS / F,
+//     lo = j mod F (the same for every u of the thread).
+// A workgroup fills the tables once (fill_twiddle_tables) from the float32
+// array tw[t] = exp(-2 pi i t / L), and every transform it runs reads them.
+constexpr int kTabStride = 20;
 template <int LOG2L>
-constexpr bool kS1Tabled = LOG2L >= 8;
-template <int LOG2L>
-__device__ __forceinline__ void fill_stage1_table(h2* tab, const float2* __restrict__ tw, int tid) {
-    if constexpr (kS1Tabled<LOG2L>) {
-        if (tid < 16) {
-            h2 t[16];
-            stage_tw_h<LOG2L, 1>(tw[tid * ((1 << LOG2L) / 256)], t);
-#pragma unroll
-            for (int q = 0; q < 16; ++q) tab[tid * kS1Stride + q] = t[q];
+struct TwTab {
+    using S = Sched<LOG2L>;
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int TPV = L / 16;
+    static constexpr int R(int s) { return S::radix(s); }
+    static constexpr int NS(int s) { return S::ns(s); }
+    static constexpr int F(int s) { return R(s) == 16 ? 16 : (TPV < 64 ? TPV : 64); }
+    static constexpr int nA(int s) { return NS(s) / F(s); }
+    static constexpr bool used(int s) { return s < S::kStages && NS(s) > 1; }
+    static constexpr int sizeA(int s) {
+        return !used(s) || nA(s) <= 1 ? 0 : (R(s) == 16 ? kTabStride * nA(s) : (R(s) - 1) * nA(s));
+    }
+    static constexpr int sizeB(int s) { return !used(s) ? 0 : (R(s) == 16 ? kTabStride * 16 : (R(s) - 1) * F(s)); }
+    static constexpr int off(int s) { return s == 0 ? 0 : off(s - 1) + sizeA(s - 1) + sizeB(s - 1); }
+    static constexpr int offA(int s) { return off(s); }
+    static constexpr int offB(int s) { return off(s) + sizeA(s); }
+    static constexpr int kSize = off(S::kStages);  // pairs
+    static_assert(S::kFull <= 3, "radix-16 stages beyond NS = 256 are not tabled");
+};
+
+// Entries of the tables of stage s, in fill order: R = 16: B rows (16 x
+// 16 pairs, q fastest) then A rows (nA x 16); R < 16: B (q-major, F per q)
+// then A (q-major, nA per q).  Entry i: its table index and the index of
+// its value in tw.
+template <int LOG2L, int s>
+struct TwFill {
+    using T = TwTab<LOG2L>;
+    static constexpr int L = T::L, R = T::R(s), F = T::F(s), nA = T::nA(s);
+    static constexpr int D = L / (R * T::NS(s));  // tw index step of one turn / (R NS)
+    static constexpr int nB = R == 16 ? 256 : (R - 1) * F;
+    static constexpr int nAe = nA > 1 ? (R == 16 ? nA * 16 : (R - 1) * nA) : 0;
+    static constexpr int count = T::used(s) ? nB + nAe : 0;
+    static constexpr int oA = T::offA(s), oB = T::offB(s);
+    __device__ __forceinline__ static void entry(int i, int& dst, int& src) {
+        if (i < nB) {
+            if constexpr (R == 16) {
+                const int lo = i >> 4, q = i & 15;
+                dst = oB + lo * kTabStride + q;
+                src = q * lo * D;
+            } else {
+                const int q = i / F + 1, lo = i % F;
+                dst = oB + i;
+                src = q * lo * D;
+            }
+        } else {
+            const int k = i - nB;
+            if constexpr (R == 16) {
+                const int hi = k >> 4, q = k & 15;
+                dst = oA + hi * kTabStride + q;
+                src = q * hi * F * D;
+            } else {
+                const int q = k / nA + 1, hi = k % nA;
+                dst = oA + k;
+                src = q * hi * F * D;
+            }
         }
-        // keep the caller's first loads after the table work, so that their
-        // registers and the table's temporaries are not live together
-        asm volatile("" ::: "memory");
+    }
+};
+
+// Fill every stage table of a length-2^LOG2L transform (ONLY_S1: the
+// stage-1 table only); NT threads (tid < NT) share the work.  Every load of a thread is issued before its first
+// store (indices past a table's end re-read a valid entry and are not
+// stored), so the fill costs one memory latency, which overlaps the
+// caller's own loads issued before it.
+template <int LOG2L, int NT, bool ONLY_S1 = false>
+__device__ __forceinline__ void fill_twiddle_tables(h2* tab, const float2* __restrict__ tw, int tid) {
+    using S = Sched<LOG2L>;
+    constexpr int L = 1 << LOG2L;
+    static_for<S::kStages>([&](auto si) {
+        constexpr int s = decltype(si)::value;
+        using Fi = TwFill<LOG2L, s>;
+        if constexpr (Fi::count > 0 && (!ONLY_S1 || s == 1)) {
+            constexpr int kIt = (Fi::count + NT - 1) / NT;
+            float2 val[kIt];
+            int dst[kIt];
+#pragma unroll
+            for (int it = 0; it < kIt; ++it) {
+                const int i = tid + it * NT;
+                int d, src;
+                Fi::entry(i < Fi::count ? i : Fi::count - 1, d, src);
+                dst[it] = i < Fi::count ? d : -1;
+                val[it] = tw[src & (L - 1)];
+            }
+#pragma unroll
+            for (int it = 0; it < kIt; ++it)
+                if (dst[it] >= 0) tab[dst[it]] = to_h2(val[it]);
+        }
+    });
+    // keep the caller's later loads after the table work, so that their
+    // registers and the table's temporaries are not live together
+    asm volatile("" ::: "memory");
+}
+
+// The float16 twiddles of thread j for stage s, from the tables (same
+// placement as stage_tw_h: R = 16 at t[q], R < 16 at t[u R + q]).
+template <int LOG2L, int s>
+__device__ __forceinline__ void stage_tw_tab(const h2* tab, int j, h2 (&t)[16]) {
+    using T = TwTab<LOG2L>;
+    constexpr int R = T::R(s), F = T::F(s), nA = T::nA(s);
+    constexpr int oA = T::offA(s), oB = T::offB(s), NS = T::NS(s), TPV = T::TPV;
+    // Opaque index: the reads are issued at each use instead of being
+    // shared between transforms (or hoisted out of loops) and held live.
+    asm volatile("" : "+v"(j));
+    if constexpr (R == 16) {
+        const int k = j & (NS - 1);
+        const uint4* rb = reinterpret_cast<const uint4*>(tab + oB + (k & 15) * kTabStride);
+        h2 b[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint4 x = rb[i];
+            b[4 * i] = __builtin_bit_cast(h2, x.x);
+            b[4 * i + 1] = __builtin_bit_cast(h2, x.y);
+            b[4 * i + 2] = __builtin_bit_cast(h2, x.z);
+            b[4 * i + 3] = __builtin_bit_cast(h2, x.w);
+        }
+        if constexpr (nA > 1) {
+            const uint4* ra = reinterpret_cast<const uint4*>(tab + oA + (k >> 4) * kTabStride);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint4 x = ra[i];
+                const h2 a4[4] = {__builtin_bit_cast(h2, x.x), __builtin_bit_cast(h2, x.y),
+                                  __builtin_bit_cast(h2, x.z), __builtin_bit_cast(h2, x.w)};
+#pragma unroll
+                for (int m = 0; m < 4; ++m) t[4 * i + m] = cmul(a4[m], b[4 * i + m]);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) t[q] = b[q];
+        }
+    } else {
+        const int lo = j & (F - 1);
+        static_for<16 / R>([&](auto ui) {
+            constexpr int u = decltype(ui)::value;
+            const int hi = (j >> __builtin_ctz(F)) + (TPV / F) * u;
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                const h2 bq = tab[oB + (q - 1) * F + lo];
+                if constexpr (nA > 1) t[u * R + q] = cmul(tab[oA + (q - 1) * nA + hi], bq);
+                else t[u * R + q] = bq;
+            }
+        });
     }
 }
 
@@ -561,8 +699,9 @@ __device__ __forceinline__ void fill_stage1_table(h2* tab, const float2* __restr
 // (it contains barriers).  With HALF_NORM (float16 forward transforms)
 // every even stage but the first scales its input by 1/16 (the caller
 // scales the first stage's input and applies the remaining 2^-kHalfRem).
-// Float16 transforms of length >= 2^8 with S1 read their stage-1 twiddles
-// from the table s1tab (fill_stage1_table).  Without LEAD the caller
+// Float16 transforms read their stage twiddles from the LDS tables ttab
+// (fill_twiddle_tables) as TW says: 0 none (float32 powers of the stage
+// bases, rounded once), 1 stage 1 only, 2 every stage.  Without LEAD the caller
 // guarantees that no thread still reads the vector's LDS, and the barrier
 // before the first exchange's stores is left out.  hook() runs after the stores
 // of the last exchange, before its barrier: global loads issued there for
@@ -570,10 +709,10 @@ __device__ __forceinline__ void fill_stage1_table(h2* tab, const float2* __restr
 struct NoHook {
     __device__ __forceinline__ void operator()() const {}
 };
-template <int LOG2L, int DIR, bool HALF_NORM = false, bool S1 = false, bool LEAD = true, class V, class Lds,
+template <int LOG2L, int DIR, bool HALF_NORM = false, int TW = 0, bool LEAD = true, class V, class Lds,
           class Hook = NoHook>
 __device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L, V>& tb, const Lds& lds,
-                                       const h2* s1tab = nullptr, const Hook& hook = Hook{}) {
+                                       const h2* ttab = nullptr, const Hook& hook = Hook{}) {
     using S = Sched<LOG2L>;
     constexpr int L = 1 << LOG2L;
     constexpr int TPV = L / 16;
@@ -588,16 +727,8 @@ __device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L
         h2 tw[16];
         if constexpr (HALF) {
             base = cone<V>();
-            if constexpr (S1 && s == 1 && kS1Tabled<LOG2L>) {
-                const uint4* row = reinterpret_cast<const uint4*>(s1tab + (j & 15) * kS1Stride);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const uint4 x = row[i];
-                    tw[4 * i] = __builtin_bit_cast(h2, x.x);
-                    tw[4 * i + 1] = __builtin_bit_cast(h2, x.y);
-                    tw[4 * i + 2] = __builtin_bit_cast(h2, x.z);
-                    tw[4 * i + 3] = __builtin_bit_cast(h2, x.w);
-                }
+            if constexpr (NS > 1 && (TW == 2 || (TW == 1 && s == 1))) {
+                stage_tw_tab<LOG2L, s>(ttab, j, tw);
             } else if constexpr (NS > 1) {
                 float2 b = tb.b[s];
                 asm volatile("" : "+v"(b.x), "+v"(b.y));  // recompute per use, not hoisted
@@ -629,148 +760,226 @@ __device__ __forceinline__ void fft_wg(V (&v)[16], int j, const StageBases<LOG2L
 //   A[l % 16][8 (l / 16) + t]   and   B[8 (l / 16) + t][l % 16],  t < 8,
 //   D[4 (l / 16) + t][l % 16],  t < 4.
 // With the input vector interleaved as (Re x0, Im x0, Re x1, ...) along K,
-// lane (g = l / 16, n = l % 16) supplies inputs q = 4g..4g+3 of vector n and
-// receives outputs s = 4g..4g+3 of vector n.
+// lane (g = l / 16, n = l % 16) supplies inputs q = 4g..4g+3 of vector n
+// and receives outputs s = 4g..4g+3 of vector n.
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-// The DFT matrix is carried as a float16 pair hi + lo (lo = the rounding
-// error of hi): a single float16 matrix would give every output a fixed
-// ~1e-4 gain error, which does not average out in a folded profile.
-struct Dft16Operands {
-    half8_t re_hi, re_lo, im_hi, im_lo;
-};
-
-__device__ __forceinline__ floatx4_t mfma16x16x32(const half8_t& hi, const half8_t& lo, const half8_t& b) {
-    const floatx4_t z = {0.f, 0.f, 0.f, 0.f};
-    const floatx4_t c = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo, b, z, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ void split_half(float x, _Float16& hi, _Float16& lo) {
-    hi = (_Float16)x;
-    lo = (_Float16)(x - (float)hi);
-}
-
-// cos and sin of 2 pi e / 16, e < 16 (float32 nearest to the exact values).
+// cos(2 pi e / 16), e < 16 (float32 nearest to the exact values).
 __constant__ const float kCos16[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
                                        0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
                                        -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
                                        0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
 
-// This lane's A operands for scale * exp(DIR 2 pi i q s / 16): rows of real
-// outputs hold (Re c, -Im c) per input q, rows of imaginary outputs (Im c, Re c).
+// The A operands of scale * exp(DIR 2 pi i s q / 16), one float16 per entry:
+// lane l holds row s = l % 16 (real outputs: (Re c, -Im c) per input q;
+// imaginary outputs: (Im c, Re c)) for inputs q = 4 (l / 16) .. +3.  A fixed
+// rounding of an entry changes the power gain of its output position by
+// about 1e-4, which the measured power gain of the path takes out on
+// average (float32 accumulation keeps the sums themselves exact).
+struct Dft16H {
+    half8_t re, im;
+};
 template <int DIR>
-__device__ __forceinline__ Dft16Operands dft16_operands(int lane, float scale) {
-    const int s = lane & 15;
-    const int g = lane >> 4;
-    Dft16Operands m;
+__device__ __forceinline__ Dft16H dft16_h(int lane, float scale) {
+    const int srow = lane & 15, g = (lane >> 4) & 3;
+    Dft16H m;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int e = ((4 * g + t) * s) & 15;
-        const float cs = kCos16[e], sn = kCos16[(e + 12) & 15];  // sin x = cos(x - pi/2)
-        const float cr = scale * cs, ci = scale * (DIR < 0 ? -sn : sn);
-        _Float16 h, l;
-        split_half(cr, h, l);
-        m.re_hi[2 * t] = h;
-        m.re_lo[2 * t] = l;
-        m.im_hi[2 * t + 1] = h;
-        m.im_lo[2 * t + 1] = l;
-        split_half(-ci, h, l);
-        m.re_hi[2 * t + 1] = h;
-        m.re_lo[2 * t + 1] = l;
-        split_half(ci, h, l);
-        m.im_hi[2 * t] = h;
-        m.im_lo[2 * t] = l;
+        const int e = ((4 * g + t) * srow) & 15;
+        const float c = scale * kCos16[e];
+        const float sn = scale * kCos16[(e + 12) & 15];  // sin x = cos(x - pi/2)
+        const float si = DIR < 0 ? -sn : sn;
+        m.re[2 * t] = (_Float16)c;
+        m.re[2 * t + 1] = (_Float16)(-si);
+        m.im[2 * t] = (_Float16)si;
+        m.im[2 * t + 1] = (_Float16)c;
     }
     return m;
 }
 
-// One radix-16 Stockham stage on matrix cores for 16 interleaved columns of
-// length L (thread c = tid % 16, j = tid / 16; wave lane = 16 (j % 4) + c).
-// The wave owns butterflies jp = (j & ~3) + b, b < 4, one MFMA batch each
-// (the 16 columns share the butterfly's twiddles).  src(pos) returns this
-// lane's column at pos; dst(pos, y) receives outputs.  If SYNC, a barrier
-// separates all reads from all writes (in-place LDS stages).
-template <int L, int NS, int DIR, bool SYNC, class Src, class Dst>
-__device__ __forceinline__ void mfma16_stage_cols(int j, const Dft16Operands& m, const float2* __restrict__ tw,
-                                                  Src&& src, Dst&& dst) {
-    asm volatile("" : "+v"(j));
-    const int g = j & 3;
-    const int jb = j & ~3;
-    floatx4_t dre[4], dim[4];
+// Outputs s = 4g..4g+3 of the 16 vectors of a batch from their inputs q =
+// 4g..4g+3 (x), rounded once from the float32 accumulators.
+__device__ __forceinline__ void mfma_dft16_h(const Dft16H& m, const h2* x, h2* y) {
+    half8_t b;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int jp = jb + b;
-        const int k = jp & (NS - 1);
-        half8_t bv;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int q = 4 * g + t;
-            float2 x = src(jp + q * (L / 16));
-            if constexpr (NS > 1) {
-                const float2 w = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(tw) +
-                                                                  (uint32_t)(q * k * (L / (16 * NS))) * 8u);
-                x = DIR < 0 ? cmul(x, w) : cmulc(x, w);
-            }
-            bv[2 * t] = (_Float16)x.x;
-            bv[2 * t + 1] = (_Float16)x.y;
-        }
-        dre[b] = mfma16x16x32(m.re_hi, m.re_lo, bv);
-        dim[b] = mfma16x16x32(m.im_hi, m.im_lo, bv);
+    for (int t = 0; t < 4; ++t) {
+        b[2 * t] = x[t].x;
+        b[2 * t + 1] = x[t].y;
     }
-    if constexpr (SYNC) __syncthreads();
+    const floatx4_t z = {0.f, 0.f, 0.f, 0.f};
+    const floatx4_t dr = __builtin_amdgcn_mfma_f32_16x16x32_f16(m.re, b, z, 0, 0, 0);
+    const floatx4_t di = __builtin_amdgcn_mfma_f32_16x16x32_f16(m.im, b, z, 0, 0, 0);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int jp = jb + b;
-        const int k = jp & (NS - 1);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) dst((jp - k) * 16 + k + (4 * g + t) * NS, make_float2(dre[b][t], dim[b][t]));
-    }
+    for (int t = 0; t < 4; ++t) y[t] = to_h2(make_float2(dr[t], di[t]));
 }
 
-// Length-L transform of 16 interleaved columns with the radix-16 stages on
-// matrix cores (operands in float16, accumulation in float32) and the final
-// small-radix stage, if any, in float32 arithmetic.  Each radix-16 stage is
-// scaled by scale16 (folded into the matrix), the small stage by scale_rem.
-// in(pos) gives the first stage's input for this lane's column; out(pos, y)
-// receives every output of this lane's column exactly once.  lds(pos) is
-// the float2 slot of this column at pos.  With OUT_SYNC a barrier precedes
-// the first out() call (out may then reuse the LDS).  Contains barriers.
-template <int LOG2L, int DIR, bool OUT_SYNC, class In, class Lds, class Out>
-__device__ __forceinline__ void colfft_mfma(int c, int j, const float2* __restrict__ tw, const StageBases<LOG2L>& tb,
-                                            float scale16, float scale_rem, In&& in, Lds&& lds, Out&& out) {
+// Matrix-core layout of a float16 transform of length L = 2^LOG2L (TPV =
+// L / 16 threads per vector).  Each wave holds 64 butterflies of a
+// radix-16 stage as 4 batches b of 16: lane (g, n) takes inputs q = 4g+t
+// (t < 4) of butterfly jp(b), in its registers v[4b + t].
+//   Rows (one vector per TPV threads, TPV >= 64, thread j of the vector):
+//     g = (j / 16) mod 4, n = j mod 16, jp(b) = 64 (j / 64) + 16 b + n.
+//   Columns (16 interleaved vectors, thread (c, j) with c = tid mod 16 the
+//     vector, j = tid / 16, TPV >= 4): g = j mod 4, n = c,
+//     jp(b) = 4 (j / 4) + b.
+template <bool COLS>
+__device__ __forceinline__ int mx_g(int j) {
+    return COLS ? (j & 3) : ((j >> 4) & 3);
+}
+template <bool COLS>
+__device__ __forceinline__ int mx_jp(int j, int b) {
+    return COLS ? 4 * (j >> 2) + b : (j & ~63) + 16 * b + (j & 15);
+}
+// Position of register e = 4b + t of thread j (the first stage's input).
+template <bool COLS, int TPV>
+__device__ __forceinline__ int mx_pos(int j, int e) {
+    return mx_jp<COLS>(j, e >> 2) + (4 * mx_g<COLS>(j) + (e & 3)) * TPV;
+}
+template <int LOG2L, bool COLS>
+constexpr bool kMxShape = COLS ? (LOG2L >= 6) : (LOG2L >= 10);
+
+// An int the optimiser cannot see through: values derived from it are
+// computed where used instead of being shared and held in registers.
+__device__ __forceinline__ int opaque_i(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Full length-L float16 transform with its radix-16 stages on the matrix
+// cores and the final small-radix stage (if any) in packed float16 vector
+// arithmetic: the same numbers as fft_wg<..., HALF_NORM, TT> but for the
+// butterfly sums.  v holds the input in the matrix-core layout (mx_pos),
+// or with IN_CANON in the canonical one (positions j + TPV e, moved
+// through LDS first), and receives the output in the canonical layout.
+// Twiddles come from the tables ttab (fill_twiddle_tables).  lds is the
+// vector's LDS accessor (PadLds for rows, ColLds for columns).  Every
+// thread of the workgroup calls this together.  Without LEAD the caller
+// guarantees that no thread still reads the vector's LDS.  hook() runs
+// after the stores of the last exchange, before its barrier.
+template <int LOG2L, int DIR, bool HALF_NORM, bool COLS, bool LEAD = true, bool IN_CANON = false, class Lds,
+          class Hook = NoHook>
+__device__ __forceinline__ void fft_mx(h2 (&v)[16], int j, const StageBases<LOG2L, h2>& tb, const Lds& lds,
+                                       const h2* ttab, const Hook& hook = Hook{}) {
     using S = Sched<LOG2L>;
+    using T = TwTab<LOG2L>;
     constexpr int L = 1 << LOG2L;
     constexpr int TPV = L / 16;
-    // A wave must hold 4 butterflies of 16 columns: L >= 64.
-    static_assert(LOG2L >= 6, "matrix-core column transform needs columns of at least 64 points");
-    const Dft16Operands m = dft16_operands<DIR>(threadIdx.x & 63, scale16);
-    auto from_lds = [&](int pos) { return lds(pos); };
-    auto to_lds = [&](int pos, float2 y) { lds(pos) = y; };
+    static_assert(kMxShape<LOG2L, COLS>, "matrix-core transform shape");
+    asm volatile("" : "+v"(j));
+    const int g = mx_g<COLS>(j);
+    const Dft16H m = dft16_h<DIR>((int)(threadIdx.x & 63), 1.0f);
+    if constexpr (IN_CANON) {
+        if constexpr (LEAD) __syncthreads();
+        static_for<16>([&](auto ei) {
+            constexpr int e = decltype(ei)::value;
+            lds.template put<TPV * e>(j, v[e]);
+        });
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = *lds.template addr<0>(mx_pos<COLS, TPV>(j, e));
+    }
+    // Per-thread bases: every access below is a base plus a compile-time
+    // offset.  Rows (PadLds, index p + p / 16): J0 = 64 (j / 64) + n is the
+    // batch-0 butterfly; columns (ColLds, index 16 p + 4 (p / 4) from the
+    // column): J0 = 4 (j / 4), a multiple of 4.
+    const int n = COLS ? 0 : (j & 15);
+    const int J0 = COLS ? 4 * (j >> 2) : (j & ~63) + n;
     static_for<S::kFull>([&](auto si) {
         constexpr int s = decltype(si)::value;
         constexpr int NS = S::ns(s);
-        constexpr bool LAST = (s == S::kStages - 1);
+        constexpr bool SC = HALF_NORM && s > 0 && (s % 2 == 0);
+        constexpr bool LASTMX = s == S::kFull - 1;
+        h2 x[16];
         if constexpr (s == 0) {
-            if constexpr (LAST) mfma16_stage_cols<L, NS, DIR, OUT_SYNC>(j, m, tw, in, out);
-            else mfma16_stage_cols<L, NS, DIR, false>(j, m, tw, in, to_lds);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = v[e];
         } else {
-            __syncthreads();
-            if constexpr (LAST) mfma16_stage_cols<L, NS, DIR, true>(j, m, tw, from_lds, out);
-            else mfma16_stage_cols<L, NS, DIR, true>(j, m, tw, from_lds, to_lds);
+            // input q = 4g + t of butterfly J0 + db: position J0 + 4g TPV + (db + t TPV)
+            const int p0 = opaque_i(J0 + 4 * g * TPV);
+            static_for<16>([&](auto ei) {
+                constexpr int e = decltype(ei)::value;
+                constexpr int b = e >> 2, t = e & 3;
+                constexpr int db = COLS ? b : 16 * b;
+                x[e] = *lds.template addr<db + t * TPV, true>(p0);
+            });
         }
+        if constexpr (NS > 1) {
+            constexpr int oA = T::offA(s), oB = T::offB(s);
+            // k = jp mod NS: rows k = (J0 mod NS) + 16 b (no wrap: 16 b + n < 64);
+            // columns k = (J0 mod NS) + b (J0 mod NS a multiple of 4)
+            const int k0 = opaque_i(J0 & (NS - 1));
+            const h2* tb0 = ttab + oB + (k0 & 15) * kTabStride + 4 * g;
+            const h2* ta0 = ttab + oA + (k0 >> 4) * kTabStride + 4 * g;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                // B row lo = k mod 16, A row hi = k / 16
+                const int dlo = COLS ? b : 0, dhi = COLS ? 0 : b;
+                const uint4 wb = *reinterpret_cast<const uint4*>(tb0 + dlo * kTabStride);
+                h2 w[4] = {__builtin_bit_cast(h2, wb.x), __builtin_bit_cast(h2, wb.y), __builtin_bit_cast(h2, wb.z),
+                           __builtin_bit_cast(h2, wb.w)};
+                if constexpr (NS > 16) {
+                    const uint4 wa = *reinterpret_cast<const uint4*>(ta0 + dhi * kTabStride);
+                    w[0] = cmul(__builtin_bit_cast(h2, wa.x), w[0]);
+                    w[1] = cmul(__builtin_bit_cast(h2, wa.y), w[1]);
+                    w[2] = cmul(__builtin_bit_cast(h2, wa.z), w[2]);
+                    w[3] = cmul(__builtin_bit_cast(h2, wa.w), w[3]);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) x[4 * b + t] = DIR < 0 ? cmul(x[4 * b + t], w[t]) : cmulc(x[4 * b + t], w[t]);
+            }
+        }
+        if constexpr (SC) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) x[e] = cscale(x[e], (_Float16)0.0625f);
+        }
+        h2 y[16];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) mfma_dft16_h(m, x + 4 * b, y + 4 * b);
+        // every thread has read this stage's inputs before any output lands
+        if constexpr (s > 0 || LEAD || IN_CANON) __syncthreads();
+        // output s' = 4g + t of butterfly jp = J0 + db (k = jp mod NS) goes to
+        // (jp - k) 16 + k + s' NS
+        if constexpr (!COLS && NS == 1) {
+            // rows, first stage: position 16 J0 + 4g + (256 b + t), index
+            // 17 J0 + 4g + (272 b + t) (4g + t < 16: no carry into p / 16)
+            h2* const w0 = lds.base + opaque_i(17 * J0 + 4 * g);
+            static_for<16>([&](auto ei) {
+                constexpr int e = decltype(ei)::value;
+                w0[272 * (e >> 2) + (e & 3)] = y[e];
+            });
+        } else {
+            const int kk = J0 & (NS - 1);
+            const int p0 = opaque_i((J0 - kk) * 16 + kk + 4 * g * NS);
+            static_for<16>([&](auto ei) {
+                constexpr int e = decltype(ei)::value;
+                constexpr int b = e >> 2, t = e & 3;
+                // columns: k = (J0 mod NS) + b (NS >= 16) or 0 (NS = 1); rows:
+                // k = n for NS = 16 (jp - k then moves by 16 b), k = (J0 mod
+                // NS) + 16 b for NS >= 64 (jp - k fixed)
+                constexpr int d = COLS ? (NS == 1 ? 16 * b + t : b + t * NS)
+                                       : (NS == 16 ? 256 * b + 16 * t : 16 * b + t * NS);
+                *lds.template addr<d, true>(p0) = y[e];
+            });
+        }
+        if constexpr (LASTMX) hook();
+        __syncthreads();
     });
     if constexpr (S::kRem > 1) {
         constexpr int s = S::kStages - 1;
-        __syncthreads();
-        float2 v[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = lds(j + TPV * e);
-        stockham_stage<L, S::kRem, S::ns(s), DIR, true>(v, j, tb.b[s], NoLds<float2>{});
-        if constexpr (OUT_SYNC) __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 16; ++e) out(j + TPV * e, cscale(v[e], scale_rem));
+        constexpr bool SC = HALF_NORM && s > 0 && (s % 2 == 0);
+        static_for<16>([&](auto ei) {
+            constexpr int e = decltype(ei)::value;
+            v[e] = lds.template get<TPV * e>(j);
+        });
+        h2 tw[16];
+        stage_tw_tab<LOG2L, s>(ttab, j, tw);
+        stockham_stage<L, S::kRem, S::ns(s), DIR, true, SC>(v, j, cone<h2>(), NoLds<h2>{}, tw);
+    } else {
+        static_for<16>([&](auto ei) {
+            constexpr int e = decltype(ei)::value;
+            v[e] = lds.template get<TPV * e>(j);
+        });
     }
 }
 

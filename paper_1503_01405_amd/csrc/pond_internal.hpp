@@ -19,6 +19,8 @@ constexpr double kFoldScale = 65536.0;
 constexpr double kFoldRangeLimit = 1099511627776.0;  // 2^40: flag larger single contributions
 
 enum Precision { kFp32 = 0, kMixed = 1, kMixedValu = 2, kHalf = 3 };
+// Forms whose arithmetic is packed float16 (float16 tables, measured power gain).
+constexpr bool f16_arith(int prec) { return prec == kHalf || prec == kMixed; }
 
 // K1: int8 unpack + forward column FFTs (length n2, stride n1).
 struct K1Args {
@@ -197,6 +199,7 @@ int plan_max_batch(int64_t nfft, int32_t precision, int32_t max_batch);
 // blocks in `work` and names the buffer K3 reads.  Synchronous; runs on the
 // null stream.
 struct HalfCal {
+    int prec = kHalf;             // kHalf or kMixed (float16 arithmetic forms)
     int log2n1 = 0, log2n2 = 0;
     const float2* tw2 = nullptr;  // exp(-2 pi i t / n2)
     void* work = nullptr;         // max_batch blocks of float16 pairs

@@ -77,24 +77,44 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
         }
     };
     T* out = reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
-    if constexpr (FORM == kFormF16) {
+    if constexpr (FORM == kFormF16 || FORM == kFormMfma) {
         // Packed float16: int8 is exact in float16; the first stage's 1/16
         // is applied here, the even stages scale themselves, and the rest
         // of the 1/n2 normalisation is applied on output, so no value
-        // exceeds 16x the input bound.
+        // exceeds 16x the input bound.  Matrix-core form: the radix-16
+        // stages' butterfly sums on the matrix cores (inputs loaded in
+        // their layout), the same numbers otherwise.
+        constexpr bool MX = FORM == kFormMfma && kMxShape<LOG2N2, true>;
         StageBases<LOG2N2, h2> tb;
         tb.load(j, a.tw2);
+        __shared__ __align__(16) h2 ttab[TwTab<LOG2N2>::kSize];
+        if (threadIdx.x < 64) fill_twiddle_tables<LOG2N2, 64>(ttab, a.tw2, threadIdx.x);  // one wave
         // int8 pair -> float16 pair / 16, exactly: the bytes, sign bit
         // flipped, become the low mantissa bits of 1024 (1152 + x), and
         // (1152 + x) / 16 - 72 = x / 16 is representable.
-        h2 v[16];
-        load_all([&](int e, auto uni) {
-            const uint32_t s = *reinterpret_cast<const uint16_t*>(src(e, uni));
+        auto unpack = [](const int8_t* p) {
+            const uint32_t s = *reinterpret_cast<const uint16_t*>(p);
             const uint32_t w = ((s & 0xffu) | ((s & 0xff00u) << 8)) ^ 0x64806480u;
-            v[e] = __builtin_elementwise_fma(__builtin_bit_cast(h2, w), h2{(_Float16)0.0625f, (_Float16)0.0625f},
+            return __builtin_elementwise_fma(__builtin_bit_cast(h2, w), h2{(_Float16)0.0625f, (_Float16)0.0625f},
                                              h2{(_Float16)-72.0f, (_Float16)-72.0f});
-        });
-        fft_wg<LOG2N2, -1, true, false, false>(v, j, tb, ColLds<h2, true>{lds + c});  // first LDS use: no lead barrier
+        };
+        h2 v[16];
+        if constexpr (MX) {
+            // value e = 4b + t at position 4 (j / 4) + b + (4 (j mod 4) + t) TPV
+            const uint32_t mxoff = BPE * (o0 + ((uint32_t)(4 * (j >> 2) + 4 * (j & 3) * TPV) << a.log2n1));
+            if (one_src) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    v[e] = unpack(at(ubase + ((int64_t)(BPE * ((e >> 2) + (e & 3) * TPV)) << a.log2n1), mxoff));
+            } else {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) v[e] = unpack(src_pos(mx_pos<true, TPV>(j, e)));
+            }
+            fft_mx<LOG2N2, -1, true, true, false>(v, j, tb, ColLds<h2, true>{lds + c}, ttab);  // first LDS use
+        } else {
+            load_all([&](int e, auto uni) { v[e] = unpack(src(e, uni)); });
+            fft_wg<LOG2N2, -1, true, 2, false>(v, j, tb, ColLds<h2, true>{lds + c}, ttab);  // first LDS use
+        }
         constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N2>::kHalfRem);
         const uint32_t woff = (opaque((uint32_t)col) + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
         T* const ob = uniform_ptr(out);
@@ -103,18 +123,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     } else {
         StageBases<LOG2N2> tb;
         tb.load(j, a.tw2);
-        if constexpr (FORM == kFormMfma && LOG2N2 >= 6) {
-            // Normalised forward pass (1/16 per radix-16 stage, folded into
-            // the DFT matrix): no float16 value can exceed the input range.
-            const uint32_t w0 = opaque((uint32_t)col);
-            colfft_mfma<LOG2N2, -1, false>(
-                c, j, a.tw2, tb, 1.0f / 16.0f, 1.0f / (float)Sched<LOG2N2>::kRem,
-                [&](int pos) { return cvt_in(src_pos(pos)); },
-                [&](int pos) -> float2& { return lds[pos * 16 + c]; },
-                [&](int pos, float2 y) {
-                    Elem<T>::store(at(out, (w0 + ((uint32_t)pos << a.log2n1)) * (uint32_t)sizeof(T)), y);
-                });
-        } else {
+        {
             float2 v[16];
             load_all([&](int e, auto uni) { v[e] = cvt_in(src(e, uni)); });
             fft_wg<LOG2N2, -1, false, false, false>(v, j, tb, ColLds<float2, true>{lds + c});  // first LDS use

@@ -55,11 +55,15 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 // modes: twiddle/16 and chirp).  The forward transform is normalised stage
 // by stage (1/16 of the first stage in the twiddle table), so the spectrum
 // is the block's spectrum / n; the output is 1/16 of the float32 forms'.
-template <int LOG2N1, class T, int MODE, bool F16>
-__global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+// MXF (with F16, rows of 2^10 and more): the radix-16 stages' butterfly
+// sums on the matrix cores (fft_mx), inputs loaded in their layout.
+template <int LOG2N1, class T, int MODE, bool F16, bool MXF = false>
+__global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS)
+    __attribute__((amdgpu_waves_per_eu(MXF && MODE == kRowFull && LOG2N1 >= 13 ? 8 : 4)))
 k2_row(K2Args a) {
     using Sh = K2Shape<LOG2N1>;
     using V = std::conditional_t<F16, h2, float2>;
+    constexpr bool MX = F16 && MXF && kMxShape<LOG2N1, false>;
     constexpr int TPV = Sh::TPV;
     __shared__ V lds[Sh::ROWS * Sh::STRIDE];
 
@@ -75,9 +79,9 @@ k2_row(K2Args a) {
     const int row = rg * Sh::ROWS + r;
     const bool valid = row < n2;
     // packed float16 rows of 2^12 and more: per-stage bank-conflict-free layouts
-    using RowL = std::conditional_t<F16 && LOG2N1 >= 12, StageRowLds<V>, PadLds<V>>;
+    using RowL = std::conditional_t<F16 && !MX && LOG2N1 >= 12, StageRowLds<V>, PadLds<V>>;
     const RowL lrow{lds + r * Sh::STRIDE};
-    static_assert(!(F16 && LOG2N1 >= 12) || (Sh::STRIDE >= (1 << LOG2N1) + 16 * ((1 << LOG2N1) >> 8)),
+    static_assert(!(F16 && !MX && LOG2N1 >= 12) || (Sh::STRIDE >= (1 << LOG2N1) + 16 * ((1 << LOG2N1) >> 8)),
                   "per-stage layouts fit the row");
 
     StageBases<LOG2N1, V> tb;
@@ -94,8 +98,11 @@ k2_row(K2Args a) {
     T* dst = INV ? reinterpret_cast<T*>(a.out) + rowbase : rows;
 
     if constexpr (F16) {
-        __shared__ h2 s1tab[kS1Pairs];
-        fill_stage1_table<LOG2N1>(s1tab, a.tw1, threadIdx.x);
+        __shared__ __align__(16) h2 ttab[TwTab<LOG2N1>::kSize];
+        // one wave fills the tables: every stage's for the matrix-core form,
+        // stage 1's for the packed-float16 form (its other stages form their
+        // twiddles from float32 powers, which measures faster here)
+        if (threadIdx.x < 64) fill_twiddle_tables<LOG2N1, 64, !MX>(ttab, a.tw1, threadIdx.x);
         const uint2* tab = reinterpret_cast<const uint2*>(a.htable) + ((int64_t)row0 << LOG2N1);
         const h2* tw4 = reinterpret_cast<const h2*>(a.htw4) + ((int64_t)row0 << LOG2N1);
         const h2* chirp = reinterpret_cast<const h2*>(a.hchirp) + ((int64_t)row0 << LOG2N1);
@@ -105,9 +112,11 @@ k2_row(K2Args a) {
         };
         h2 v[16];
         uint32_t to = opaque(toff);
+        // MX: value e at the matrix-core position mx_pos(j, e) of the row
+        const uint32_t mxo = opaque(toff - (uint32_t)j + (uint32_t)mx_pos<false, TPV>(j, 0));
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const uint32_t i = to + TPV * e;
+            const uint32_t i = MX ? mxo + (uint32_t)(16 * (e >> 2) + (e & 3) * TPV) : to + TPV * e;
             const h2 x = ld_h2(at(src, i * (uint32_t)sizeof(T)));
             if constexpr (MODE == kRowInv) v[e] = cmul(x, *at(chirp, i * 4u));
             else v[e] = cmul(x, tw_at(i));
@@ -120,8 +129,14 @@ k2_row(K2Args a) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) ch[e] = __builtin_bit_cast(h2, at(tab, (t2 + TPV * e) * 8u)->y);
         };
-        if constexpr (MODE == kRowFull) fft_wg<LOG2N1, -1, true, true>(v, j, tb, lrow, s1tab, fetch_chirp);
-        else if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true, true>(v, j, tb, lrow, s1tab);
+        if constexpr (MX) {
+            // first LDS use of the row: no barrier before the first stores
+            if constexpr (MODE == kRowFull) fft_mx<LOG2N1, -1, true, false, false>(v, j, tb, lrow, ttab, fetch_chirp);
+            else if constexpr (MODE != kRowInv) fft_mx<LOG2N1, -1, true, false, false>(v, j, tb, lrow, ttab);
+        } else {
+            if constexpr (MODE == kRowFull) fft_wg<LOG2N1, -1, true, 1>(v, j, tb, lrow, ttab, fetch_chirp);
+            else if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true, 1>(v, j, tb, lrow, ttab);
+        }
         if constexpr (MODE == kRowFwd) {
             constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N1>::kHalfRem);
             if (valid) {
@@ -143,7 +158,11 @@ k2_row(K2Args a) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) wo[e] = tw_at(t2 + TPV * e);
         };
-        fft_wg<LOG2N1, +1, false, true>(v, j, tb, lrow, s1tab, fetch_tw);
+        if constexpr (MX && MODE == kRowFull)  // input in registers (canonical), moved through LDS
+            fft_mx<LOG2N1, +1, false, false, true, true>(v, j, tb, lrow, ttab, fetch_tw);
+        else if constexpr (MX)  // kRowInv: input loaded in the matrix-core layout, first LDS use
+            fft_mx<LOG2N1, +1, false, false, false>(v, j, tb, lrow, ttab, fetch_tw);
+        else fft_wg<LOG2N1, +1, false, 1>(v, j, tb, lrow, ttab, fetch_tw);
         asm volatile("" ::: "memory");
         to = opaque(toff);
         if (valid) {
@@ -308,28 +327,28 @@ __global__ void __launch_bounds__(256) k2_build_split_tables(float2* __restrict_
     chirp[i] = make_float2((float)cc, (float)-cs);
 }
 
-template <class T, int MODE, bool F16, int LOG2N1>
+template <class T, int MODE, bool F16, bool MX, int LOG2N1>
 static hipError_t k2_one(const K2Args& a, hipStream_t s) {
     using Sh = K2Shape<LOG2N1>;
     const int groups = ((1 << a.log2n2) + Sh::ROWS - 1) / Sh::ROWS * a.nblocks;
     const int grid = (groups + 7) & ~7;
-    hipLaunchKernelGGL((k2_row<LOG2N1, T, MODE, F16>), dim3(grid), dim3(Sh::THREADS), 0, s, a);
+    hipLaunchKernelGGL((k2_row<LOG2N1, T, MODE, F16, MX>), dim3(grid), dim3(Sh::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-template <class T, int MODE, bool F16>
+template <class T, int MODE, bool F16, bool MX = false>
 static hipError_t k2_dispatch(int log2n1, const K2Args& a, hipStream_t s) {
     switch (log2n1) {
-        case 5: return k2_one<T, MODE, F16, 5>(a, s);
-        case 6: return k2_one<T, MODE, F16, 6>(a, s);
-        case 7: return k2_one<T, MODE, F16, 7>(a, s);
-        case 8: return k2_one<T, MODE, F16, 8>(a, s);
-        case 9: return k2_one<T, MODE, F16, 9>(a, s);
-        case 10: return k2_one<T, MODE, F16, 10>(a, s);
-        case 11: return k2_one<T, MODE, F16, 11>(a, s);
-        case 12: return k2_one<T, MODE, F16, 12>(a, s);
-        case 13: return k2_one<T, MODE, F16, 13>(a, s);
-        case 14: return k2_one<T, MODE, F16, 14>(a, s);
+        case 5: return k2_one<T, MODE, F16, MX, 5>(a, s);
+        case 6: return k2_one<T, MODE, F16, MX, 6>(a, s);
+        case 7: return k2_one<T, MODE, F16, MX, 7>(a, s);
+        case 8: return k2_one<T, MODE, F16, MX, 8>(a, s);
+        case 9: return k2_one<T, MODE, F16, MX, 9>(a, s);
+        case 10: return k2_one<T, MODE, F16, MX, 10>(a, s);
+        case 11: return k2_one<T, MODE, F16, MX, 11>(a, s);
+        case 12: return k2_one<T, MODE, F16, MX, 12>(a, s);
+        case 13: return k2_one<T, MODE, F16, MX, 13>(a, s);
+        case 14: return k2_one<T, MODE, F16, MX, 14>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -339,6 +358,7 @@ static hipError_t k2_prec(int prec, int log2n1, const K2Args& a, hipStream_t s) 
     switch (prec) {
         case kFp32: return k2_dispatch<float2, MODE, false>(log2n1, a, s);
         case kHalf: return k2_dispatch<__half2, MODE, true>(log2n1, a, s);
+        case kMixed: return k2_dispatch<__half2, MODE, true, true>(log2n1, a, s);
         default: return k2_dispatch<__half2, MODE, false>(log2n1, a, s);
     }
 }

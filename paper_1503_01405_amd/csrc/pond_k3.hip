@@ -40,7 +40,9 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     uint64_t* hsum = dyn_u64;
     uint32_t* hcnt = reinterpret_cast<uint32_t*>(dyn_u64 + (a.global_mode ? 0 : a.entries));
     float2* lds = reinterpret_cast<float2*>(lds_raw);
-    float* pf = reinterpret_cast<float*>(lds_raw + (FORM == kFormF16 ? Sh::kHalfTile : 0));
+    constexpr bool H16 = FORM == kFormF16 || FORM == kFormMfma;  // float16 arithmetic
+    constexpr bool MX = FORM == kFormMfma && kMxShape<LOG2N2, true>;  // radix-16 sums on matrix cores
+    float* pf = reinterpret_cast<float*>(lds_raw + (H16 ? Sh::kHalfTile : 0));
 
     const int c = threadIdx.x & 15;
     const int j = threadIdx.x >> 4;
@@ -68,15 +70,15 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
     StageBases<LOG2N2, LdsVal<FORM>> tb;
     tb.load(j, a.tw2);
     // packed float16: the stage-1 twiddle table follows the power buffer
-    h2* s1tab = reinterpret_cast<h2*>(lds_raw + Sh::kHalfTile + Sh::kHalfPf);
-    if constexpr (FORM == kFormF16) fill_stage1_table<LOG2N2>(s1tab, a.tw2, threadIdx.x);
+    h2* ttab = reinterpret_cast<h2*>(lds_raw + Sh::kHalfTile + Sh::kHalfPf);
+    if constexpr (H16) if (threadIdx.x < 64) fill_twiddle_tables<LOG2N2, 64>(ttab, a.tw2, threadIdx.x);
 
     // Float16 storage with VALU arithmetic, columns of 2^9 and 2^10: the
     // next item's column tile is loaded (as float16 pairs) while this one
     // is transformed and folded, so its latency is not exposed once per
     // item (the 16 registers are free there: the LDS already limits the
     // kernel to four waves per SIMD).
-    constexpr bool kPrefetch = (FORM == kFormF16 || (FORM == kFormF32 && std::is_same<T, __half2>::value)) &&
+    constexpr bool kPrefetch = (H16 || (FORM == kFormF32 && std::is_same<T, __half2>::value)) &&
                                (LOG2N2 == 10 || (LOG2N2 == 9 && !REAL));  // (else past 128 registers)
     h2 nxt[16];
     auto load_tile = [&](int it, h2(&dst)[16]) {
@@ -85,9 +87,19 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         const uint32_t cc = opaque((uint32_t)((r0 + 16 * tt + c) & (n1 - 1)));
         const __half2* const ib =
             uniform_ptr(reinterpret_cast<const __half2*>(a.work) + ((int64_t)bb << (a.log2n1 + LOG2N2)));
-        const uint32_t ioff = (cc + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(__half2);
+        if constexpr (MX) {
+            // matrix-core layout: value e = 4b + t at position
+            // 4 (j / 4) + b + (4 (j mod 4) + t) TPV
+            const uint32_t ioff =
+                (cc + ((uint32_t)(4 * (j >> 2) + 4 * (j & 3) * TPV) << a.log2n1)) * (uint32_t)sizeof(__half2);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) dst[e] = ld_h2(at(ib + ((int64_t)(TPV * e) << a.log2n1), ioff));
+            for (int e = 0; e < 16; ++e)
+                dst[e] = ld_h2(at(ib + ((int64_t)((e >> 2) + (e & 3) * TPV) << a.log2n1), ioff));
+        } else {
+            const uint32_t ioff = (cc + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(__half2);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) dst[e] = ld_h2(at(ib + ((int64_t)(TPV * e) << a.log2n1), ioff));
+        }
     };
     if constexpr (kPrefetch) {
         if (xcd * chunk + local < it_end) load_tile(xcd * chunk + local, nxt);
@@ -99,12 +111,10 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 
         const T* in = reinterpret_cast<const T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2));
         const uint32_t o0 = opaque((uint32_t)col);
-        auto load_in = [&](int pos) {
-            return Elem<T>::load(at(in, (o0 + ((uint32_t)pos << a.log2n1)) * (uint32_t)sizeof(T)));
-        };
-        if constexpr (FORM == kFormF16) {
-            // Packed float16 inverse transform (unnormalised), then the
-            // power in float32 from the float16 pair (exact products).
+        if constexpr (H16) {
+            // Packed float16 inverse transform (unnormalised; matrix-core
+            // form: radix-16 sums on the matrix cores), then the power in
+            // float32 from the float16 pair (exact products).
             h2* lh = reinterpret_cast<h2*>(lds);
             h2 v[16];
             if constexpr (kPrefetch) {
@@ -116,21 +126,13 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             }
             // no barrier before the first exchange: every wave has left the
             // previous item's transform (the barrier after its powers)
-            fft_wg<LOG2N2, +1, false, true, false>(v, j, tb, ColLds<h2, true>{lh + c}, s1tab);
+            if constexpr (MX) fft_mx<LOG2N2, +1, false, true, false>(v, j, tb, ColLds<h2, true>{lh + c}, ttab);
+            else fft_wg<LOG2N2, +1, false, 2, false>(v, j, tb, ColLds<h2, true>{lh + c}, ttab);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const float yx = (float)v[e].x, yy = (float)v[e].y;
                 pf[k3h_pidx(j + TPV * e, c)] = fmaf(yx, yx, yy * yy) * a.pscale;
             }
-            __syncthreads();
-        } else if constexpr (FORM == kFormMfma && LOG2N2 >= 6) {
-            __syncthreads();  // the previous item's epilogue has finished with the LDS
-            colfft_mfma<LOG2N2, +1, true>(
-                c, j, a.tw2, tb, 1.0f, 1.0f, load_in, [&](int pos) -> float2& { return lds[pos * 16 + c]; },
-                [&](int pos, float2 y) {
-                    const float2 z = cscale(y, a.scale);
-                    pf[pos * PSTRIDE + c] = fmaf(z.x, z.x, z.y * z.y);
-                });
             __syncthreads();
         } else {
             float2 v[16];
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float4 x4 = *reinterpret_cast<const float4*>(
-                    pf + (FORM == kFormF16 ? k3h_pidx(q, 4 * i) : q * PSTRIDE + 4 * i));
+                    pf + (H16 ? k3h_pidx(q, 4 * i) : q * PSTRIDE + 4 * i));
                 p[4 * i] = x4.x;
                 p[4 * i + 1] = x4.y;
                 p[4 * i + 2] = x4.z;
@@ -203,7 +205,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int rsrc = q + ((r0 + 16 * t + i) >> a.log2n1);
-                p[i] = rsrc < L ? pf[FORM == kFormF16 ? k3h_pidx(rsrc, i) : rsrc * PSTRIDE + i] : 0.f;
+                p[i] = rsrc < L ? pf[H16 ? k3h_pidx(rsrc, i) : rsrc * PSTRIDE + i] : 0.f;
             }
         }
         if (off < 0 || off >= a.hop) continue;
@@ -389,11 +391,16 @@ int k3_grid(int log2n2, int prec, size_t dyn_lds, int64_t items, int64_t entries
 }
 
 size_t k3_static_lds(int log2n2, int prec) {
-    const size_t l = (size_t)1 << log2n2;
-    if (prec == kHalf) return (16 * l + l) * sizeof(h2) + 16 * l * sizeof(float) + kS1Pairs * sizeof(h2);
-    return sizeof(float2) * 16 * l;
+    if (prec != kHalf && prec != kMixed) return sizeof(float2) * 16 * ((size_t)1 << log2n2);
+    switch (log2n2) {
+        case 5: return K3Shape<5>::LDS_HALF;
+        case 6: return K3Shape<6>::LDS_HALF;
+        case 7: return K3Shape<7>::LDS_HALF;
+        case 8: return K3Shape<8>::LDS_HALF;
+        case 9: return K3Shape<9>::LDS_HALF;
+        default: return K3Shape<10>::LDS_HALF;
+    }
 }
-static_assert(K3Shape<10>::LDS_HALF == (16 * 1024 + 1024) * 4 + 16 * 1024 * 4 + kS1Pairs * 4, "host copy of the K3 layout");
 int k1_threads(int log2n2) { return 1 << log2n2; }
 int k3_threads(int log2n2) { return 1 << log2n2; }
 int k2_threads(int log2n1) {

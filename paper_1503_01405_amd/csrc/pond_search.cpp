@@ -180,7 +180,7 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
         if (e == hipSuccess) chk(launch_stage_twiddles(g.tw2, n2, nullptr));
         chk(hipMalloc(&g.spec, (size_t)g.max_batch * g.nfft * s->elem));
         chk(hipMalloc(&g.out, (size_t)g.max_batch * g.nfft * s->elem));
-        const bool half = precision == POND_HALF;
+        const bool half = f16_arith(precision);
         if (half) chk(hipMalloc(&g.htw4, g.nfft * 4));
         else chk(hipMalloc(reinterpret_cast<void**>(&g.tw4), g.nfft * sizeof(float2)));
         g.chirp.assign(g.trials.size(), nullptr);
@@ -205,6 +205,7 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
         // group's first trial; every trial's table rounds alike).
         if (half && e == hipSuccess) {
             HalfCal cal;
+            cal.prec = precision;
             cal.log2n1 = g.log2n1;
             cal.log2n2 = g.log2n2;
             cal.tw2 = g.tw2;
@@ -220,12 +221,12 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
                     f.log2n2 = g.log2n2;
                     f.tw1 = g.tw1;
                     f.htw4 = g.htw4;
-                    hipError_t r = launch_k2(POND_HALF, kRowFwd, g.log2n1, f, nullptr);
+                    hipError_t r = launch_k2(precision, kRowFwd, g.log2n1, f, nullptr);
                     K2Args v = f;
                     v.in = g.spec;
                     v.out = g.out;
                     v.hchirp = g.hchirp[0];
-                    if (r == hipSuccess) r = launch_k2(POND_HALF, kRowInv, g.log2n1, v, nullptr);
+                    if (r == hipSuccess) r = launch_k2(precision, kRowInv, g.log2n1, v, nullptr);
                     *res = g.out;
                     return r;
                 },

@@ -63,7 +63,7 @@ int64_t pond_dedisperse_segment_noalloc(double f0_mhz, double bw_mhz, double dm,
                                         double period_s, int32_t precision, const int8_t* iq, int64_t nsamp,
                                         int32_t decim, float* profile, float* series, int64_t series_cap,
                                         void* hip_stream) {
-    if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU) return POND_EINVAL;
+    if (precision != POND_FP32 && precision != POND_MIXED_VALU) return POND_EINVAL;
     if (nfft <= 0 || (nfft & (nfft - 1)) || nfft < 1024 || nfft > kMaxNfft) return POND_EINVAL;
     if (nbins < 1 || nbins > kMaxBins || nsamp < 0 || (nsamp > 0 && !iq) || !profile) return POND_EINVAL;
     if ((reinterpret_cast<uintptr_t>(iq) & 1u) || !std::isfinite(period_s)) return POND_EINVAL;

@@ -25,8 +25,8 @@ pytestmark = pytest.mark.gpu
 
 DM, NFFT, NBINS, PERIOD = 50.0, 1 << 23, 1024, synth.PERIOD_S
 NSAMP, SUBINT, DECIM = 960_000_000, 160_000_000, 16
-PROFILE_TOL = {"fp32": 1e-6, "half": 1e-4}
-SERIES_TOL = {"fp32": 1e-5, "half": 1e-2}
+PROFILE_TOL = {"fp32": 1e-6, "half": 1e-4, "mixed": 1e-4}
+SERIES_TOL = {"fp32": 1e-5, "half": 1e-2, "mixed": 1e-2}
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +44,7 @@ def oracle_full(stream):
     return r
 
 
-@pytest.mark.parametrize("precision", ["half", "fp32"])
+@pytest.mark.parametrize("precision", ["half", "mixed", "fp32"])
 def test_full_stream_profiles_and_series_vs_oracle(stream, oracle_full, precision):
     import torch
     import paper_1503_01405_amd as P
