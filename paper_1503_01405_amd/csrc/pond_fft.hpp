@@ -846,21 +846,144 @@ __device__ __forceinline__ int opaque_i(int x) {
     return x;
 }
 
+// LDS layouts of the matrix-core transform's exchanges.  A float16 pair is
+// one dword; a wave's 32-bit LDS access is served half a wave (32 lanes) at
+// a time from 32 banks (dword index mod 32), so an access is free of bank
+// conflicts when the 16 butterflies n and the two input groups g mod 2 of
+// each half wave land on 32 distinct banks.  The stores of one stage and
+// the reads of the next put g on different position bits (4 g TPV for the
+// reads, 4 g NS for the stores), so each exchange X (0: the canonical input
+// moved in, s + 1: after radix-16 stage s) has its own layout: position p
+// is stored at index p ^ F(p), where F copies a few high bits of p onto low
+// (bank) bits (columns, 16 interleaved vectors at index 16 p' + vector: bit
+// 0 of p').  Sources and targets are disjoint, so the map is a bijection of
+// [0, L).  An access at base p0 plus a compile-time offset d (p0 and d with
+// no common bits) becomes (index(p0) ^ X(d)) + C(d): target bits of d XOR
+// into the base, the rest is an immediate offset.
+//
+// Rows keep the plain layout (F = 0).  Conflict-free row layouts exist
+// (after stage 0: bits 5, 6, 7, L-2 onto 0, 1, 3, 4; after stage 1: bits 6
+// and L-2 onto 4), but both make the stage's stores XOR in their output
+// index t, which splits the stores of a thread over several bases and
+// holds them until every matrix product of the stage has finished; the row
+// kernel measured 10-15% slower with them, while its bank conflicts (up to
+// 8-way on the stage-0 stores) cost it nothing measurable: it is bound by
+// exchange latency, not by LDS cycles.
+template <int LOG2L, bool COLS, int X>
+struct MxSwz {
+    static constexpr int SH = COLS ? 4 : 0;
+    // target bit of source bit k, or -1
+    static constexpr int tgt(int k) {
+        if (COLS) {
+            if (X == 1) return (k == 2 || (LOG2L >= 8 && k == LOG2L - 2)) ? 0 : -1;
+            if (X == 2) return k == 6 ? 0 : -1;
+        }
+        return -1;
+    }
+    static constexpr uint32_t F(uint32_t p) {
+        uint32_t r = 0;
+        for (int k = 0; k < LOG2L; ++k)
+            if (tgt(k) >= 0 && ((p >> k) & 1u)) r ^= 1u << tgt(k);
+        return r;
+    }
+    static constexpr uint32_t tmask() {
+        uint32_t r = 0;
+        for (int k = 0; k < LOG2L; ++k)
+            if (tgt(k) >= 0) r |= 1u << tgt(k);
+        return r;
+    }
+    static constexpr uint32_t kT = tmask();
+    // the part of an offset that XORs into the base
+    static constexpr uint32_t xpart(uint32_t d) { return (d & kT) ^ F(d); }
+    // scaled index of a base position (computed where used)
+    __device__ static __forceinline__ uint32_t base(int p0) {
+        const uint32_t p = (uint32_t)opaque_i(p0);
+        uint32_t r = p;
+        static_for<LOG2L>([&](auto ki) {
+            constexpr int k = decltype(ki)::value;
+            constexpr int m = tgt(k);
+            if constexpr (m >= 0) r ^= (p >> (k - m)) & (1u << m);
+        });
+        return r << SH;
+    }
+    // scaled index of base + D (D a compile-time offset disjoint from the base)
+    template <uint32_t D>
+    __device__ static __forceinline__ uint32_t at(uint32_t mb) {
+        constexpr uint32_t xd = xpart(D) << SH;
+        constexpr uint32_t cd = (D & ~kT) << SH;
+        if constexpr (xd != 0) return (mb ^ xd) + cd;
+        else return mb + cd;
+    }
+};
+
+// Offsets of the 16 accesses of a thread: reads of a stage (inputs q = 4g + t
+// of butterfly batch b), stores of a stage with NS = ns, canonical (j + TPV e).
+template <bool COLS, int TPV>
+struct MxRead {
+    static constexpr uint32_t d(int e) { return (COLS ? (e >> 2) : 16 * (e >> 2)) + (e & 3) * TPV; }
+};
+template <bool COLS, int NS>
+struct MxStore {
+    // columns: k = (J0 mod NS) + b (NS >= 16) or 0 (NS = 1); rows: k = 0
+    // (NS = 1; jp - k moves by 16 b), k = n for NS = 16 (jp - k moves by
+    // 16 b), k = (J0 mod NS) + 16 b for NS >= 64 (jp - k fixed)
+    static constexpr uint32_t d(int e) {
+        const int b = e >> 2, t = e & 3;
+        if (COLS) return NS == 1 ? 16 * b + t : b + t * NS;
+        return NS == 1 ? 256 * b + t : NS == 16 ? 256 * b + 16 * t : 16 * b + t * NS;
+    }
+};
+template <int TPV>
+struct MxCanon {
+    static constexpr uint32_t d(int e) { return TPV * e; }
+};
+// The 16 accesses grouped by their XOR term (first appearance order):
+// accesses from one base are issued next to each other, so the compiler
+// can merge pairs of them into one two-address instruction.
+struct Ord16 {
+    int v[16];
+};
+template <class W, class D>
+constexpr Ord16 mx_order() {
+    Ord16 o{};
+    uint32_t key[16] = {};
+    for (int e = 0; e < 16; ++e) key[e] = W::xpart(D::d(e));
+    int k = 0;
+    for (int e = 0; e < 16; ++e) {
+        bool first = true;
+        for (int f = 0; f < e; ++f)
+            if (key[f] == key[e]) first = false;
+        if (!first) continue;
+        for (int f = e; f < 16; ++f)
+            if (key[f] == key[e]) o.v[k++] = f;
+    }
+    return o;
+}
+// fn(e, D(e)) for the 16 accesses, grouped by base
+template <class W, class D, class Fn>
+__device__ __forceinline__ void mx_each(Fn&& fn) {
+    constexpr Ord16 o = mx_order<W, D>();
+    static_for<16>([&](auto ii) {
+        constexpr int e = o.v[decltype(ii)::value];
+        fn(std::integral_constant<int, e>{}, std::integral_constant<uint32_t, D::d(e)>{});
+    });
+}
+
 // Full length-L float16 transform with its radix-16 stages on the matrix
 // cores and the final small-radix stage (if any) in packed float16 vector
 // arithmetic: the same numbers as fft_wg<..., HALF_NORM, TT> but for the
 // butterfly sums.  v holds the input in the matrix-core layout (mx_pos),
 // or with IN_CANON in the canonical one (positions j + TPV e, moved
 // through LDS first), and receives the output in the canonical layout.
-// Twiddles come from the tables ttab (fill_twiddle_tables).  lds is the
-// vector's LDS accessor (PadLds for rows, ColLds for columns).  Every
-// thread of the workgroup calls this together.  Without LEAD the caller
-// guarantees that no thread still reads the vector's LDS.  hook() runs
-// after the stores of the last exchange, before its barrier.
-template <int LOG2L, int DIR, bool HALF_NORM, bool COLS, bool LEAD = true, bool IN_CANON = false, class Lds,
+// Twiddles come from the tables ttab (fill_twiddle_tables).  buf is the
+// vector's LDS: L dwords for a row, or for columns the first of 16
+// interleaved vectors (16 L dwords from the tile, offset by the vector).
+// Every thread of the workgroup calls this together.  Without LEAD the
+// caller guarantees that no thread still reads the vector's LDS.  hook()
+// runs after the stores of the last exchange, before its barrier.
+template <int LOG2L, int DIR, bool HALF_NORM, bool COLS, bool LEAD = true, bool IN_CANON = false,
           class Hook = NoHook>
-__device__ __forceinline__ void fft_mx(h2 (&v)[16], int j, const StageBases<LOG2L, h2>& tb, const Lds& lds,
-                                       const h2* ttab, const Hook& hook = Hook{}) {
+__device__ __forceinline__ void fft_mx(h2 (&v)[16], int j, h2* buf, const h2* ttab, const Hook& hook = Hook{}) {
     using S = Sched<LOG2L>;
     using T = TwTab<LOG2L>;
     constexpr int L = 1 << LOG2L;
@@ -869,22 +992,28 @@ __device__ __forceinline__ void fft_mx(h2 (&v)[16], int j, const StageBases<LOG2
     asm volatile("" : "+v"(j));
     const int g = mx_g<COLS>(j);
     const Dft16H m = dft16_h<DIR>((int)(threadIdx.x & 63), 1.0f);
-    if constexpr (IN_CANON) {
-        if constexpr (LEAD) __syncthreads();
-        static_for<16>([&](auto ei) {
-            constexpr int e = decltype(ei)::value;
-            lds.template put<TPV * e>(j, v[e]);
-        });
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = *lds.template addr<0>(mx_pos<COLS, TPV>(j, e));
-    }
-    // Per-thread bases: every access below is a base plus a compile-time
-    // offset.  Rows (PadLds, index p + p / 16): J0 = 64 (j / 64) + n is the
-    // batch-0 butterfly; columns (ColLds, index 16 p + 4 (p / 4) from the
-    // column): J0 = 4 (j / 4), a multiple of 4.
+    // Batch-0 butterfly of the thread: rows J0 = 64 (j / 64) + n, columns
+    // J0 = 4 (j / 4); batch b is J0 + 16 b (rows) or J0 + b (columns).
     const int n = COLS ? 0 : (j & 15);
     const int J0 = COLS ? 4 * (j >> 2) : (j & ~63) + n;
+    // inputs q = 4g + t of butterfly J0 + db: position J0 + 4g TPV + (db + t TPV)
+    auto read_mx = [&](auto xi, h2(&x)[16]) {
+        using W = MxSwz<LOG2L, COLS, decltype(xi)::value>;
+        const uint32_t mb = W::base(J0 + 4 * g * TPV);
+        mx_each<W, MxRead<COLS, TPV>>([&](auto ei, auto di) {
+            x[decltype(ei)::value] = buf[W::template at<decltype(di)::value>(mb)];
+        });
+    };
+    if constexpr (IN_CANON) {
+        using W = MxSwz<LOG2L, COLS, 0>;
+        if constexpr (LEAD) __syncthreads();
+        const uint32_t mb = W::base(j);
+        mx_each<W, MxCanon<TPV>>([&](auto ei, auto di) {
+            buf[W::template at<decltype(di)::value>(mb)] = v[decltype(ei)::value];
+        });
+        __syncthreads();
+        read_mx(std::integral_constant<int, 0>{}, v);
+    }
     static_for<S::kFull>([&](auto si) {
         constexpr int s = decltype(si)::value;
         constexpr int NS = S::ns(s);
@@ -895,14 +1024,7 @@ __device__ __forceinline__ void fft_mx(h2 (&v)[16], int j, const StageBases<LOG2
 #pragma unroll
             for (int e = 0; e < 16; ++e) x[e] = v[e];
         } else {
-            // input q = 4g + t of butterfly J0 + db: position J0 + 4g TPV + (db + t TPV)
-            const int p0 = opaque_i(J0 + 4 * g * TPV);
-            static_for<16>([&](auto ei) {
-                constexpr int e = decltype(ei)::value;
-                constexpr int b = e >> 2, t = e & 3;
-                constexpr int db = COLS ? b : 16 * b;
-                x[e] = *lds.template addr<db + t * TPV, true>(p0);
-            });
+            read_mx(std::integral_constant<int, s>{}, x);
         }
         if constexpr (NS > 1) {
             constexpr int oA = T::offA(s), oB = T::offB(s);
@@ -939,47 +1061,31 @@ __device__ __forceinline__ void fft_mx(h2 (&v)[16], int j, const StageBases<LOG2
         // every thread has read this stage's inputs before any output lands
         if constexpr (s > 0 || LEAD || IN_CANON) __syncthreads();
         // output s' = 4g + t of butterfly jp = J0 + db (k = jp mod NS) goes to
-        // (jp - k) 16 + k + s' NS
-        if constexpr (!COLS && NS == 1) {
-            // rows, first stage: position 16 J0 + 4g + (256 b + t), index
-            // 17 J0 + 4g + (272 b + t) (4g + t < 16: no carry into p / 16)
-            h2* const w0 = lds.base + opaque_i(17 * J0 + 4 * g);
-            static_for<16>([&](auto ei) {
-                constexpr int e = decltype(ei)::value;
-                w0[272 * (e >> 2) + (e & 3)] = y[e];
-            });
-        } else {
+        // (jp - k) 16 + k + s' NS; the base is that of batch 0, t = 0
+        {
+            using W = MxSwz<LOG2L, COLS, s + 1>;
             const int kk = J0 & (NS - 1);
-            const int p0 = opaque_i((J0 - kk) * 16 + kk + 4 * g * NS);
-            static_for<16>([&](auto ei) {
-                constexpr int e = decltype(ei)::value;
-                constexpr int b = e >> 2, t = e & 3;
-                // columns: k = (J0 mod NS) + b (NS >= 16) or 0 (NS = 1); rows:
-                // k = n for NS = 16 (jp - k then moves by 16 b), k = (J0 mod
-                // NS) + 16 b for NS >= 64 (jp - k fixed)
-                constexpr int d = COLS ? (NS == 1 ? 16 * b + t : b + t * NS)
-                                       : (NS == 16 ? 256 * b + 16 * t : 16 * b + t * NS);
-                *lds.template addr<d, true>(p0) = y[e];
+            const uint32_t mb = W::base((J0 - kk) * 16 + kk + 4 * g * NS);
+            mx_each<W, MxStore<COLS, NS>>([&](auto ei, auto di) {
+                buf[W::template at<decltype(di)::value>(mb)] = y[decltype(ei)::value];
             });
         }
         if constexpr (LASTMX) hook();
         __syncthreads();
     });
+    {
+        using W = MxSwz<LOG2L, COLS, S::kFull>;
+        const uint32_t mb = W::base(j);
+        mx_each<W, MxCanon<TPV>>([&](auto ei, auto di) {
+            v[decltype(ei)::value] = buf[W::template at<decltype(di)::value>(mb)];
+        });
+    }
     if constexpr (S::kRem > 1) {
         constexpr int s = S::kStages - 1;
         constexpr bool SC = HALF_NORM && s > 0 && (s % 2 == 0);
-        static_for<16>([&](auto ei) {
-            constexpr int e = decltype(ei)::value;
-            v[e] = lds.template get<TPV * e>(j);
-        });
         h2 tw[16];
         stage_tw_tab<LOG2L, s>(ttab, j, tw);
         stockham_stage<L, S::kRem, S::ns(s), DIR, true, SC>(v, j, cone<h2>(), NoLds<h2>{}, tw);
-    } else {
-        static_for<16>([&](auto ei) {
-            constexpr int e = decltype(ei)::value;
-            v[e] = lds.template get<TPV * e>(j);
-        });
     }
 }
 

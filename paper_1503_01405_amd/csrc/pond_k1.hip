@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
 #pragma unroll
                 for (int e = 0; e < 16; ++e) v[e] = unpack(src_pos(mx_pos<true, TPV>(j, e)));
             }
-            fft_mx<LOG2N2, -1, true, true, false>(v, j, tb, ColLds<h2, true>{lds + c}, ttab);  // first LDS use
+            fft_mx<LOG2N2, -1, true, true, false>(v, j, lds + c, ttab);  // first LDS use
         } else {
             load_all([&](int e, auto uni) { v[e] = unpack(src(e, uni)); });
             fft_wg<LOG2N2, -1, true, 2, false>(v, j, tb, ColLds<h2, true>{lds + c}, ttab);  // first LDS use

@@ -131,8 +131,8 @@ k2_row(K2Args a) {
         };
         if constexpr (MX) {
             // first LDS use of the row: no barrier before the first stores
-            if constexpr (MODE == kRowFull) fft_mx<LOG2N1, -1, true, false, false>(v, j, tb, lrow, ttab, fetch_chirp);
-            else if constexpr (MODE != kRowInv) fft_mx<LOG2N1, -1, true, false, false>(v, j, tb, lrow, ttab);
+            if constexpr (MODE == kRowFull) fft_mx<LOG2N1, -1, true, false, false>(v, j, lrow.base, ttab, fetch_chirp);
+            else if constexpr (MODE != kRowInv) fft_mx<LOG2N1, -1, true, false, false>(v, j, lrow.base, ttab);
         } else {
             if constexpr (MODE == kRowFull) fft_wg<LOG2N1, -1, true, 1>(v, j, tb, lrow, ttab, fetch_chirp);
             else if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true, 1>(v, j, tb, lrow, ttab);
@@ -159,9 +159,9 @@ k2_row(K2Args a) {
             for (int e = 0; e < 16; ++e) wo[e] = tw_at(t2 + TPV * e);
         };
         if constexpr (MX && MODE == kRowFull)  // input in registers (canonical), moved through LDS
-            fft_mx<LOG2N1, +1, false, false, true, true>(v, j, tb, lrow, ttab, fetch_tw);
+            fft_mx<LOG2N1, +1, false, false, true, true>(v, j, lrow.base, ttab, fetch_tw);
         else if constexpr (MX)  // kRowInv: input loaded in the matrix-core layout, first LDS use
-            fft_mx<LOG2N1, +1, false, false, false>(v, j, tb, lrow, ttab, fetch_tw);
+            fft_mx<LOG2N1, +1, false, false, false>(v, j, lrow.base, ttab, fetch_tw);
         else fft_wg<LOG2N1, +1, false, 1>(v, j, tb, lrow, ttab, fetch_tw);
         asm volatile("" ::: "memory");
         to = opaque(toff);

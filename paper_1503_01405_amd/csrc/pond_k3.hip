@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
             }
             // no barrier before the first exchange: every wave has left the
             // previous item's transform (the barrier after its powers)
-            if constexpr (MX) fft_mx<LOG2N2, +1, false, true, false>(v, j, tb, ColLds<h2, true>{lh + c}, ttab);
+            if constexpr (MX) fft_mx<LOG2N2, +1, false, true, false>(v, j, lh + c, ttab);
             else fft_wg<LOG2N2, +1, false, 2, false>(v, j, tb, ColLds<h2, true>{lh + c}, ttab);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
