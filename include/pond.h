@@ -161,7 +161,11 @@ int64_t pond_dedisperse_segment_noalloc(double f0_mhz, double bw_mhz, double dm,
  *   f0_mhz   band centre, sky MHz (> bw_mhz/2)
  *   bw_mhz   complex bandwidth = sample rate in Msps (> 0)
  *   dm       dispersion measure, pc cm^-3, finite, >= 0
- *   nfft     FFT length, power of two in [2^10, 2^24]
+ *   nfft     FFT length, power of two in [2^10, 2^27]; rows of the four-step
+ *            factorisation (n1 = nfft / 2^10) longer than 2^14, i.e. nfft of
+ *            2^25 and more, are themselves transformed in four steps (a
+ *            column pass of length n1 / 2^13 and sub-rows of 2^13), which
+ *            adds one read and one write of the block per pass
  *   nbins    profile bins in [1, 65536]
  *   period_s folding period in seconds, finite, period_s * fs >= 1
  * Geometry: n_front = ceil(delta_hi fs), s = n_front + ceil(delta_lo fs),

@@ -20,7 +20,8 @@ namespace {
 thread_local int32_t g_create_status = POND_OK;
 
 constexpr int64_t kMinLog2N = 10;
-constexpr int64_t kMaxLog2N = 24;
+constexpr int64_t kMaxLog2N = 27;       // complex input; rows past 2^14 take the split middle pass
+constexpr int64_t kMaxLog2NReal = 24;   // real input (its middle passes transform whole rows)
 constexpr int kMaxLog2N2 = 10;          // column length cap (K1/K3 tile = 16 columns in LDS)
 constexpr int64_t kDefaultAccSlots = 4; // sub-integrations the accumulator ring holds at creation
 
@@ -95,6 +96,16 @@ struct pond_plan {
     float2* tw2 = nullptr;
     float4* table = nullptr;    // float32 forms
     void* htable = nullptr;     // packed float16 form (8 bytes per entry)
+    // Split middle pass (rows n1 = m2 2^13 longer than 2^14): tw1 then holds
+    // the sub-row twiddles, tw_n1 the row's, tw_hi / tw_lo the two-level
+    // block twiddle, chirp_split the chirp in sub-row order (float2, or
+    // float16 pairs for the float16 arithmetic forms).
+    int log2m2 = 0;             // 0: rows transformed whole
+    int log2s = 0;
+    float2* tw_n1 = nullptr;
+    float2* tw_hi = nullptr;
+    float2* tw_lo = nullptr;
+    void* chirp_split = nullptr;
     float pscale = 1.0f;        // detected-power scale applied in K3
     // Packed float16: the middle pass leaves 1/16 of the value (its twiddle
     // table carries the first stage's 1/16), so the power scale is 256
@@ -184,10 +195,46 @@ void free_plan_memory(pond_plan* p) {
     p->marks.clear();
     for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     p->event_pool.clear();
-    void* ptrs[] = {p->work, p->tail[0], p->tail[1], p->tw1, p->tw2, p->table, p->htable, p->tw4, p->rtab, p->wk,
-                    p->acc_sum, p->acc_cnt, p->part_sum, p->part_cnt, p->status};
+    void* ptrs[] = {p->work,   p->tail[0], p->tail[1], p->tw1,     p->tw2,         p->table,
+                    p->htable, p->tw4,     p->rtab,    p->wk,      p->tw_n1,       p->tw_hi,
+                    p->tw_lo,  p->acc_sum, p->acc_cnt, p->part_sum, p->part_cnt, p->status, p->chirp_split};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+}
+
+// The middle pass of a complex-input plan over nb blocks in p->work: K2 in
+// kRowFull mode, or for rows longer than 2^14 the split pass (forward column
+// pass, K2 kRowChirp on the sub-rows of 2^13, inverse column pass).  The
+// normalisation is the same either way: 1/n1 on the forward side (split:
+// 1/m2 in the column pass, 1/m1 in the sub-rows), and the float16 forms'
+// output keeps 1/16 of the value (K2 multiplies by the twiddle / 16; the
+// split pass's inverse columns scale by 1/16; the forward columns carry the
+// first row stage's 1/16, which K2 otherwise takes from its table).
+hipError_t run_middle(const pond_plan* p, int nb, hipStream_t stream) {
+    K2Args a2{};
+    a2.work = p->work;
+    a2.nblocks = nb;
+    a2.tw1 = p->tw1;
+    if (p->log2m2 == 0) {
+        a2.log2n2 = p->log2n2;
+        a2.table = p->table;
+        a2.htable = p->htable;
+        a2.scale = std::ldexp(1.0f, -p->log2n1);
+        return launch_k2(p->precision, kRowFull, p->log2n1, a2, stream);
+    }
+    const bool h = f16_arith(p->precision);
+    SplitColArgs sc{p->work, nb, p->log2n1, p->log2n2, p->tw_n1, p->tw_hi, p->tw_lo, p->log2s, 1.0f};
+    sc.scale = std::ldexp(1.0f, -p->log2m2 - (h ? 4 : 0));
+    hipError_t e = launch_split_cols(p->precision, false, sc, stream);
+    if (e != hipSuccess) return e;
+    a2.log2n2 = p->log2n2 + p->log2m2;
+    a2.chirp = reinterpret_cast<const float2*>(p->chirp_split);
+    a2.hchirp = p->chirp_split;
+    a2.scale = std::ldexp(1.0f, -kSplitLog2M1);
+    e = launch_k2(p->precision, kRowChirp, kSplitLog2M1, a2, stream);
+    if (e != hipSuccess) return e;
+    sc.scale = h ? 1.0f / 16.0f : 1.0f;
+    return launch_split_cols(p->precision, true, sc, stream);
 }
 
 int default_max_batch(int64_t nfft, int32_t precision, int32_t max_batch) {
@@ -304,10 +351,15 @@ int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t m
     const int64_t n1 = (int64_t)1 << (log2n - log2n2), n2 = (int64_t)1 << log2n2;
     const int64_t elem = precision == POND_FP32 ? 8 : 4;
     const int64_t mb = default_max_batch(nfft, precision, max_batch);
-    const int64_t table = f16_arith(precision) ? 8 : 16;
+    const bool split = (log2n - log2n2) > kMaxLog2RowN1;
+    int64_t tables = nfft * (f16_arith(precision) ? 8 : 16) + (n1 + n2) * 8;
+    if (split) {
+        const int log2s = (log2n + 1) / 2;
+        const int64_t m1 = (int64_t)1 << kSplitLog2M1;
+        tables = nfft * (f16_arith(precision) ? 4 : 8) + (m1 + n2 + n1 + (nfft >> log2s) + ((int64_t)1 << log2s)) * 8;
+    }
     const int64_t slots = acc_slots > kDefaultAccSlots ? acc_slots : kDefaultAccSlots;
-    return mb * nfft * elem + 2 * nfft * 2 + (n1 + n2) * 8 + nfft * table + 2 * slots * (int64_t)nbins * 8 +
-           kPartEntries * 12 + 8;
+    return mb * nfft * elem + 2 * nfft * 2 + tables + 2 * slots * (int64_t)nbins * 8 + kPartEntries * 12 + 8;
 }
 
 int plan_max_batch(int64_t nfft, int32_t precision, int32_t max_batch) {
@@ -369,6 +421,9 @@ hipError_t build_filter(pond_plan* p, double alpha) {
                                             alpha, nullptr);
     if (p->kind != POND_INPUT_COMPLEX)
         return launch_real_build_table(p->rtab, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->bw, lsb, alpha, nullptr);
+    if (p->log2m2 > 0)
+        return launch_build_split_chirp(p->chirp_split, f16_arith(p->precision), p->log2n1, p->log2n2, p->chirp_a,
+                                        p->f0, p->df, alpha, nullptr);
     if (f16_arith(p->precision))
         return launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
     return launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
@@ -383,7 +438,7 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     if (!(bw_mhz > 0) || !(f0_mhz - bw_mhz / 2 > 0) || !(dm >= 0)) return nullptr;
     if (nfft <= 0 || (nfft & (nfft - 1)) != 0) return nullptr;
     const int log2n = ilog2(nfft);
-    if (log2n < kMinLog2N || log2n > kMaxLog2N) return nullptr;
+    if (log2n < kMinLog2N || log2n > (kind == POND_INPUT_COMPLEX ? kMaxLog2N : kMaxLog2NReal)) return nullptr;
     if (nbins < 1 || nbins > 65536) return nullptr;
     if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU && precision != POND_HALF)
         return nullptr;
@@ -441,10 +496,24 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     chk(hipMalloc(reinterpret_cast<void**>(&p->tail[0]), (size_t)nfft * p->bpe));
     chk(hipMalloc(reinterpret_cast<void**>(&p->tail[1]), (size_t)nfft * p->bpe));
     const int64_t n1 = (int64_t)1 << p->log2n1, n2 = (int64_t)1 << p->log2n2;
-    chk(hipMalloc(reinterpret_cast<void**>(&p->tw1), (size_t)n1 * sizeof(float2)));
+    // rows longer than one workgroup transforms: the split middle pass
+    p->log2m2 = p->log2n1 > kMaxLog2RowN1 ? p->log2n1 - kSplitLog2M1 : 0;
+    const int64_t row = p->log2m2 ? (int64_t)1 << kSplitLog2M1 : n1;  // K2's row length
+    chk(hipMalloc(reinterpret_cast<void**>(&p->tw1), (size_t)row * sizeof(float2)));
     chk(hipMalloc(reinterpret_cast<void**>(&p->tw2), (size_t)n2 * sizeof(float2)));
-    if (e == hipSuccess) chk(launch_stage_twiddles(p->tw1, n1, nullptr));
+    if (e == hipSuccess) chk(launch_stage_twiddles(p->tw1, row, nullptr));
     if (e == hipSuccess) chk(launch_stage_twiddles(p->tw2, n2, nullptr));
+    if (p->log2m2) {
+        p->log2s = (log2n + 1) / 2;
+        const int64_t nlo = (int64_t)1 << p->log2s, nhi = nfft >> p->log2s;
+        chk(hipMalloc(reinterpret_cast<void**>(&p->tw_n1), (size_t)n1 * sizeof(float2)));
+        chk(hipMalloc(reinterpret_cast<void**>(&p->tw_hi), (size_t)nhi * sizeof(float2)));
+        chk(hipMalloc(reinterpret_cast<void**>(&p->tw_lo), (size_t)nlo * sizeof(float2)));
+        chk(hipMalloc(&p->chirp_split, (size_t)nfft * (f16_arith(precision) ? 4 : 8)));
+        if (e == hipSuccess) chk(launch_stage_twiddles(p->tw_n1, n1, nullptr));
+        if (e == hipSuccess) chk(launch_stage_twiddles(p->tw_hi, nhi, nullptr));
+        if (e == hipSuccess) chk(launch_partial_twiddles(p->tw_lo, nlo, nfft, nullptr));
+    }
     if (kind != POND_INPUT_COMPLEX) {
         p->real_fused = p->log2n1 <= kRealPairMaxLog2N1;
         chk(hipMalloc(reinterpret_cast<void**>(&p->rtab), (size_t)(nfft + 1) * sizeof(float4)));
@@ -455,6 +524,8 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
             if (e == hipSuccess)
                 chk(launch_k2_build_split_tables(p->tw4, nullptr, p->log2n1, p->log2n2, 0.0, p->f0, p->df, nullptr));
         }
+    } else if (p->log2m2) {
+        // chirp_split, above
     } else if (f16_arith(precision)) {
         chk(hipMalloc(&p->htable, (size_t)nfft * 8));
     } else {
@@ -476,14 +547,8 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
         chk(half_power_gain(
             cal,
             [&](int nb, const void** res) {
-                K2Args a2{};
-                a2.work = p->work;
-                a2.nblocks = nb;
-                a2.log2n2 = p->log2n2;
-                a2.tw1 = p->tw1;
-                a2.htable = p->htable;
                 *res = p->work;
-                return launch_k2(precision, kRowFull, p->log2n1, a2, nullptr);
+                return run_middle(p, nb, nullptr);
             },
             &g));
         p->half_gain = g;
@@ -871,7 +936,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
                 return r;
             });
         } else {
-            e = timed(1, nb, [&] { return launch_k2(p->precision, kRowFull, p->log2n1, a2, stream); });
+            e = timed(1, nb, [&] { return run_middle(p, (int)nb, stream); });
         }
         if (e != hipSuccess) return fail(e);
 

@@ -107,11 +107,11 @@ __global__ void __launch_bounds__(256) copy_u128(u32x4* __restrict__ dst, const 
     }
 }
 
-// Stage twiddles of a length-n transform: w[t] = exp(-2 pi i t / n),
-// float64 sine and cosine rounded to float32.
-__global__ void __launch_bounds__(256) stage_twiddles(float2* w, int64_t n) {
+// Stage twiddles of a length-n transform: w[t] = exp(-2 pi i t / n) for
+// t < count, float64 sine and cosine rounded to float32.
+__global__ void __launch_bounds__(256) stage_twiddles(float2* w, int64_t count, int64_t n) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
+    if (t >= count) return;
     double sn, cs;
     sincospi(2.0 * (double)t / (double)n, &sn, &cs);
     w[t] = make_float2((float)cs, (float)-sn);
@@ -145,9 +145,12 @@ hipError_t launch_copy_u128(void* dst, const void* src, int64_t n16, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_stage_twiddles(float2* w, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(stage_twiddles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, n);
+hipError_t launch_stage_twiddles(float2* w, int64_t n, hipStream_t s) { return launch_partial_twiddles(w, n, n, s); }
+
+hipError_t launch_partial_twiddles(float2* w, int64_t count, int64_t n, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (count > n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stage_twiddles, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, w, count, n);
     return hipGetLastError();
 }
 

@@ -41,7 +41,12 @@ struct K1Args {
 // FFT, conjugate twiddle.
 // kRowInvPlain: kRowInv with no filter (float32 arithmetic forms; the real
 // input path's longest rows, filtered by real_split before).
-enum RowMode { kRowFull = 0, kRowFwd = 1, kRowInv = 2, kRowInvPlain = 3 };
+// kRowChirp: forward row FFT, chirp, inverse row FFT, no twiddles (the
+// sub-rows of the split middle pass, rows of 2^kSplitLog2M1; chirp table in
+// their order).
+enum RowMode { kRowFull = 0, kRowFwd = 1, kRowInv = 2, kRowInvPlain = 3, kRowChirp = 4 };
+constexpr int kMaxLog2RowN1 = 14;  // longest row one workgroup transforms in LDS
+constexpr int kSplitLog2M1 = 13;   // sub-row length of the split middle pass
 
 struct K2Args {
     void* work;             // rows, in place (kRowFull, kRowFwd)
@@ -52,12 +57,40 @@ struct K2Args {
     const float2* tw1;      // exp(-2 pi i t / n1), t < n1
     const float4* table;    // kRowFull: [n2][n1] four-step twiddle (x, y), inverse ISM response (z, w)
     const float2* tw4;      // kRowFwd, kRowInv: [n2][n1] four-step twiddle
-    const float2* chirp;    // kRowInv: [n2][n1] inverse ISM response of one trial
+    const float2* chirp;    // kRowInv: [n2][n1] inverse ISM response of one trial; kRowChirp: split table
     float scale;            // power-of-two scale applied on output (float32 arithmetic)
     const void* htable;     // packed float16, kRowFull: [n2][n1] 4 halves (twiddle / 16, chirp * 2^-rem)
     const void* htw4;       // packed float16, split modes: [n2][n1] twiddle / 16
-    const void* hchirp;     // packed float16, kRowInv: [n2][n1] chirp of one trial
+    const void* hchirp;     // packed float16, kRowInv: [n2][n1] chirp of one trial; kRowChirp: split table
 };
+
+// Split middle pass, for rows longer than one workgroup's LDS holds (n1 =
+// m2 * m1, m1 = 2^kSplitLog2M1, m2 = 2..16): the row transform of length n1
+// is itself done in four steps.  Forward: for each row k2 and column c < m1,
+// the m2 values at c + m1 i are multiplied by the block twiddle
+// exp(-2 pi i k2 (c + m1 i) / N), transformed (length m2), multiplied by
+// exp(-2 pi i c k / n1) and stored at c + m1 k (sub-row k).  Inverse: the
+// same steps conjugated, in reverse order.  Float32 arithmetic for every
+// storage type.
+struct SplitColArgs {
+    void* work;             // [nblocks][n2][n1], in place
+    int32_t nblocks;
+    int32_t log2n1, log2n2;
+    const float2* tw_n1;    // exp(-2 pi i t / n1), t < n1
+    const float2* tw_hi;    // exp(-2 pi i t 2^log2s / N), t < N / 2^log2s
+    const float2* tw_lo;    // exp(-2 pi i t / N), t < 2^log2s
+    int32_t log2s;
+    float scale;            // applied to every output
+};
+hipError_t launch_split_cols(int prec, bool inverse, const SplitColArgs& a, hipStream_t s);
+// Chirp tables of the split middle pass, in sub-row order: entry (k2 m2 + k)
+// m1 + c' holds the inverse ISM response at frequency k2 + n2 (k + m2 c').
+// Float32 (float2) or packed float16 (times 2^-half_row_rem(kSplitLog2M1)).
+hipError_t launch_build_split_chirp(void* tab, bool f16, int log2n1, int log2n2, double chirp_a, double f0, double df,
+                                    double taper, hipStream_t s);
+// w[t] = exp(-2 pi i t / n) for t < count (count <= n), float64 sine/cosine
+// rounded to float32.
+hipError_t launch_partial_twiddles(float2* w, int64_t count, int64_t n, hipStream_t s);
 
 // K3: inverse column FFTs, detection, decimation, fold partials.
 struct K3Args {

@@ -50,6 +50,10 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 //   MODE kRowInv:  spectrum (in) times one trial's chirp (float2 table),
 //                  inverse FFT, conjugate twiddle, to `out`.
 //   MODE kRowInvPlain: kRowInv without the chirp (float32 arithmetic only).
+//   MODE kRowChirp: forward FFT, chirp (float2 or float16 table in the rows'
+//                  order), inverse FFT, in place, no twiddles (the sub-rows
+//                  of the split middle pass; the float16 forms' input already
+//                  carries the first stage's 1/16).
 // F16: packed float16 arithmetic on float16 storage with float16 tables
 // (kRowFull: 4 halves per entry, twiddle/16 and chirp*2^-kHalfRem; split
 // modes: twiddle/16 and chirp).  The forward transform is normalised stage
@@ -59,7 +63,7 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 // sums on the matrix cores (fft_mx), inputs loaded in their layout.
 template <int LOG2N1, class T, int MODE, bool F16, bool MXF = false>
 __global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS)
-    __attribute__((amdgpu_waves_per_eu(MXF && MODE == kRowFull && LOG2N1 >= 13 ? 8 : 4)))
+    __attribute__((amdgpu_waves_per_eu(MXF && (MODE == kRowFull || MODE == kRowChirp) && LOG2N1 >= 13 ? 8 : 4)))
 k2_row(K2Args a) {
     using Sh = K2Shape<LOG2N1>;
     using V = std::conditional_t<F16, h2, float2>;
@@ -119,6 +123,7 @@ k2_row(K2Args a) {
             const uint32_t i = MX ? mxo + (uint32_t)(16 * (e >> 2) + (e & 3) * TPV) : to + TPV * e;
             const h2 x = ld_h2(at(src, i * (uint32_t)sizeof(T)));
             if constexpr (MODE == kRowInv) v[e] = cmul(x, *at(chirp, i * 4u));
+            else if constexpr (MODE == kRowChirp) v[e] = x;
             else v[e] = cmul(x, tw_at(i));
         }
         // kRowFull: the chirp of each element is fetched during the forward
@@ -127,14 +132,19 @@ k2_row(K2Args a) {
         auto fetch_chirp = [&] {
             const uint32_t t2 = opaque(toff);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) ch[e] = __builtin_bit_cast(h2, at(tab, (t2 + TPV * e) * 8u)->y);
+            for (int e = 0; e < 16; ++e) {
+                if constexpr (MODE == kRowChirp) ch[e] = *at(chirp, (t2 + TPV * e) * 4u);
+                else ch[e] = __builtin_bit_cast(h2, at(tab, (t2 + TPV * e) * 8u)->y);
+            }
         };
         if constexpr (MX) {
             // first LDS use of the row: no barrier before the first stores
-            if constexpr (MODE == kRowFull) fft_mx<LOG2N1, -1, true, false, false>(v, j, lrow.base, ttab, fetch_chirp);
+            if constexpr (MODE == kRowFull || MODE == kRowChirp)
+                fft_mx<LOG2N1, -1, true, false, false>(v, j, lrow.base, ttab, fetch_chirp);
             else if constexpr (MODE != kRowInv) fft_mx<LOG2N1, -1, true, false, false>(v, j, lrow.base, ttab);
         } else {
-            if constexpr (MODE == kRowFull) fft_wg<LOG2N1, -1, true, 1>(v, j, tb, lrow, ttab, fetch_chirp);
+            if constexpr (MODE == kRowFull || MODE == kRowChirp)
+                fft_wg<LOG2N1, -1, true, 1>(v, j, tb, lrow, ttab, fetch_chirp);
             else if constexpr (MODE != kRowInv) fft_wg<LOG2N1, -1, true, 1>(v, j, tb, lrow, ttab);
         }
         if constexpr (MODE == kRowFwd) {
@@ -146,9 +156,20 @@ k2_row(K2Args a) {
             }
             return;
         }
-        if constexpr (MODE == kRowFull) {
+        if constexpr (MODE == kRowFull || MODE == kRowChirp) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], ch[e]);
+        }
+        if constexpr (MODE == kRowChirp) {
+            if constexpr (MX) fft_mx<LOG2N1, +1, false, false, true, true>(v, j, lrow.base, ttab);
+            else fft_wg<LOG2N1, +1, false, 1>(v, j, tb, lrow, ttab);
+            asm volatile("" ::: "memory");
+            to = opaque(toff);
+            if (valid) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) st_h2(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), v[e]);
+            }
+            return;
         }
         // the output twiddles are fetched during the inverse transform's
         // last exchange (rather than one dependent load per store)
@@ -188,7 +209,7 @@ k2_row(K2Args a) {
             } else if constexpr (MODE == kRowInv) {
                 v[e] = cmul(x, *at(chirp, (to + TPV * e) * 8u));
             } else {
-                v[e] = x;  // kRowInvPlain: the filter was applied before (real input path)
+                v[e] = x;  // kRowInvPlain: the filter was applied before (real input path); kRowChirp
             }
         }
         // kRowFull: the chirp is fetched again (from L2) during the forward
@@ -198,11 +219,15 @@ k2_row(K2Args a) {
             const uint32_t t2 = opaque(toff);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const float4 t = *at(tab, (t2 + TPV * e) * 16u);
-                ch[e] = make_float2(t.z, t.w);
+                if constexpr (MODE == kRowChirp) {
+                    ch[e] = *at(chirp, (t2 + TPV * e) * 8u);
+                } else {
+                    const float4 t = *at(tab, (t2 + TPV * e) * 16u);
+                    ch[e] = make_float2(t.z, t.w);
+                }
             }
         };
-        if constexpr (MODE == kRowFull) {
+        if constexpr (MODE == kRowFull || MODE == kRowChirp) {
             fft_wg<LOG2N1, -1>(v, j, tb, lrow, nullptr, fetch_chirp);
 #pragma unroll
             for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], ch[e]);
@@ -210,6 +235,17 @@ k2_row(K2Args a) {
             fft_wg<LOG2N1, -1>(v, j, tb, lrow);
         }
         if constexpr (MODE == kRowFwd) {
+            if (valid) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+            }
+            return;
+        }
+        if constexpr (MODE == kRowChirp) {
+            fft_wg<LOG2N1, +1>(v, j, tb, lrow);
+            asm volatile("" ::: "memory");
+            to = opaque(toff);
             if (valid) {
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
@@ -368,6 +404,15 @@ hipError_t launch_k2(int prec, int mode, int log2n1, const K2Args& a, hipStream_
         case kRowFull: return k2_prec<kRowFull>(prec, log2n1, a, s);
         case kRowFwd: return k2_prec<kRowFwd>(prec, log2n1, a, s);
         case kRowInv: return k2_prec<kRowInv>(prec, log2n1, a, s);
+        case kRowChirp:
+            // sub-rows of the split middle pass only
+            if (log2n1 != kSplitLog2M1) return hipErrorInvalidValue;
+            switch (prec) {
+                case kFp32: return k2_one<float2, kRowChirp, false, false, kSplitLog2M1>(a, s);
+                case kHalf: return k2_one<__half2, kRowChirp, true, false, kSplitLog2M1>(a, s);
+                case kMixed: return k2_one<__half2, kRowChirp, true, true, kSplitLog2M1>(a, s);
+                default: return k2_one<__half2, kRowChirp, false, false, kSplitLog2M1>(a, s);
+            }
         case kRowInvPlain:
             // float32 arithmetic forms only (the real input path)
             if (prec == kFp32) return k2_dispatch<float2, kRowInvPlain, false>(log2n1, a, s);

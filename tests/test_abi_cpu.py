@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.parametrize("args", [
     (326.5, 16.0, 1.0, (1 << 18) + 1, 256, 0.0891),   # nfft not a power of two
     (326.5, 16.0, 1.0, 1 << 9, 256, 0.0891),          # nfft below 2^10
-    (326.5, 16.0, 1.0, 1 << 25, 256, 0.0891),         # nfft above 2^24
+    (326.5, 16.0, 1.0, 1 << 28, 256, 0.0891),         # nfft above 2^27
     (326.5, 16.0, -1.0, 1 << 18, 256, 0.0891),        # negative DM
     (326.5, 16.0, float("nan"), 1 << 18, 256, 0.0891),
     (326.5, 0.0, 1.0, 1 << 18, 256, 0.0891),          # zero bandwidth
