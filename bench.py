@@ -136,8 +136,12 @@ def run_form(precision, x, steps, warmup, graph=False):
     import torch
     import paper_1503_01405_amd as P
 
-    plan = P.Plan(F0, BW, DM, NFFT, NBINS, PERIOD, precision=precision, subint_nsamp=SUBINT, decim=DECIM)
+    # blocks per launch chosen by the library's autotuner at plan creation
+    # (outside the timed region; POND_AUTOTUNE_CACHE, if set, holds it)
+    plan = P.Plan(F0, BW, DM, NFFT, NBINS, PERIOD, precision=precision, subint_nsamp=SUBINT, decim=DECIM,
+                  max_batch=P.POND_BATCH_AUTOTUNE)
     info = plan.info()
+    tune = plan.autotune()
     nsamp = x.numel() // 2
     nprof, nout = P.pond_plan_expect(plan.handle, nsamp, SUBINT)
     prof = torch.empty((nprof + 1, NBINS), dtype=torch.float32, device=x.device)
@@ -176,7 +180,7 @@ def run_form(precision, x, steps, warmup, graph=False):
         step()
     kt = P.pond_plan_kernel_times(plan.handle)
     P.pond_plan_set_timing(plan.handle, False)
-    res = dict(ms_per_step=ms, ms_events=ev_ms, ms_wall=wall, outputs=nout, kernels=kt, info=info)
+    res = dict(ms_per_step=ms, ms_events=ev_ms, ms_wall=wall, outputs=nout, kernels=kt, info=info, tune=tune)
     if graph:
         # the same step captured once into a HIP graph and replayed
         g = torch.cuda.CUDAGraph()
@@ -781,8 +785,13 @@ def main():
     forms_out = {}
     for f, r in res.items():
         v = r["outputs"] / (r["ms_per_step"] / 1e3) / 1e6
+        tu = r["tune"]
         forms_out[f] = dict(value=round(v, 2), xrealtime=round(v / 16.0, 1), ms_per_step=round(r["ms_per_step"], 3),
-                            kernel_ms_per_step={k: round(kv[0] / args.steps, 4) for k, kv in r["kernels"].items()})
+                            kernel_ms_per_step={k: round(kv[0] / args.steps, 4) for k, kv in r["kernels"].items()},
+                            autotune=dict(batch=tu["batch"], ms_per_block=round(tu["ms_per_block"], 4),
+                                          default_batch=tu["default_batch"],
+                                          default_ms_per_block=round(tu["default_ms_per_block"], 4),
+                                          from_cache=tu["from_cache"]))
         if "graph_ms_per_step" in r:
             forms_out[f]["graph_ms_per_step"] = round(r["graph_ms_per_step"], 3)
 

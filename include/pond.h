@@ -180,12 +180,34 @@ pond_plan* pond_plan_create(double f0_mhz, double bw_mhz, double dm,
 
 /*
  * As pond_plan_create with a precision form (POND_FP32, POND_MIXED,
- * POND_MIXED_VALU or POND_HALF) and a cap on overlap-save blocks per launch (max_batch
- * <= 0 picks a default).
+ * POND_MIXED_VALU or POND_HALF) and a cap on overlap-save blocks per launch:
+ * max_batch > 0 is used as given; POND_BATCH_AUTOTUNE has the plan time its
+ * own launch sequence (K1, middle pass, K3, fold) on pseudo-random int8
+ * input at 1, 2, 3, 4, 6, 8, 12, 16, 24 and 32 blocks per launch (those
+ * whose work area fits in min(4 GiB, a third of the free device memory),
+ * plus the default) during creation and
+ * keep the fastest per block, a larger launch winning only by more than 2%;
+ * other values <= 0 pick the default (2^29 bytes of work area, 1 .. 16
+ * blocks).  With the environment variable POND_AUTOTUNE_CACHE naming a
+ * text file, a choice already measured for the same device, nfft, form,
+ * input kind and histogram placement is read from it instead, and new
+ * choices are appended (one line each; the last matching line wins).
  */
+#define POND_BATCH_AUTOTUNE (-1)
 pond_plan* pond_plan_create_ex(double f0_mhz, double bw_mhz, double dm,
                                int64_t nfft, int32_t nbins, double period_s,
                                int32_t precision, int32_t max_batch);
+
+/*
+ * The autotuner's result for a plan created with POND_BATCH_AUTOTUNE: the
+ * blocks per launch it chose and their measured time per block (ms), the
+ * default rule's batch and its measured time per block, and whether the
+ * choice came from the cache (1; its times are those of the measuring run).
+ * POND_EINVAL for a null plan or one created without the tuner.
+ */
+int32_t pond_plan_autotune(const pond_plan* p, int32_t* batch, double* ms_per_block,
+                           int32_t* default_batch, double* default_ms_per_block,
+                           int32_t* from_cache);
 
 /* Status of the last pond_plan_create / _ex call on this thread. */
 int32_t pond_create_status(void);
@@ -346,8 +368,13 @@ int32_t pond_real_expect(const pond_plan* p, int64_t nsamp, int64_t subint_nsamp
  * hop = N_t / 2 and therefore one forward transform per block; each keeps
  * its own n_front_t.  dms (host, ntrials values >= 0), nfft_min/nfft_max
  * powers of two in [2^10, 2^24]; every trial needs discard_t <= nfft_max/2.
- * precision as for pond_plan_create_ex.  Returns NULL on invalid arguments
- * or allocation/device failure.
+ * precision as for pond_plan_create_ex.  Device memory per length group:
+ * the blocks of one launch twice (spectrum, one trial's output), the
+ * four-step twiddles and one float64 table of the chirp's turns per unit DM
+ * of each bin, shared by the group's trials (a trial's chirp is
+ * exp(-2 pi i frac(DM g_k)), formed as the inverse rows read the spectrum;
+ * its sine and cosine in float32 after the float64 reduction).  Returns
+ * NULL on invalid arguments or allocation/device failure.
  */
 typedef struct pond_search pond_search;
 pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms, int32_t ntrials,

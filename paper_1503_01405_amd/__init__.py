@@ -17,4 +17,5 @@ from .pond import (POND_EBUSY, POND_EDEVICE, POND_EINVAL, POND_ENOMEM, FORMS, PO
                    POND_INPUT_COMPLEX, POND_INPUT_REAL_LSB, POND_INPUT_REAL_USB, pond_real_plan_create,
                    pond_real_dedisperse, pond_real_expect, pond_copy_device, pond_geometry,
                    pond_server_stream_state, POND_ECANCELED, POND_TICKET_ADMITTED, POND_STREAM_WAITING,
-                   POND_STREAM_OPEN, POND_STREAM_CLOSED, pond_dedisperse_segment_noalloc)
+                   POND_STREAM_OPEN, POND_STREAM_CLOSED, pond_dedisperse_segment_noalloc,
+                   POND_BATCH_AUTOTUNE, pond_plan_autotune)

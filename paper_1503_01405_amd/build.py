@@ -21,9 +21,10 @@ LIB = os.path.join(PKG, "libpond.so")
 
 KERNEL_SOURCES = ["pond_k1.hip", "pond_k2.hip", "pond_k3.hip", "pond_fold.hip", "pond_real.hip",
                   "pond_aid_kernels.hip", "pond_split.hip"]
-HOST_SOURCES = ["pond_api.cpp", "pond_search.cpp", "pond_serve.cpp", "pond_aid.cpp", "pond_static.cpp"]
+HOST_SOURCES = ["pond_api.cpp", "pond_search.cpp", "pond_serve.cpp", "pond_aid.cpp", "pond_static.cpp",
+                "pond_tune.cpp"]
 SOURCES = KERNEL_SOURCES + HOST_SOURCES
-HEADERS = ["pond_fft.hpp", "pond_device.hpp", "pond_internal.hpp"]
+HEADERS = ["pond_fft.hpp", "pond_device.hpp", "pond_internal.hpp", "pond_tune.hpp"]
 
 # -ffp-contract=off: no implicit fused multiply-adds, so the float64 fold
 # phase and plan geometry round exactly as written (fmaf is used explicitly

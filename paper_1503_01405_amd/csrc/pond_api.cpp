@@ -12,6 +12,7 @@
 
 #include "../../include/pond.h"
 #include "pond_internal.hpp"
+#include "pond_tune.hpp"
 
 using namespace pond;
 
@@ -107,6 +108,8 @@ struct pond_plan {
     float2* tw_lo = nullptr;
     void* chirp_split = nullptr;
     float pscale = 1.0f;        // detected-power scale applied in K3
+    bool tuned = false;         // max_batch chosen by the autotuner
+    TuneResult tune;
     // Packed float16: the middle pass leaves 1/16 of the value (its twiddle
     // table carries the first stage's 1/16), so the power scale is 256
     // divided by half_gain, the measured power gain of the float16
@@ -210,9 +213,9 @@ void free_plan_memory(pond_plan* p) {
 // output keeps 1/16 of the value (K2 multiplies by the twiddle / 16; the
 // split pass's inverse columns scale by 1/16; the forward columns carry the
 // first row stage's 1/16, which K2 otherwise takes from its table).
-hipError_t run_middle(const pond_plan* p, int nb, hipStream_t stream) {
+hipError_t run_middle(const pond_plan* p, void* work, int nb, hipStream_t stream) {
     K2Args a2{};
-    a2.work = p->work;
+    a2.work = work;
     a2.nblocks = nb;
     a2.tw1 = p->tw1;
     if (p->log2m2 == 0) {
@@ -223,7 +226,7 @@ hipError_t run_middle(const pond_plan* p, int nb, hipStream_t stream) {
         return launch_k2(p->precision, kRowFull, p->log2n1, a2, stream);
     }
     const bool h = f16_arith(p->precision);
-    SplitColArgs sc{p->work, nb, p->log2n1, p->log2n2, p->tw_n1, p->tw_hi, p->tw_lo, p->log2s, 1.0f};
+    SplitColArgs sc{work, nb, p->log2n1, p->log2n2, p->tw_n1, p->tw_hi, p->tw_lo, p->log2s, 1.0f};
     sc.scale = std::ldexp(1.0f, -p->log2m2 - (h ? 4 : 0));
     hipError_t e = launch_split_cols(p->precision, false, sc, stream);
     if (e != hipSuccess) return e;
@@ -235,6 +238,100 @@ hipError_t run_middle(const pond_plan* p, int nb, hipStream_t stream) {
     if (e != hipSuccess) return e;
     sc.scale = h ? 1.0f / 16.0f : 1.0f;
     return launch_split_cols(p->precision, true, sc, stream);
+}
+
+// One launch sequence of a complex-input plan (K1, middle pass, K3, fold
+// reduction) over blocks 0 .. nb-1 of `in`, with one open sub-integration
+// and no series: what the autotuner times.  Null stream.
+hipError_t run_blocks(pond_plan* p, void* work, const int8_t* in, int nb) {
+    K1Args a1{};
+    a1.tail = in;
+    a1.tail_start = 0;
+    a1.in = in;
+    a1.in_start = 0;
+    a1.hop = p->hop;
+    a1.block0 = 0;
+    a1.nblocks = nb;
+    a1.log2n1 = p->log2n1;
+    a1.work = work;
+    a1.tw2 = p->tw2;
+    a1.scale = std::ldexp(1.0f, -p->log2n2);
+    hipError_t e = launch_k1(p->precision, p->log2n2, a1, nullptr);
+    if (e == hipSuccess) e = run_middle(p, work, nb, nullptr);
+    if (e != hipSuccess) return e;
+    const bool global_mode = p->nbins > p->hist_cap;
+    K3Args a3{};
+    a3.work = work;
+    a3.nblocks = nb;
+    a3.log2n1 = p->log2n1;
+    a3.hop = p->hop;
+    a3.n_front = p->n_front;
+    a3.block0 = 0;
+    a3.tw2 = p->tw2;
+    a3.scale = 1.0f;
+    a3.pscale = p->pscale;
+    a3.series = nullptr;
+    a3.decim = 16;
+    a3.nbins = p->nbins;
+    a3.inv_pfs = p->inv_pfs;
+    a3.subint = 0;
+    a3.s_base = 0;
+    a3.entries = p->nbins;
+    a3.global_mode = global_mode ? 1 : 0;
+    a3.part_sum = p->part_sum;
+    a3.part_cnt = p->part_cnt;
+    a3.acc_sum = p->acc_sum;
+    a3.acc_cnt = p->acc_cnt;
+    a3.acc_s0 = 0;
+    a3.status = reinterpret_cast<uint32_t*>(p->status);
+    const size_t dyn = global_mode ? 0 : (size_t)p->nbins * 12;
+    const int grid = k3_grid(p->log2n2, p->precision, dyn, (int64_t)nb << (p->log2n1 - 4), p->nbins, global_mode);
+    e = launch_k3(p->precision, p->log2n2, a3, grid, dyn, nullptr);
+    if (e == hipSuccess && !global_mode)
+        e = launch_fold_reduce(p->part_sum, p->part_cnt, grid, p->nbins, p->acc_sum, p->acc_cnt, 0, nullptr);
+    return e;
+}
+
+int default_max_batch(int64_t nfft, int32_t precision, int32_t max_batch);
+
+// Autotuned blocks per launch of a complex-input plan (tables, twiddles and
+// fold buffers in place, p->work not yet allocated): candidates whose work
+// area fits in min(4 GiB, a third of the free device memory), timed on a
+// pseudo-random int8 stream.  Leaves the fold buffers dirty (the caller
+// clears them).
+hipError_t tune_plan(pond_plan* p) {
+    size_t free_b = 0, total_b = 0;
+    hipError_t e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) return e;
+    const int64_t block_bytes = p->nfft * (int64_t)p->elem;
+    const int64_t cap = std::min<int64_t>((int64_t)4 << 30, (int64_t)(free_b / 3));
+    const int dflt = default_max_batch(p->nfft, p->precision, 0);
+    const std::vector<int> cand = batch_candidates(block_bytes, cap, dflt);
+    const int nb_max = cand.back();
+    void* work = nullptr;
+    int8_t* in = nullptr;
+    const int64_t in_bytes = ((int64_t)(nb_max - 1) * p->hop + p->nfft) * p->bpe;
+    e = hipMalloc(&work, (size_t)nb_max * block_bytes);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&in), (size_t)((in_bytes + 7) & ~7ll));
+    if (e == hipSuccess)
+        e = launch_fill_noise_u64(reinterpret_cast<uint64_t*>(in), (in_bytes + 7) / 8, 0x706f6e64ull, nullptr);
+    if (e == hipSuccess) {
+        TuneKey key;
+        key.path = "dedisperse";
+        key.nfft = p->nfft;
+        key.precision = p->precision;
+        key.kind = p->kind;
+        key.global_hist = p->nbins > p->hist_cap;
+        e = autotune_batch(key, cand, dflt, [&](int nb) { return run_blocks(p, work, in, nb); }, &p->tune);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (work) (void)hipFree(work);
+    if (in) (void)hipFree(in);
+    if (e == hipSuccess) {
+        p->max_batch = p->tune.batch;
+        p->tuned = true;
+    }
+    return e;
 }
 
 int default_max_batch(int64_t nfft, int32_t precision, int32_t max_batch) {
@@ -484,6 +581,7 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     p->nbins = nbins;
     p->precision = precision;
     p->elem = precision == POND_FP32 ? 8 : 4;
+    const bool autotune = max_batch == POND_BATCH_AUTOTUNE;
     p->max_batch = max_batch = default_max_batch(nfft, precision, max_batch);
 
     p->hist_cap = hist_capacity(p->log2n2, p->precision);
@@ -492,7 +590,6 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     auto chk = [&](hipError_t x) {
         if (e == hipSuccess) e = x;
     };
-    chk(hipMalloc(&p->work, (size_t)max_batch * (size_t)nfft * p->elem));
     chk(hipMalloc(reinterpret_cast<void**>(&p->tail[0]), (size_t)nfft * p->bpe));
     chk(hipMalloc(reinterpret_cast<void**>(&p->tail[1]), (size_t)nfft * p->bpe));
     const int64_t n1 = (int64_t)1 << p->log2n1, n2 = (int64_t)1 << p->log2n2;
@@ -532,6 +629,15 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
         chk(hipMalloc(reinterpret_cast<void**>(&p->table), (size_t)nfft * sizeof(float4)));
     }
     if (e == hipSuccess) chk(build_filter(p, 0.0));
+    // Fold buffers before the tuner (its launches fold too), cleared below.
+    p->acc_slots = acc_slots > kDefaultAccSlots ? acc_slots : kDefaultAccSlots;
+    chk(hipMalloc(reinterpret_cast<void**>(&p->acc_sum), (size_t)p->acc_slots * nbins * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->acc_cnt), (size_t)p->acc_slots * nbins * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->part_sum), (size_t)kPartEntries * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->part_cnt), (size_t)kPartEntries * 4));
+    chk(hipMalloc(reinterpret_cast<void**>(&p->status), 8));
+    if (e == hipSuccess && autotune && kind == POND_INPUT_COMPLEX) chk(tune_plan(p));
+    chk(hipMalloc(&p->work, (size_t)p->max_batch * (size_t)nfft * p->elem));
     // Float16 arithmetic (packed float16 and matrix-core forms): the power
     // scale is 256 over the measured gain of the plan's float16 arithmetic
     // (the unit-taper table just built).
@@ -548,18 +654,12 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
             cal,
             [&](int nb, const void** res) {
                 *res = p->work;
-                return run_middle(p, nb, nullptr);
+                return run_middle(p, p->work, nb, nullptr);
             },
             &g));
         p->half_gain = g;
         p->pscale = (float)(256.0 / g);
     }
-    p->acc_slots = acc_slots > kDefaultAccSlots ? acc_slots : kDefaultAccSlots;
-    chk(hipMalloc(reinterpret_cast<void**>(&p->acc_sum), (size_t)p->acc_slots * nbins * 8));
-    chk(hipMalloc(reinterpret_cast<void**>(&p->acc_cnt), (size_t)p->acc_slots * nbins * 8));
-    chk(hipMalloc(reinterpret_cast<void**>(&p->part_sum), (size_t)kPartEntries * 8));
-    chk(hipMalloc(reinterpret_cast<void**>(&p->part_cnt), (size_t)kPartEntries * 4));
-    chk(hipMalloc(reinterpret_cast<void**>(&p->status), 8));
     if (e == hipSuccess) chk(hipMemset(p->acc_sum, 0, (size_t)p->acc_slots * nbins * 8));
     if (e == hipSuccess) chk(hipMemset(p->acc_cnt, 0, (size_t)p->acc_slots * nbins * 8));
     if (e == hipSuccess) chk(hipMemset(p->status, 0, 8));
@@ -636,6 +736,17 @@ int32_t pond_plan_set_taper(pond_plan* p, double alpha) {
         return POND_EDEVICE;
     }
     p->taper = alpha;
+    return POND_OK;
+}
+
+int32_t pond_plan_autotune(const pond_plan* p, int32_t* batch, double* ms_per_block, int32_t* default_batch,
+                           double* default_ms_per_block, int32_t* from_cache) {
+    if (!p || !p->tuned) return POND_EINVAL;
+    if (batch) *batch = p->tune.batch;
+    if (ms_per_block) *ms_per_block = p->tune.ms_per_block;
+    if (default_batch) *default_batch = p->tune.default_batch;
+    if (default_ms_per_block) *default_ms_per_block = p->tune.default_ms_per_block;
+    if (from_cache) *from_cache = p->tune.from_cache ? 1 : 0;
     return POND_OK;
 }
 
@@ -936,7 +1047,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
                 return r;
             });
         } else {
-            e = timed(1, nb, [&] { return run_middle(p, (int)nb, stream); });
+            e = timed(1, nb, [&] { return run_middle(p, p->work, (int)nb, stream); });
         }
         if (e != hipSuccess) return fail(e);
 

@@ -117,6 +117,17 @@ __global__ void __launch_bounds__(256) stage_twiddles(float2* w, int64_t count, 
     w[t] = make_float2((float)cs, (float)-sn);
 }
 
+// Pseudo-random bytes (splitmix64 of the word index and a seed, Steele,
+// Lea & Flood 2014): timing input for the autotuner, not part of the method.
+__global__ void __launch_bounds__(256) fill_noise_u64(uint64_t* p, int64_t n, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t x = seed + 0x9e3779b97f4a7c15ull * (uint64_t)(i + 1);
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    p[i] = x ^ (x >> 31);
+}
+
 __global__ void __launch_bounds__(256) zero_u64(uint64_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -151,6 +162,12 @@ hipError_t launch_partial_twiddles(float2* w, int64_t count, int64_t n, hipStrea
     if (count <= 0) return hipSuccess;
     if (count > n) return hipErrorInvalidValue;
     hipLaunchKernelGGL(stage_twiddles, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, w, count, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_noise_u64(uint64_t* p, int64_t n, uint64_t seed, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_noise_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, seed);
     return hipGetLastError();
 }
 

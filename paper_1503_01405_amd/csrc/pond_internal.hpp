@@ -57,11 +57,13 @@ struct K2Args {
     const float2* tw1;      // exp(-2 pi i t / n1), t < n1
     const float4* table;    // kRowFull: [n2][n1] four-step twiddle (x, y), inverse ISM response (z, w)
     const float2* tw4;      // kRowFwd, kRowInv: [n2][n1] four-step twiddle
-    const float2* chirp;    // kRowInv: [n2][n1] inverse ISM response of one trial; kRowChirp: split table
+    const float2* chirp;    // kRowChirp: split middle pass chirp (float32 forms)
     float scale;            // power-of-two scale applied on output (float32 arithmetic)
     const void* htable;     // packed float16, kRowFull: [n2][n1] 4 halves (twiddle / 16, chirp * 2^-rem)
     const void* htw4;       // packed float16, split modes: [n2][n1] twiddle / 16
-    const void* hchirp;     // packed float16, kRowInv: [n2][n1] chirp of one trial; kRowChirp: split table
+    const void* hchirp;     // packed float16, kRowChirp: split middle pass chirp
+    const double* geo;      // kRowInv: [n2][n1] turns per unit DM of each bin (shared by the trials)
+    double dm;              // kRowInv: the trial's DM (chirp exp(-2 pi i frac(dm geo)))
 };
 
 // Split middle pass, for rows longer than one workgroup's LDS holds (n1 =
@@ -182,6 +184,8 @@ hipError_t launch_fold_finalize(uint64_t* acc_sum, uint64_t* acc_cnt, int nbins,
                                 float* profiles, hipStream_t s);
 hipError_t launch_copy_u128(void* dst, const void* src, int64_t n16, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s);
+// n words of pseudo-random bits (splitmix64 of index and seed): timing input.
+hipError_t launch_fill_noise_u64(uint64_t* p, int64_t n, uint64_t seed, hipStream_t s);
 // w[t] = exp(-2 pi i t / n) for t < n, float64 sine/cosine rounded to float32.
 hipError_t launch_stage_twiddles(float2* w, int64_t n, hipStream_t s);
 hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
@@ -193,6 +197,10 @@ hipError_t launch_k2_build_table_h(void* tab, int log2n1, int log2n2, double chi
                                    double taper, hipStream_t s);
 hipError_t launch_k2_build_split_tables_h(void* tw, void* chirp, int log2n1, int log2n2, double chirp_a, double f0,
                                           double df, hipStream_t s);
+// geo[i] = f^2 / (2.41e-10 f0^2 (f0 + f)), the chirp's turns per unit DM at
+// the bin f = k df of entry i = k2 n1 + k1 (k = k2 + n2 k1, k >= n/2 taken
+// as k - n), float64.
+hipError_t launch_build_dm_geometry(double* geo, int log2n1, int log2n2, double f0, double df, hipStream_t s);
 // Packed-float16 row transforms apply 2^-half_row_rem(log2n1) of their
 // 1/n1 normalisation after the stages (the rest is spread over them).
 constexpr int half_row_rem(int log2n1) {

@@ -47,8 +47,10 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 //                  twiddle, in place (float4 table: twiddle, chirp).
 //   MODE kRowFwd:  twiddle and forward FFT only, in place: leaves the block's
 //                  spectrum, row k2 holding bins k2 + n2 k1 (float2 twiddle table).
-//   MODE kRowInv:  spectrum (in) times one trial's chirp (float2 table),
-//                  inverse FFT, conjugate twiddle, to `out`.
+//   MODE kRowInv:  spectrum (in) times one trial's chirp, inverse FFT,
+//                  conjugate twiddle, to `out`; the chirp is formed from the
+//                  trial's DM and the shared float64 table of turns per unit
+//                  DM (dm_chirp).
 //   MODE kRowInvPlain: kRowInv without the chirp (float32 arithmetic only).
 //   MODE kRowChirp: forward FFT, chirp (float2 or float16 table in the rows'
 //                  order), inverse FFT, in place, no twiddles (the sub-rows
@@ -61,6 +63,17 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 // is the block's spectrum / n; the output is 1/16 of the float32 forms'.
 // MXF (with F16, rows of 2^10 and more): the radix-16 stages' butterfly
 // sums on the matrix cores (fft_mx), inputs loaded in their layout.
+// exp(-2 pi i turns) of one trial's chirp at a bin with turns = dm g (Eq.
+// (4) with the DM factored out): the product and the reduction mod 1 in
+// float64, the sine and cosine of the reduced phase in float32.
+__device__ __forceinline__ float2 dm_chirp(double dm, double g) {
+    const double turns = dm * g;
+    const float frac = (float)(turns - rint(turns));
+    float sn, cs;
+    sincospif(2.0f * frac, &sn, &cs);
+    return make_float2(cs, -sn);
+}
+
 template <int LOG2N1, class T, int MODE, bool F16, bool MXF = false>
 __global__ void __launch_bounds__(K2Shape<LOG2N1>::THREADS)
     __attribute__((amdgpu_waves_per_eu(MXF && (MODE == kRowFull || MODE == kRowChirp) && LOG2N1 >= 13 ? 8 : 4)))
@@ -110,6 +123,7 @@ k2_row(K2Args a) {
         const uint2* tab = reinterpret_cast<const uint2*>(a.htable) + ((int64_t)row0 << LOG2N1);
         const h2* tw4 = reinterpret_cast<const h2*>(a.htw4) + ((int64_t)row0 << LOG2N1);
         const h2* chirp = reinterpret_cast<const h2*>(a.hchirp) + ((int64_t)row0 << LOG2N1);
+        const double* geo = a.geo + ((int64_t)row0 << LOG2N1);
         auto tw_at = [&](uint32_t i) {
             if constexpr (MODE == kRowFull) return __builtin_bit_cast(h2, at(tab, i * 8u)->x);
             else return *at(tw4, i * 4u);
@@ -122,7 +136,7 @@ k2_row(K2Args a) {
         for (int e = 0; e < 16; ++e) {
             const uint32_t i = MX ? mxo + (uint32_t)(16 * (e >> 2) + (e & 3) * TPV) : to + TPV * e;
             const h2 x = ld_h2(at(src, i * (uint32_t)sizeof(T)));
-            if constexpr (MODE == kRowInv) v[e] = cmul(x, *at(chirp, i * 4u));
+            if constexpr (MODE == kRowInv) v[e] = cmul(x, to_h2(dm_chirp(a.dm, *at(geo, i * 8u))));
             else if constexpr (MODE == kRowChirp) v[e] = x;
             else v[e] = cmul(x, tw_at(i));
         }
@@ -196,6 +210,7 @@ k2_row(K2Args a) {
         const float4* tab = a.table + ((int64_t)row0 << LOG2N1);
         const float2* tw4 = a.tw4 + ((int64_t)row0 << LOG2N1);
         const float2* chirp = a.chirp + ((int64_t)row0 << LOG2N1);
+        const double* geo = a.geo + ((int64_t)row0 << LOG2N1);
         float2 v[16];
         uint32_t to = opaque(toff);
 #pragma unroll
@@ -207,7 +222,7 @@ k2_row(K2Args a) {
             } else if constexpr (MODE == kRowFwd) {
                 v[e] = cmul(x, *at(tw4, (to + TPV * e) * 8u));
             } else if constexpr (MODE == kRowInv) {
-                v[e] = cmul(x, *at(chirp, (to + TPV * e) * 8u));
+                v[e] = cmul(x, dm_chirp(a.dm, *at(geo, (to + TPV * e) * 8u)));
             } else {
                 v[e] = x;  // kRowInvPlain: the filter was applied before (real input path); kRowChirp
             }
@@ -324,6 +339,7 @@ __global__ void __launch_bounds__(256) k2_build_split_tables_h(h2* __restrict__ 
         sincospi(2.0 * (double)r / (double)n, &s, &c);
         tw[i] = f16_unit(c / 16.0, -s / 16.0, 1.0 / 16.0);
     }
+    if (!chirp) return;
     const int64_t k = k2 + (k1 << log2n2);
     const int64_t kk = k < (n >> 1) ? k : k - n;
     const double f = (double)kk * df;
@@ -420,6 +436,27 @@ hipError_t launch_k2(int prec, int mode, int log2n1, const K2Args& a, hipStream_
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
+}
+
+// Turns per unit DM of every bin, in the row layout (see the header).
+__global__ void __launch_bounds__(256) build_dm_geometry(double* __restrict__ geo, int log2n1, int log2n2, double f0,
+                                                         double df) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    if (i >= n) return;
+    const int64_t k2 = i >> log2n1;
+    const int64_t k1 = i & ((1ll << log2n1) - 1);
+    const int64_t k = k2 + (k1 << log2n2);
+    const int64_t kk = k < (n >> 1) ? k : k - n;
+    const double f = (double)kk * df;
+    geo[i] = (f * f) / (2.41e-10 * f0 * f0 * (f0 + f));
+}
+
+hipError_t launch_build_dm_geometry(double* geo, int log2n1, int log2n2, double f0, double df, hipStream_t s) {
+    const int64_t n = 1ll << (log2n1 + log2n2);
+    hipLaunchKernelGGL(build_dm_geometry, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, geo, log2n1, log2n2, f0,
+                       df);
+    return hipGetLastError();
 }
 
 hipError_t launch_k2_build_split_tables(float2* tw, float2* chirp, int log2n1, int log2n2, double chirp_a, double f0,

@@ -6,7 +6,9 @@
 // transform (int8 unpack + column FFTs + twiddle + row FFTs) runs once per
 // group.  Each trial then multiplies the stored spectrum by its own inverse
 // ISM response (Sec. 3.7, Eq. (4)), inverts the row and column transforms,
-// detects and folds into its own integer accumulators.
+// detects and folds into its own integer accumulators.  The response's
+// phase is DM times a per-bin geometry factor, so one float64 table of that
+// factor per group serves every trial (no per-trial tables).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,9 +35,8 @@ struct Group {
     float2* tw1 = nullptr;    // exp(-2 pi i t / n1)
     float2* tw2 = nullptr;    // exp(-2 pi i t / n2)
     float2* tw4 = nullptr;    // [n2][n1] four-step twiddle
-    std::vector<float2*> chirp;  // per trial of the group, [n2][n1] (float32 forms)
-    void* htw4 = nullptr;        // packed float16 form: [n2][n1] twiddle / 16
-    std::vector<void*> hchirp;   // packed float16 form: per trial, [n2][n1]
+    void* htw4 = nullptr;     // packed float16 form: [n2][n1] twiddle / 16
+    double* geo = nullptr;    // [n2][n1] chirp turns per unit DM, shared by the group's trials
     void* spec = nullptr;     // max_batch blocks of spectrum
     void* out = nullptr;      // max_batch blocks of one trial's row-inverse output
 };
@@ -70,13 +71,9 @@ namespace {
 
 void free_search(pond_search* s) {
     for (auto& g : s->groups) {
-        void* ptrs[] = {g.tw1, g.tw2, g.tw4, g.htw4, g.spec, g.out};
+        void* ptrs[] = {g.tw1, g.tw2, g.tw4, g.htw4, g.geo, g.spec, g.out};
         for (void* q : ptrs)
             if (q) (void)hipFree(q);
-        for (float2* c : g.chirp)
-            if (c) (void)hipFree(c);
-        for (void* c : g.hchirp)
-            if (c) (void)hipFree(c);
     }
     void* ptrs[] = {s->acc_sum, s->acc_cnt, s->part_sum, s->part_cnt, s->status};
     for (void* q : ptrs)
@@ -180,29 +177,22 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
         if (e == hipSuccess) chk(launch_stage_twiddles(g.tw2, n2, nullptr));
         chk(hipMalloc(&g.spec, (size_t)g.max_batch * g.nfft * s->elem));
         chk(hipMalloc(&g.out, (size_t)g.max_batch * g.nfft * s->elem));
+        // One table per group for every trial: the four-step twiddle, and the
+        // chirp's turns per unit DM of each bin (each trial's chirp is formed
+        // from it and its DM in the inverse rows).
         const bool half = f16_arith(precision);
+        const double df = bw_mhz / (double)g.nfft;
         if (half) chk(hipMalloc(&g.htw4, g.nfft * 4));
         else chk(hipMalloc(reinterpret_cast<void**>(&g.tw4), g.nfft * sizeof(float2)));
-        g.chirp.assign(g.trials.size(), nullptr);
-        g.hchirp.assign(g.trials.size(), nullptr);
-        for (size_t i = 0; i < g.trials.size() && e == hipSuccess; ++i) {
-            const double dm = s->dm[g.trials[i]];
-            const double a = dm / (2.41e-10 * f0_mhz * f0_mhz), df = bw_mhz / (double)g.nfft;
-            if (half) {
-                chk(hipMalloc(&g.hchirp[i], g.nfft * 4));
-                if (e == hipSuccess)
-                    chk(launch_k2_build_split_tables_h(i == 0 ? g.htw4 : nullptr, g.hchirp[i], g.log2n1, g.log2n2, a,
-                                                       f0_mhz, df, nullptr));
-            } else {
-                chk(hipMalloc(reinterpret_cast<void**>(&g.chirp[i]), g.nfft * sizeof(float2)));
-                if (e == hipSuccess)
-                    chk(launch_k2_build_split_tables(i == 0 ? g.tw4 : nullptr, g.chirp[i], g.log2n1, g.log2n2, a,
-                                                     f0_mhz, df, nullptr));
-            }
+        chk(hipMalloc(reinterpret_cast<void**>(&g.geo), g.nfft * sizeof(double)));
+        if (e == hipSuccess) {
+            if (half) chk(launch_k2_build_split_tables_h(g.htw4, nullptr, g.log2n1, g.log2n2, 0.0, f0_mhz, df, nullptr));
+            else chk(launch_k2_build_split_tables(g.tw4, nullptr, g.log2n1, g.log2n2, 0.0, f0_mhz, df, nullptr));
         }
+        if (e == hipSuccess) chk(launch_build_dm_geometry(g.geo, g.log2n1, g.log2n2, f0_mhz, df, nullptr));
         // Packed float16: power scale 256 over the measured gain of the
         // group's float16 path (forward rows, then the inverse rows of the
-        // group's first trial; every trial's table rounds alike).
+        // group's first trial; every trial's chirp rounds alike).
         if (half && e == hipSuccess) {
             HalfCal cal;
             cal.prec = precision;
@@ -225,7 +215,8 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
                     K2Args v = f;
                     v.in = g.spec;
                     v.out = g.out;
-                    v.hchirp = g.hchirp[0];
+                    v.geo = g.geo;
+                    v.dm = s->dm[g.trials[0]];
                     if (r == hipSuccess) r = launch_k2(precision, kRowInv, g.log2n1, v, nullptr);
                     *res = g.out;
                     return r;
@@ -325,9 +316,9 @@ int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* 
                 v.log2n2 = g.log2n2;
                 v.tw1 = g.tw1;
                 v.tw4 = g.tw4;
-                v.chirp = g.chirp[i];
                 v.htw4 = g.htw4;
-                v.hchirp = g.hchirp[i];
+                v.geo = g.geo;
+                v.dm = s->dm[t];
                 v.scale = 1.0f;
                 e = launch_k2(s->precision, kRowInv, g.log2n1, v, stream);
                 if (e != hipSuccess) return fail();

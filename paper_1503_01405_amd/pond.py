@@ -34,6 +34,8 @@ FORMS = {"fp32": POND_FP32, "mixed": POND_MIXED, "mixed_valu": POND_MIXED_VALU, 
 POND_STATUS_NONFINITE = 1
 POND_STATUS_RANGE = 2
 
+POND_BATCH_AUTOTUNE = -1
+
 POND_INPUT_COMPLEX = 0
 POND_INPUT_REAL_LSB = 1
 POND_INPUT_REAL_USB = 2
@@ -52,7 +54,7 @@ EXPORTS = (
     "pond_server_destroy", "pond_server_stream_state",
     "pond_aid_create", "pond_aid_geometry", "pond_aid_run", "pond_aid_destroy",
     "pond_real_plan_create", "pond_real_dedisperse", "pond_real_expect",
-    "pond_copy_device", "pond_geometry", "pond_dedisperse_segment_noalloc",
+    "pond_copy_device", "pond_geometry", "pond_dedisperse_segment_noalloc", "pond_plan_autotune",
 )
 KERNEL_NAMES = ("k1_unpack_colfft", "k2_row", "k3_colinv_detect_fold", "fold_reduce", "fold_finalize")
 
@@ -123,6 +125,9 @@ def _load():
     lib.pond_dedisperse_series.restype = i64
     lib.pond_plan_query.argtypes = [P, ctypes.POINTER(pond_info)]
     lib.pond_plan_query.restype = i32
+    lib.pond_plan_autotune.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+    lib.pond_plan_autotune.restype = i32
     lib.pond_plan_expect.argtypes = [P, i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.pond_plan_expect.restype = i32
     lib.pond_plan_destroy.argtypes = [P]
@@ -246,6 +251,20 @@ def pond_plan_query(plan):
     if r != POND_OK:
         raise PondError(r, "pond_plan_query")
     return {name: getattr(info, name) for name, _ in pond_info._fields_}
+
+
+def pond_plan_autotune(plan):
+    """The autotuner's choice for a plan created with POND_BATCH_AUTOTUNE:
+    dict of batch, ms_per_block, default_batch, default_ms_per_block,
+    from_cache."""
+    b, d, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    t, td = ctypes.c_double(0), ctypes.c_double(0)
+    r = _lib.pond_plan_autotune(plan, ctypes.byref(b), ctypes.byref(t), ctypes.byref(d), ctypes.byref(td),
+                                ctypes.byref(c))
+    if r != POND_OK:
+        raise PondError(r, "pond_plan_autotune")
+    return {"batch": b.value, "ms_per_block": t.value, "default_batch": d.value,
+            "default_ms_per_block": td.value, "from_cache": bool(c.value)}
 
 
 def pond_plan_expect(plan, nsamp, subint_nsamp):
@@ -493,6 +512,10 @@ class Plan:
 
     def info(self):
         return pond_plan_query(self.handle)
+
+    def autotune(self):
+        """The autotuner's result (plans created with max_batch=POND_BATCH_AUTOTUNE)."""
+        return pond_plan_autotune(self.handle)
 
     def _expect(self, nsamp):
         return (pond_real_expect if self.real else pond_plan_expect)(self.handle, nsamp, self.subint)
