@@ -253,12 +253,14 @@ def run_search(precision, x, dms, steps, warmup):
     import torch
     import paper_1503_01405_amd as P
     prec = P.FORMS[precision]
-    h = P.pond_search_create(F0, BW, dms, SEARCH_NBINS, PERIOD, 1 << 20, 1 << 23, prec)
+    h = P.pond_search_create(F0, BW, dms, SEARCH_NBINS, PERIOD, 1 << 20, 1 << 23, prec,
+                             max_batch=P.POND_BATCH_AUTOTUNE)
     nsamp = x.numel() // 2
     out = torch.empty((len(dms), SEARCH_NBINS), dtype=torch.float32, device=x.device)
     stream = torch.cuda.current_stream()
     try:
         geo = [P.pond_search_trial(h, t) for t in range(len(dms))]
+        tune = {n: P.pond_search_autotune(h, n) for n in sorted({g[0] for g in geo})}
         for _ in range(warmup):
             if P.pond_search_run(h, x, nsamp, out, stream) != P.POND_OK:
                 raise RuntimeError("pond_search_run failed")
@@ -280,7 +282,7 @@ def run_search(precision, x, dms, steps, warmup):
     for n, _, hop in geo:
         groups.setdefault((n, hop), 0)
         groups[(n, hop)] += 1
-    return dict(ms_per_step=ms, groups=[(n, hop, c) for (n, hop), c in sorted(groups.items())])
+    return dict(ms_per_step=ms, groups=[(n, hop, c) for (n, hop), c in sorted(groups.items())], tune=tune)
 
 
 def search_cpu_baseline(iq_np, dms):
@@ -340,7 +342,11 @@ def main_search(args):
                    "groups_nfft_hop_trials": h["groups"], "form": head},
         "stream_xrealtime": round(SEARCH_NSAMP / 16e6 / (h["ms_per_step"] / 1e3), 2),
         "forms": {f: dict(ms_per_step=round(r["ms_per_step"], 3),
-                          value=round(len(dms) * SEARCH_NSAMP / (r["ms_per_step"] / 1e3) / 1e6, 1))
+                          value=round(len(dms) * SEARCH_NSAMP / (r["ms_per_step"] / 1e3) / 1e6, 1),
+                          autotune={str(n): dict(batch=t["batch"], ms_per_block=round(t["ms_per_block"], 4),
+                                                 default_batch=t["default_batch"],
+                                                 default_ms_per_block=round(t["default_ms_per_block"], 4))
+                                    for n, t in r["tune"].items()})
                   for f, r in res.items()},
         "roofline": dict(bound="hbm", kernel="whole search step", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                          unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,

@@ -382,6 +382,24 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
                                 int32_t precision);
 
 /*
+ * As pond_search_create with blocks per launch for every length group:
+ * max_batch > 0 as given; POND_BATCH_AUTOTUNE tunes each group as
+ * pond_plan_create_ex does (its forward pass and two trials' inverse
+ * passes timed on pseudo-random input; POND_AUTOTUNE_CACHE as there);
+ * other values <= 0 the default (2^28 bytes of spectrum, 1 .. 16 blocks).
+ */
+pond_search* pond_search_create_ex(double f0_mhz, double bw_mhz, const double* dms, int32_t ntrials,
+                                   int32_t nbins, double period_s, int64_t nfft_min, int64_t nfft_max,
+                                   int32_t precision, int32_t max_batch);
+
+/* The autotuner's result for the length group of FFT length nfft (see
+   pond_plan_autotune); POND_EINVAL if there is no such group or it was not
+   tuned. */
+int32_t pond_search_autotune(const pond_search* s, int64_t nfft, int32_t* batch, double* ms_per_block,
+                             int32_t* default_batch, double* default_ms_per_block,
+                             int32_t* from_cache);
+
+/*
  * Fold one whole stream (iq: device, 2*nsamp int8) at every trial DM and
  * write profiles (device, ntrials*nbins float32): trial t's mean detected
  * power per bin over all outputs of its fully covered blocks (one open-ended

@@ -11,6 +11,7 @@
 // factor per group serves every trial (no per-trial tables).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -19,6 +20,7 @@
 
 #include "../../include/pond.h"
 #include "pond_internal.hpp"
+#include "pond_tune.hpp"
 
 using namespace pond;
 
@@ -39,6 +41,8 @@ struct Group {
     double* geo = nullptr;    // [n2][n1] chirp turns per unit DM, shared by the group's trials
     void* spec = nullptr;     // max_batch blocks of spectrum
     void* out = nullptr;      // max_batch blocks of one trial's row-inverse output
+    bool tuned = false;       // max_batch chosen by the autotuner
+    TuneResult tune;
 };
 
 int ilog2(int64_t v) {
@@ -98,12 +102,144 @@ void trial_geometry(double f0, double bw, double dm, int64_t* n_front, int64_t* 
     *discard = d;
 }
 
+// The group's work for blocks block0 .. block0 + nb - 1 of `iq` (absolute
+// sample 0 at iq): K1 and the forward rows into `spec`, then for each of
+// the first `ntr` trials of the group the inverse rows into `out`, K3 and
+// the fold reduction into that trial's accumulators.
+hipError_t run_group(const pond_search* s, const Group& g, void* spec, void* out, const int8_t* iq, int64_t block0,
+                     int nb, size_t ntr, hipStream_t stream) {
+    const int32_t nbins = s->nbins;
+    const int64_t n1 = (int64_t)1 << g.log2n1;
+    const int64_t cap = hist_capacity(g.log2n2, s->precision);
+    const bool global_mode = nbins > cap;
+    K1Args a1{};
+    a1.tail = iq;
+    a1.tail_start = 0;
+    a1.in = iq;
+    a1.in_start = 0;
+    a1.hop = g.hop;
+    a1.block0 = block0;
+    a1.nblocks = nb;
+    a1.log2n1 = g.log2n1;
+    a1.work = spec;
+    a1.tw2 = g.tw2;
+    a1.scale = std::ldexp(1.0f, -g.log2n2);
+    hipError_t e = launch_k1(s->precision, g.log2n2, a1, stream);
+    if (e != hipSuccess) return e;
+    K2Args f{};
+    f.work = spec;
+    f.nblocks = nb;
+    f.log2n2 = g.log2n2;
+    f.tw1 = g.tw1;
+    f.tw4 = g.tw4;
+    f.htw4 = g.htw4;
+    f.scale = std::ldexp(1.0f, -g.log2n1);
+    e = launch_k2(s->precision, kRowFwd, g.log2n1, f, stream);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i < ntr && i < g.trials.size(); ++i) {
+        const int t = g.trials[i];
+        K2Args v{};
+        v.in = spec;
+        v.out = out;
+        v.nblocks = nb;
+        v.log2n2 = g.log2n2;
+        v.tw1 = g.tw1;
+        v.tw4 = g.tw4;
+        v.htw4 = g.htw4;
+        v.geo = g.geo;
+        v.dm = s->dm[t];
+        v.scale = 1.0f;
+        e = launch_k2(s->precision, kRowInv, g.log2n1, v, stream);
+        if (e != hipSuccess) return e;
+        K3Args a3{};
+        a3.work = out;
+        a3.nblocks = nb;
+        a3.log2n1 = g.log2n1;
+        a3.hop = g.hop;
+        a3.n_front = s->n_front[t];
+        a3.block0 = block0;
+        a3.tw2 = g.tw2;
+        a3.scale = 1.0f;
+        a3.pscale = g.pscale;
+        a3.series = nullptr;
+        a3.series_base = 0;
+        a3.decim = 16;
+        a3.nbins = nbins;
+        a3.inv_pfs = s->inv_pfs;
+        a3.subint = 0;
+        a3.s_base = 0;
+        a3.entries = nbins;
+        a3.global_mode = global_mode ? 1 : 0;
+        a3.part_sum = s->part_sum;
+        a3.part_cnt = s->part_cnt;
+        a3.acc_sum = s->acc_sum + (int64_t)t * nbins;
+        a3.acc_cnt = s->acc_cnt + (int64_t)t * nbins;
+        a3.acc_s0 = 0;
+        a3.status = reinterpret_cast<uint32_t*>(s->status);
+        const size_t dyn = global_mode ? 0 : (size_t)nbins * 12;
+        const int grid = k3_grid(g.log2n2, s->precision, dyn, (int64_t)nb * (n1 / 16), nbins, global_mode);
+        e = launch_k3(s->precision, g.log2n2, a3, grid, dyn, stream);
+        if (e != hipSuccess) return e;
+        if (!global_mode) {
+            e = launch_fold_reduce(s->part_sum, s->part_cnt, grid, nbins, a3.acc_sum, a3.acc_cnt, 0, stream);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// Autotuned blocks per launch of one group (tables built, fold buffers in
+// place, spec/out not allocated): the group's pass with two trials (the
+// per-trial part is the same for every trial) on pseudo-random input.
+hipError_t tune_group(pond_search* s, Group& g, int default_batch) {
+    size_t free_b = 0, total_b = 0;
+    hipError_t e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) return e;
+    const int64_t block_bytes = 2 * g.nfft * (int64_t)s->elem;  // spec + out
+    const int64_t cap = std::min<int64_t>((int64_t)4 << 30, (int64_t)(free_b / 3));
+    const std::vector<int> cand = batch_candidates(block_bytes, cap, default_batch);
+    const int nb_max = cand.back();
+    void *spec = nullptr, *out = nullptr;
+    int8_t* in = nullptr;
+    const int64_t in_bytes = ((int64_t)(nb_max - 1) * g.hop + g.nfft) * 2;
+    e = hipMalloc(&spec, (size_t)nb_max * g.nfft * s->elem);
+    if (e == hipSuccess) e = hipMalloc(&out, (size_t)nb_max * g.nfft * s->elem);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&in), (size_t)((in_bytes + 7) & ~7ll));
+    if (e == hipSuccess)
+        e = launch_fill_noise_u64(reinterpret_cast<uint64_t*>(in), (in_bytes + 7) / 8, 0x706f6e64ull, nullptr);
+    if (e == hipSuccess) {
+        TuneKey key;
+        key.path = "search2";
+        key.nfft = g.nfft;
+        key.precision = s->precision;
+        key.kind = POND_INPUT_COMPLEX;
+        key.global_hist = s->nbins > hist_capacity(g.log2n2, s->precision);
+        e = autotune_batch(key, cand, default_batch,
+                           [&](int nb) { return run_group(s, g, spec, out, in, 0, nb, 2, nullptr); }, &g.tune);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (spec) (void)hipFree(spec);
+    if (out) (void)hipFree(out);
+    if (in) (void)hipFree(in);
+    if (e == hipSuccess) {
+        g.max_batch = g.tune.batch;
+        g.tuned = true;
+    }
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
 
 pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms, int32_t ntrials, int32_t nbins,
                                 double period_s, int64_t nfft_min, int64_t nfft_max, int32_t precision) {
+    return pond_search_create_ex(f0_mhz, bw_mhz, dms, ntrials, nbins, period_s, nfft_min, nfft_max, precision, 0);
+}
+
+pond_search* pond_search_create_ex(double f0_mhz, double bw_mhz, const double* dms, int32_t ntrials, int32_t nbins,
+                                   double period_s, int64_t nfft_min, int64_t nfft_max, int32_t precision,
+                                   int32_t max_batch) {
     if (!dms || ntrials < 1 || nbins < 1 || nbins > 65536) return nullptr;
     if (!std::isfinite(f0_mhz) || !std::isfinite(bw_mhz) || !std::isfinite(period_s)) return nullptr;
     if (!(bw_mhz > 0) || !(f0_mhz - bw_mhz / 2 > 0)) return nullptr;
@@ -157,7 +293,7 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
             g.log2n2 = g.log2n / 2 < 10 ? g.log2n / 2 : 10;
             g.log2n1 = g.log2n - g.log2n2;
             int64_t b = ((int64_t)1 << 28) / (n * (int64_t)s->elem);
-            g.max_batch = (int)(b < 1 ? 1 : (b > 16 ? 16 : b));
+            g.max_batch = max_batch > 0 ? max_batch : (int)(b < 1 ? 1 : (b > 16 ? 16 : b));
             s->groups.push_back(g);
             gi = (int)s->groups.size() - 1;
         }
@@ -169,14 +305,19 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
     auto chk = [&](hipError_t x) {
         if (e == hipSuccess) e = x;
     };
+    // fold buffers first (the autotuner's launches fold too; every run
+    // clears the accumulators it uses)
+    chk(hipMalloc(reinterpret_cast<void**>(&s->acc_sum), (size_t)ntrials * nbins * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&s->acc_cnt), (size_t)ntrials * nbins * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&s->part_sum), (size_t)kPartEntries * 8));
+    chk(hipMalloc(reinterpret_cast<void**>(&s->part_cnt), (size_t)kPartEntries * 4));
+    chk(hipMalloc(reinterpret_cast<void**>(&s->status), 8));
     for (auto& g : s->groups) {
         const int64_t n1 = (int64_t)1 << g.log2n1, n2 = (int64_t)1 << g.log2n2;
         chk(hipMalloc(reinterpret_cast<void**>(&g.tw1), n1 * sizeof(float2)));
         chk(hipMalloc(reinterpret_cast<void**>(&g.tw2), n2 * sizeof(float2)));
         if (e == hipSuccess) chk(launch_stage_twiddles(g.tw1, n1, nullptr));
         if (e == hipSuccess) chk(launch_stage_twiddles(g.tw2, n2, nullptr));
-        chk(hipMalloc(&g.spec, (size_t)g.max_batch * g.nfft * s->elem));
-        chk(hipMalloc(&g.out, (size_t)g.max_batch * g.nfft * s->elem));
         // One table per group for every trial: the four-step twiddle, and the
         // chirp's turns per unit DM of each bin (each trial's chirp is formed
         // from it and its DM in the inverse rows).
@@ -190,6 +331,9 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
             else chk(launch_k2_build_split_tables(g.tw4, nullptr, g.log2n1, g.log2n2, 0.0, f0_mhz, df, nullptr));
         }
         if (e == hipSuccess) chk(launch_build_dm_geometry(g.geo, g.log2n1, g.log2n2, f0_mhz, df, nullptr));
+        if (e == hipSuccess && max_batch == POND_BATCH_AUTOTUNE) chk(tune_group(s, g, g.max_batch));
+        chk(hipMalloc(&g.spec, (size_t)g.max_batch * g.nfft * s->elem));
+        chk(hipMalloc(&g.out, (size_t)g.max_batch * g.nfft * s->elem));
         // Packed float16: power scale 256 over the measured gain of the
         // group's float16 path (forward rows, then the inverse rows of the
         // group's first trial; every trial's chirp rounds alike).
@@ -225,11 +369,6 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
             g.pscale = (float)(256.0 / gain);
         }
     }
-    chk(hipMalloc(reinterpret_cast<void**>(&s->acc_sum), (size_t)ntrials * nbins * 8));
-    chk(hipMalloc(reinterpret_cast<void**>(&s->acc_cnt), (size_t)ntrials * nbins * 8));
-    chk(hipMalloc(reinterpret_cast<void**>(&s->part_sum), (size_t)kPartEntries * 8));
-    chk(hipMalloc(reinterpret_cast<void**>(&s->part_cnt), (size_t)kPartEntries * 4));
-    chk(hipMalloc(reinterpret_cast<void**>(&s->status), 8));
     if (e == hipSuccess) chk(hipMemset(s->status, 0, 8));
     if (e == hipSuccess) chk(hipStreamSynchronize(nullptr));
     if (e != hipSuccess) {
@@ -239,6 +378,22 @@ pond_search* pond_search_create(double f0_mhz, double bw_mhz, const double* dms,
         return nullptr;
     }
     return s;
+}
+
+int32_t pond_search_autotune(const pond_search* s, int64_t nfft, int32_t* batch, double* ms_per_block,
+                             int32_t* default_batch, double* default_ms_per_block, int32_t* from_cache) {
+    if (!s) return POND_EINVAL;
+    for (const Group& g : s->groups) {
+        if (g.nfft != nfft) continue;
+        if (!g.tuned) return POND_EINVAL;
+        if (batch) *batch = g.tune.batch;
+        if (ms_per_block) *ms_per_block = g.tune.ms_per_block;
+        if (default_batch) *default_batch = g.tune.default_batch;
+        if (default_ms_per_block) *default_ms_per_block = g.tune.default_ms_per_block;
+        if (from_cache) *from_cache = g.tune.from_cache ? 1 : 0;
+        return POND_OK;
+    }
+    return POND_EINVAL;
 }
 
 int32_t pond_search_trial(const pond_search* s, int32_t t, int64_t* nfft, int64_t* n_front, int64_t* hop) {
@@ -273,89 +428,13 @@ int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* 
     e = launch_zero_u64(s->acc_sum, (int64_t)s->ntrials * nbins, stream);
     if (e == hipSuccess) e = launch_zero_u64(s->acc_cnt, (int64_t)s->ntrials * nbins, stream);
     if (e != hipSuccess) return fail();
-    const bool global_mode_all = false;
-    (void)global_mode_all;
 
     for (auto& g : s->groups) {
         const int64_t nb_total = nsamp < g.nfft ? 0 : (nsamp - g.nfft) / g.hop + 1;
-        const int64_t n1 = (int64_t)1 << g.log2n1;
-        const int64_t cap = hist_capacity(g.log2n2, s->precision);
-        const bool global_mode = nbins > cap;
         for (int64_t b = 0; b < nb_total; b += g.max_batch) {
             const int nb = (int)(nb_total - b < g.max_batch ? nb_total - b : g.max_batch);
-            K1Args a1{};
-            a1.tail = iq;
-            a1.tail_start = 0;
-            a1.in = iq;
-            a1.in_start = 0;
-            a1.hop = g.hop;
-            a1.block0 = b;
-            a1.nblocks = nb;
-            a1.log2n1 = g.log2n1;
-            a1.work = g.spec;
-            a1.tw2 = g.tw2;
-            a1.scale = std::ldexp(1.0f, -g.log2n2);
-            e = launch_k1(s->precision, g.log2n2, a1, stream);
+            e = run_group(s, g, g.spec, g.out, iq, b, nb, g.trials.size(), stream);
             if (e != hipSuccess) return fail();
-            K2Args f{};
-            f.work = g.spec;
-            f.nblocks = nb;
-            f.log2n2 = g.log2n2;
-            f.tw1 = g.tw1;
-            f.tw4 = g.tw4;
-            f.htw4 = g.htw4;
-            f.scale = std::ldexp(1.0f, -g.log2n1);
-            e = launch_k2(s->precision, kRowFwd, g.log2n1, f, stream);
-            if (e != hipSuccess) return fail();
-            for (size_t i = 0; i < g.trials.size(); ++i) {
-                const int t = g.trials[i];
-                K2Args v{};
-                v.in = g.spec;
-                v.out = g.out;
-                v.nblocks = nb;
-                v.log2n2 = g.log2n2;
-                v.tw1 = g.tw1;
-                v.tw4 = g.tw4;
-                v.htw4 = g.htw4;
-                v.geo = g.geo;
-                v.dm = s->dm[t];
-                v.scale = 1.0f;
-                e = launch_k2(s->precision, kRowInv, g.log2n1, v, stream);
-                if (e != hipSuccess) return fail();
-                K3Args a3{};
-                a3.work = g.out;
-                a3.nblocks = nb;
-                a3.log2n1 = g.log2n1;
-                a3.hop = g.hop;
-                a3.n_front = s->n_front[t];
-                a3.block0 = b;
-                a3.tw2 = g.tw2;
-                a3.scale = 1.0f;
-                a3.pscale = g.pscale;
-                a3.series = nullptr;
-                a3.series_base = 0;
-                a3.decim = 16;
-                a3.nbins = nbins;
-                a3.inv_pfs = s->inv_pfs;
-                a3.subint = 0;
-                a3.s_base = 0;
-                a3.entries = nbins;
-                a3.global_mode = global_mode ? 1 : 0;
-                a3.part_sum = s->part_sum;
-                a3.part_cnt = s->part_cnt;
-                a3.acc_sum = s->acc_sum + (int64_t)t * nbins;
-                a3.acc_cnt = s->acc_cnt + (int64_t)t * nbins;
-                a3.acc_s0 = 0;
-                a3.status = reinterpret_cast<uint32_t*>(s->status);
-                const size_t dyn = global_mode ? 0 : (size_t)nbins * 12;
-                const int grid = k3_grid(g.log2n2, s->precision, dyn, (int64_t)nb * (n1 / 16), nbins, global_mode);
-                e = launch_k3(s->precision, g.log2n2, a3, grid, dyn, stream);
-                if (e != hipSuccess) return fail();
-                if (!global_mode) {
-                    e = launch_fold_reduce(s->part_sum, s->part_cnt, grid, nbins, a3.acc_sum, a3.acc_cnt, 0, stream);
-                    if (e != hipSuccess) return fail();
-                }
-            }
         }
     }
     e = launch_fold_profiles(s->acc_sum, s->acc_cnt, (int64_t)s->ntrials * nbins, profiles, stream);

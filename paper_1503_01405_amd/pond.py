@@ -49,6 +49,7 @@ EXPORTS = (
     "pond_plan_expect", "pond_plan_destroy", "pond_strerror",
     "pond_plan_set_timing", "pond_plan_kernel_times", "pond_plan_set_taper",
     "pond_search_create", "pond_search_run", "pond_search_trial", "pond_search_destroy",
+    "pond_search_create_ex", "pond_search_autotune",
     "pond_server_create", "pond_server_stream_bytes", "pond_server_open", "pond_server_submit",
     "pond_server_poll", "pond_server_take_profiles", "pond_server_close", "pond_server_query",
     "pond_server_destroy", "pond_server_stream_state",
@@ -140,6 +141,11 @@ def _load():
     lib.pond_plan_kernel_times.restype = i32
     lib.pond_search_create.argtypes = [dbl, dbl, ctypes.POINTER(dbl), i32, i32, dbl, i64, i64, i32]
     lib.pond_search_create.restype = P
+    lib.pond_search_create_ex.argtypes = [dbl, dbl, ctypes.POINTER(dbl), i32, i32, dbl, i64, i64, i32, i32]
+    lib.pond_search_create_ex.restype = P
+    lib.pond_search_autotune.argtypes = [P, i64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+    lib.pond_search_autotune.restype = i32
     lib.pond_search_run.argtypes = [P, P, i64, P, P]
     lib.pond_search_run.restype = i32
     lib.pond_search_trial.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -338,13 +344,32 @@ def pond_copy_device(dst, src, nbytes, stream=None):
 
 
 def pond_search_create(f0_mhz, bw_mhz, dms, nbins, period_s, nfft_min=1 << 20, nfft_max=1 << 23,
-                       precision=POND_FP32):
+                       precision=POND_FP32, max_batch=None):
+    """Create a DM-trial search; max_batch (None: pond_search_create's
+    default) as for pond_search_create_ex, e.g. POND_BATCH_AUTOTUNE."""
     arr = (ctypes.c_double * len(dms))(*[float(d) for d in dms])
-    h = _lib.pond_search_create(float(f0_mhz), float(bw_mhz), arr, len(dms), int(nbins), float(period_s),
-                                int(nfft_min), int(nfft_max), int(precision))
+    if max_batch is None:
+        h = _lib.pond_search_create(float(f0_mhz), float(bw_mhz), arr, len(dms), int(nbins), float(period_s),
+                                    int(nfft_min), int(nfft_max), int(precision))
+    else:
+        h = _lib.pond_search_create_ex(float(f0_mhz), float(bw_mhz), arr, len(dms), int(nbins), float(period_s),
+                                       int(nfft_min), int(nfft_max), int(precision), int(max_batch))
     if not h:
         raise PondError(POND_EINVAL, "pond_search_create")
     return h
+
+
+def pond_search_autotune(search, nfft):
+    """The autotuner's result for the search's length group of FFT length
+    nfft (dict as pond_plan_autotune)."""
+    b, d, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    t, td = ctypes.c_double(0), ctypes.c_double(0)
+    r = _lib.pond_search_autotune(search, int(nfft), ctypes.byref(b), ctypes.byref(t), ctypes.byref(d),
+                                  ctypes.byref(td), ctypes.byref(c))
+    if r != POND_OK:
+        raise PondError(r, "pond_search_autotune")
+    return {"batch": b.value, "ms_per_block": t.value, "default_batch": d.value,
+            "default_ms_per_block": td.value, "from_cache": bool(c.value)}
 
 
 def pond_search_run(search, iq, nsamp, profiles, stream=None):

@@ -64,3 +64,39 @@ def test_autotune_with_unwritable_cache_still_tunes(tmp_path, monkeypatch):
     p.close()
     assert r["batch"] >= 1 and not r["from_cache"]
     assert not os.path.exists(tmp_path / "missing_dir")
+
+
+@pytest.mark.gpu
+def test_search_autotune_per_group_and_same_profiles(monkeypatch):
+    """A search created with POND_BATCH_AUTOTUNE tunes each length group
+    and folds the same bits as the default search (integer fold)."""
+    import torch
+    import paper_1503_01405_amd as P
+    monkeypatch.delenv("POND_AUTOTUNE_CACHE", raising=False)
+    dms = [0.0, 0.5, 1.0, 2.0]
+    nsamp = 3_000_000
+    iq = synth.white_stream_int8(11, nsamp)
+    x = torch.from_numpy(iq).to("cuda")
+    outs = []
+    for mb in (None, P.POND_BATCH_AUTOTUNE):
+        print(f"case: search autotune={mb}", flush=True)
+        h = P.pond_search_create(F0, BW, dms, 128, synth.PERIOD_S, 1 << 16, 1 << 19, P.POND_HALF, max_batch=mb)
+        try:
+            groups = sorted({P.pond_search_trial(h, t)[0] for t in range(len(dms))})
+            if mb is None:
+                with pytest.raises(P.PondError):
+                    P.pond_search_autotune(h, groups[0])
+            else:
+                for n in groups:
+                    r = P.pond_search_autotune(h, n)
+                    print(n, r, flush=True)
+                    assert r["batch"] >= 1 and r["ms_per_block"] > 0 and r["default_ms_per_block"] > 0
+                with pytest.raises(P.PondError):
+                    P.pond_search_autotune(h, 1 << 12)  # no such group
+            out = torch.empty((len(dms), 128), dtype=torch.float32, device="cuda")
+            assert P.pond_search_run(h, x, nsamp, out) == P.POND_OK
+            torch.cuda.synchronize()
+            outs.append(out.cpu().numpy())
+        finally:
+            P.pond_search_destroy(h)
+    assert np.array_equal(outs[0], outs[1])
