@@ -702,7 +702,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="fp32,mixed_valu,mixed,half")
+    ap.add_argument("--forms", default="fp32,mixed_valu,mixed,half,bf16")
     ap.add_argument("--cpu-blocks", type=int, default=80,
                     help="blocks of the stream the CPU oracle baseline processes (about 15 s on 16 cores)")
     ap.add_argument("--graph", action="store_true",
@@ -761,9 +761,9 @@ def main():
         res[f] = run_form(f, x, args.steps, args.warmup, graph=args.graph)
         log(f"{f}: {res[f]['ms_per_step']:.3f} ms/step  kernels {res[f]['kernels']}")
 
-    # headline: the faster of the two mixed-precision forms (float16 storage
-    # with float32 arithmetic, or float16 matrix-core DFT stages)
-    mixed = [f for f in res if f != "fp32"]
+    # headline: the fastest float16 form (bfloat16 storage is a reported
+    # variant only, not held to the 1e-4 accuracy)
+    mixed = [f for f in res if f not in ("fp32", "bf16")]
     head = min(mixed, key=lambda f: res[f]["ms_per_step"]) if mixed else forms[0]
     h = res[head]
     hop = h["info"]["hop"]
@@ -813,7 +813,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"mixed": "f16 (matrix-core DFT) / f32 accumulate", "mixed_valu": "f16-storage/f32",
-                  "half": "f16 (packed VALU) / f32 detect+fold",
+                  "half": "f16 (packed VALU) / f32 detect+fold", "bf16": "bf16-storage/f32",
                   "fp32": "f32"}[head],
         "data": "synthetic",
         "config": {"workload": "60 s 16 Msps int8 I/Q at 326.5 MHz, DM 50, nfft 2^23 (2^22 discarded), "

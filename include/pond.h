@@ -78,6 +78,10 @@ typedef struct pond_plan pond_plan;
                           instruction) for every butterfly, twiddle and the chirp multiply;
                           forward transforms normalised stage by stage; detection and fold
                           in float32 from the float16 pair; chirp and fold phases float64  */
+#define POND_BF16   4  /* bfloat16 storage between passes (8-bit significand), every
+                          butterfly in float32 vector arithmetic: a reported variant of
+                          POND_MIXED_VALU for single-DM plans of complex input, not held to
+                          the float16 forms' accuracy                                      */
 
 /* Status bits reported by pond_plan_query().status (sticky until flush). */
 #define POND_STATUS_NONFINITE  1u  /* a detected power was inf or NaN (fp16 overflow)        */
@@ -98,7 +102,7 @@ typedef struct pond_info {
     double  delta_hi_s;    /* advance of band top relative to f0                   */
     double  inv_pfs;       /* 1 / (period_s * fs_hz)                               */
     int32_t nbins;
-    int32_t precision;     /* POND_FP32, POND_MIXED, POND_MIXED_VALU or POND_HALF  */
+    int32_t precision;     /* POND_FP32, POND_MIXED, POND_MIXED_VALU, POND_HALF or POND_BF16 */
     uint32_t status;       /* POND_STATUS_* bits (read synchronously)              */
     int32_t input_kind;    /* POND_INPUT_*                                         */
     double  power_gain;    /* POND_HALF: measured power gain of the plan's float16 */
@@ -180,7 +184,8 @@ pond_plan* pond_plan_create(double f0_mhz, double bw_mhz, double dm,
 
 /*
  * As pond_plan_create with a precision form (POND_FP32, POND_MIXED,
- * POND_MIXED_VALU or POND_HALF) and a cap on overlap-save blocks per launch:
+ * POND_MIXED_VALU, POND_HALF or POND_BF16) and a cap on overlap-save blocks
+ * per launch:
  * max_batch > 0 is used as given; POND_BATCH_AUTOTUNE has the plan time its
  * own launch sequence (K1, middle pass, K3, fold) on pseudo-random int8
  * input at 1, 2, 3, 4, 6, 8, 12, 16, 24 and 32 blocks per launch (those

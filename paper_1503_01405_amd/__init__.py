@@ -18,4 +18,4 @@ from .pond import (POND_EBUSY, POND_EDEVICE, POND_EINVAL, POND_ENOMEM, FORMS, PO
                    pond_real_dedisperse, pond_real_expect, pond_copy_device, pond_geometry,
                    pond_server_stream_state, POND_ECANCELED, POND_TICKET_ADMITTED, POND_STREAM_WAITING,
                    POND_STREAM_OPEN, POND_STREAM_CLOSED, pond_dedisperse_segment_noalloc,
-                   POND_BATCH_AUTOTUNE, pond_plan_autotune, pond_search_autotune)
+                   POND_BATCH_AUTOTUNE, pond_plan_autotune, pond_search_autotune, POND_BF16)

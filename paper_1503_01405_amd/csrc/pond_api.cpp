@@ -537,7 +537,8 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     const int log2n = ilog2(nfft);
     if (log2n < kMinLog2N || log2n > (kind == POND_INPUT_COMPLEX ? kMaxLog2N : kMaxLog2NReal)) return nullptr;
     if (nbins < 1 || nbins > 65536) return nullptr;
-    if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU && precision != POND_HALF)
+    if (precision != POND_FP32 && precision != POND_MIXED && precision != POND_MIXED_VALU && precision != POND_HALF &&
+        precision != POND_BF16)
         return nullptr;
     const double fs = bw_mhz * 1e6;
     if (!(period_s > 0) || !(period_s * fs >= 1.0)) return nullptr;

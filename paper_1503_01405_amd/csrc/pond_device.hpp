@@ -27,6 +27,25 @@ struct Elem<__half2> {
     __device__ __forceinline__ static float2 load(const __half2* p) { return __half22float2(*p); }
     __device__ __forceinline__ static void store(__half2* p, float2 v) { *p = __float22half2_rn(v); }
 };
+// A complex value as two bfloat16 (the upper halves of float32, real part
+// in the low 16 bits), rounded to nearest even on store.
+struct __align__(4) bf16x2 {
+    uint32_t u;
+};
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, f);
+    return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+}
+template <>
+struct Elem<bf16x2> {
+    __device__ __forceinline__ static float2 load(const bf16x2* p) {
+        const uint32_t u = p->u;
+        return make_float2(__builtin_bit_cast(float, u << 16), __builtin_bit_cast(float, u & 0xffff0000u));
+    }
+    __device__ __forceinline__ static void store(bf16x2* p, float2 v) {
+        p->u = bf16_rne(v.x) | (bf16_rne(v.y) << 16);
+    }
+};
 
 // Access at a uniform base pointer plus a 32-bit byte offset (lets the
 // compiler use the scalar-base + vector-offset addressing form).

@@ -18,7 +18,7 @@ namespace pond {
 constexpr double kFoldScale = 65536.0;
 constexpr double kFoldRangeLimit = 1099511627776.0;  // 2^40: flag larger single contributions
 
-enum Precision { kFp32 = 0, kMixed = 1, kMixedValu = 2, kHalf = 3 };
+enum Precision { kFp32 = 0, kMixed = 1, kMixedValu = 2, kHalf = 3, kBf16 = 4 };
 // Forms whose arithmetic is packed float16 (float16 tables, measured power gain).
 constexpr bool f16_arith(int prec) { return prec == kHalf || prec == kMixed; }
 

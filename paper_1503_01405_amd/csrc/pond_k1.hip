@@ -192,6 +192,7 @@ hipError_t launch_k1(int prec, int log2n2, const K1Args& a, hipStream_t s) {
         case kMixed: return k1_dispatch<__half2, kFormMfma>(log2n2, a, s);
         case kMixedValu: return k1_dispatch<__half2, kFormF32>(log2n2, a, s);
         case kHalf: return k1_dispatch<__half2, kFormF16>(log2n2, a, s);
+        case kBf16: return k1_dispatch<bf16x2, kFormF32>(log2n2, a, s);
         default: return k1_dispatch<float2, kFormF32>(log2n2, a, s);
     }
 }

@@ -411,6 +411,7 @@ static hipError_t k2_prec(int prec, int log2n1, const K2Args& a, hipStream_t s) 
         case kFp32: return k2_dispatch<float2, MODE, false>(log2n1, a, s);
         case kHalf: return k2_dispatch<__half2, MODE, true>(log2n1, a, s);
         case kMixed: return k2_dispatch<__half2, MODE, true, true>(log2n1, a, s);
+        case kBf16: return k2_dispatch<bf16x2, MODE, false>(log2n1, a, s);
         default: return k2_dispatch<__half2, MODE, false>(log2n1, a, s);
     }
 }
@@ -427,6 +428,7 @@ hipError_t launch_k2(int prec, int mode, int log2n1, const K2Args& a, hipStream_
                 case kFp32: return k2_one<float2, kRowChirp, false, false, kSplitLog2M1>(a, s);
                 case kHalf: return k2_one<__half2, kRowChirp, true, false, kSplitLog2M1>(a, s);
                 case kMixed: return k2_one<__half2, kRowChirp, true, true, kSplitLog2M1>(a, s);
+                case kBf16: return k2_one<bf16x2, kRowChirp, false, false, kSplitLog2M1>(a, s);
                 default: return k2_one<__half2, kRowChirp, false, false, kSplitLog2M1>(a, s);
             }
         case kRowInvPlain:

@@ -367,6 +367,7 @@ hipError_t launch_k3(int prec, int log2n2, const K3Args& a, int grid, size_t dyn
         case kMixed: return k3_dispatch<__half2, kFormMfma>(log2n2, a, grid, dyn, s);
         case kMixedValu: return k3_dispatch<__half2, kFormF32>(log2n2, a, grid, dyn, s);
         case kHalf: return k3_dispatch<__half2, kFormF16>(log2n2, a, grid, dyn, s);
+        case kBf16: return k3_dispatch<bf16x2, kFormF32>(log2n2, a, grid, dyn, s);
         default: return k3_dispatch<float2, kFormF32>(log2n2, a, grid, dyn, s);
     }
 }

@@ -25,6 +25,8 @@ __device__ __forceinline__ float2 ld_f2(const float2* p) { return *p; }
 __device__ __forceinline__ float2 ld_f2(const __half2* p) { return to_f2(__builtin_bit_cast(h2, *p)); }
 __device__ __forceinline__ void st_f2(float2* p, float2 v) { *p = v; }
 __device__ __forceinline__ void st_f2(__half2* p, float2 v) { *p = __builtin_bit_cast(__half2, to_h2(v)); }
+__device__ __forceinline__ float2 ld_f2(const bf16x2* p) { return Elem<bf16x2>::load(p); }
+__device__ __forceinline__ void st_f2(bf16x2* p, float2 v) { Elem<bf16x2>::store(p, v); }
 
 // exp(-2 pi i r / N) from the two-level table: r = hi 2^s + lo.
 __device__ __forceinline__ float2 block_twiddle(const SplitColArgs& a, uint32_t r) {
@@ -119,6 +121,7 @@ hipError_t split_dispatch(bool inverse, const SplitColArgs& a, hipStream_t s) {
 hipError_t launch_split_cols(int prec, bool inverse, const SplitColArgs& a, hipStream_t s) {
     if (a.log2n1 + a.log2n2 > 31 || a.log2s <= 0 || a.log2s > a.log2n1 + a.log2n2) return hipErrorInvalidValue;
     if (prec == kFp32) return split_dispatch<float2>(inverse, a, s);
+    if (prec == kBf16) return split_dispatch<bf16x2>(inverse, a, s);
     return split_dispatch<__half2>(inverse, a, s);
 }
 

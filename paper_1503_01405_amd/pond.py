@@ -29,7 +29,9 @@ POND_FP32 = 0
 POND_MIXED = 1
 POND_MIXED_VALU = 2
 POND_HALF = 3
-FORMS = {"fp32": POND_FP32, "mixed": POND_MIXED, "mixed_valu": POND_MIXED_VALU, "half": POND_HALF}
+POND_BF16 = 4
+FORMS = {"fp32": POND_FP32, "mixed": POND_MIXED, "mixed_valu": POND_MIXED_VALU, "half": POND_HALF,
+         "bf16": POND_BF16}
 
 POND_STATUS_NONFINITE = 1
 POND_STATUS_RANGE = 2
