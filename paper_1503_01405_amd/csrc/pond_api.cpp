@@ -95,8 +95,8 @@ struct pond_plan {
     int64_t tail_start = 0;
     float2* tw1 = nullptr;
     float2* tw2 = nullptr;
-    float4* table = nullptr;    // float32 forms
-    void* htable = nullptr;     // packed float16 form (8 bytes per entry)
+    void* table = nullptr;      // float32 arithmetic forms: chirp (float32 storage) or twiddle and chirp
+    void* htable = nullptr;     // float16 arithmetic forms: twiddle / 16 and chirp (8 bytes per entry)
     // Split middle pass (rows n1 = m2 2^13 longer than 2^14): tw1 then holds
     // the sub-row twiddles, tw_n1 the row's, tw_hi / tw_lo the two-level
     // block twiddle, chirp_split the chirp in sub-row order (float2, or
@@ -449,7 +449,8 @@ int64_t plan_footprint(int64_t nfft, int32_t nbins, int32_t precision, int32_t m
     const int64_t elem = precision == POND_FP32 ? 8 : 4;
     const int64_t mb = default_max_batch(nfft, precision, max_batch);
     const bool split = (log2n - log2n2) > kMaxLog2RowN1;
-    int64_t tables = nfft * (f16_arith(precision) ? 8 : 16) + (n1 + n2) * 8;
+    // float2 chirp (float32), two float16 pairs (float16 arithmetic), float4 otherwise
+    int64_t tables = nfft * (precision == POND_FP32 || f16_arith(precision) ? 8 : 16) + (n1 + n2) * 8;
     if (split) {
         const int log2s = (log2n + 1) / 2;
         const int64_t m1 = (int64_t)1 << kSplitLog2M1;
@@ -523,7 +524,8 @@ hipError_t build_filter(pond_plan* p, double alpha) {
                                         p->f0, p->df, alpha, nullptr);
     if (f16_arith(p->precision))
         return launch_k2_build_table_h(p->htable, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
-    return launch_k2_build_table(p->table, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df, alpha, nullptr);
+    return launch_k2_build_table(p->table, p->precision != POND_FP32, p->log2n1, p->log2n2, p->chirp_a, p->f0, p->df,
+                                 alpha, nullptr);
 }
 
 pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, int32_t nbins, double period_s,
@@ -627,7 +629,7 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
     } else if (f16_arith(precision)) {
         chk(hipMalloc(&p->htable, (size_t)nfft * 8));
     } else {
-        chk(hipMalloc(reinterpret_cast<void**>(&p->table), (size_t)nfft * sizeof(float4)));
+        chk(hipMalloc(&p->table, (size_t)nfft * (precision == POND_FP32 ? sizeof(float2) : sizeof(float4))));
     }
     if (e == hipSuccess) chk(build_filter(p, 0.0));
     // Fold buffers before the tuner (its launches fold too), cleared below.

@@ -55,7 +55,8 @@ struct K2Args {
     int32_t nblocks;
     int32_t log2n2;
     const float2* tw1;      // exp(-2 pi i t / n1), t < n1
-    const float4* table;    // kRowFull: [n2][n1] four-step twiddle (x, y), inverse ISM response (z, w)
+    const void* table;      // kRowFull, float32 arithmetic: [n2][n1] chirp (float2, float32 storage) or
+                            // twiddle and chirp (float4, float16 / bfloat16 storage)
     const float2* tw4;      // kRowFwd, kRowInv: [n2][n1] four-step twiddle
     const float2* chirp;    // kRowChirp: split middle pass chirp (float32 forms)
     float scale;            // power-of-two scale applied on output (float32 arithmetic)
@@ -188,8 +189,9 @@ hipError_t launch_zero_u64(uint64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_noise_u64(uint64_t* p, int64_t n, uint64_t seed, hipStream_t s);
 // w[t] = exp(-2 pi i t / n) for t < n, float64 sine/cosine rounded to float32.
 hipError_t launch_stage_twiddles(float2* w, int64_t n, hipStream_t s);
-hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
-                                 double taper, hipStream_t s);
+// twiddle: float4 entries (twiddle, chirp), else float2 (chirp).
+hipError_t launch_k2_build_table(void* tab, bool twiddle, int log2n1, int log2n2, double chirp_a, double f0,
+                                 double df, double taper, hipStream_t s);
 hipError_t launch_k2_build_split_tables(float2* tw, float2* chirp, int log2n1, int log2n2, double chirp_a, double f0,
                                         double df, hipStream_t s);
 

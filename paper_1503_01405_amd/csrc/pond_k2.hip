@@ -11,22 +11,21 @@
 
 namespace pond {
 
-// Row table of the middle pass, one float4 per (k2, k1):
-//   (x, y) = W_n^(k1 k2) = exp(-2 pi i (k1 k2 mod n) / n), the four-step twiddle
-//   (z, w) = exp(-2 pi i turns_k), k = k2 + n2 k1, the inverse ISM response
-//            of Sec. 3.7 / Eq. (4); turns_k and its reduction mod 1 are float64.
+// Row table of the middle pass per (k2, k1): exp(-2 pi i turns_k) times the
+// taper, k = k2 + n2 k1, the inverse ISM response of Sec. 3.7 / Eq. (4)
+// (turns_k and its reduction mod 1 in float64), preceded with TW by the
+// four-step twiddle W_n^(k1 k2) (float4; float2 without, for the float32
+// form, whose row kernel forms the twiddle itself).
 // Built once per plan; every block reads the same table.
-__global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, int log2n1, int log2n2,
-                                                       double chirp_a, double f0, double df, double taper) {
+template <bool TW>
+__global__ void __launch_bounds__(256) k2_build_table(void* __restrict__ tab, int log2n1, int log2n2, double chirp_a,
+                                                       double f0, double df, double taper) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int log2n = log2n1 + log2n2;
     const int64_t n = 1ll << log2n;
     if (i >= n) return;
     const int64_t k2 = i >> log2n1;
     const int64_t k1 = i & ((1ll << log2n1) - 1);
-    const int64_t r = (k1 * k2) & (n - 1);
-    double s, c;
-    sincospi(2.0 * (double)r / (double)n, &s, &c);
     const int64_t k = k2 + (k1 << log2n2);
     const int64_t kk = k < (n >> 1) ? k : k - n;
     const double f = (double)kk * df;
@@ -35,7 +34,14 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
     double cs, cc;
     sincospi(2.0 * frac, &cs, &cc);
     const double w = taper_w(f, df * (double)n, taper);
-    tab[i] = make_float4((float)c, (float)-s, (float)(cc * w), (float)(-cs * w));
+    if constexpr (TW) {
+        const int64_t r = (k1 * k2) & (n - 1);
+        double s, c;
+        sincospi(2.0 * (double)r / (double)n, &s, &c);
+        reinterpret_cast<float4*>(tab)[i] = make_float4((float)c, (float)-s, (float)(cc * w), (float)(-cs * w));
+    } else {
+        reinterpret_cast<float2*>(tab)[i] = make_float2((float)(cc * w), (float)(-cs * w));
+    }
 }
 
 // One workgroup takes row k2 (ROWS rows for short rows) of one block.  The
@@ -44,7 +50,16 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 // through that XCD's L2 (the table is then fetched from HBM about once per
 // launch).
 //   MODE kRowFull: twiddle, forward FFT, chirp, inverse FFT, conjugate
-//                  twiddle, in place (float4 table: twiddle, chirp).
+//                  twiddle, in place.  Float32 form: float2 chirp table, the
+//                  twiddle W_N^(k2 n) = lo[n mod LO] hi[n / LO] from two
+//                  per-row float32 tables the workgroup forms in LDS (RowTw;
+//                  the float32 rows read 16 bytes per element besides it).
+//                  Float16 / bfloat16 storage with float32 arithmetic: a
+//                  float4 table (twiddle, chirp).  Float16 arithmetic: two
+//                  float16 pairs per element (twiddle / 16, chirp * 2^-rem).
+//                  Forming the twiddle in the row kernel measured faster only
+//                  in the float32 form; in the others it costs registers
+//                  (float16: 61 -> 92, occupancy 8 -> 5 waves) and time.
 //   MODE kRowFwd:  twiddle and forward FFT only, in place: leaves the block's
 //                  spectrum, row k2 holding bins k2 + n2 k1 (float2 twiddle table).
 //   MODE kRowInv:  spectrum (in) times one trial's chirp, inverse FFT,
@@ -63,6 +78,40 @@ __global__ void __launch_bounds__(256) k2_build_table(float4* __restrict__ tab, 
 // is the block's spectrum / n; the output is 1/16 of the float32 forms'.
 // MXF (with F16, rows of 2^10 and more): the radix-16 stages' butterfly
 // sums on the matrix cores (fft_mx), inputs loaded in their layout.
+// Four-step twiddles of a workgroup's rows for the full middle pass:
+// W_N^(k2 n) = lo[n mod LO] * hi[n / LO] with lo[t] = W_N^(k2 t) and hi[u] =
+// W_N^(k2 LO u), LO = 2^floor(log2(n1) / 2), each entry the float32 sine and
+// cosine of an exactly representable phase (k2 t mod N < 2^24): the product
+// is within a few float32 ulps of the exact twiddle, and the tables cost the
+// workgroup (LO + n1 / LO) sine/cosine pairs instead of a table read per
+// element.
+template <int LOG2N1>
+struct RowTw {
+    static constexpr int LOG2LO = LOG2N1 / 2;
+    static constexpr int LO = 1 << LOG2LO;
+    static constexpr int HI = (1 << LOG2N1) >> LOG2LO;
+    static constexpr int PER_ROW = LO + HI;
+    // rows row0 .. row0 + ROWS - 1 (k2), all threads of the workgroup
+    template <int ROWS, int THREADS>
+    __device__ __forceinline__ static void fill(float2* t, int row0, int log2n, int tid) {
+        const uint32_t nmask = (1u << log2n) - 1u;
+        const float scale = 2.0f / (float)(1u << log2n);  // exact: a power of two
+        for (int i = tid; i < ROWS * PER_ROW; i += THREADS) {
+            const int rr = i / PER_ROW, k = i - rr * PER_ROW;
+            const uint32_t k2 = (uint32_t)(row0 + rr);
+            const uint32_t e = k < LO ? (uint32_t)k : (uint32_t)(k - LO) << LOG2LO;
+            float sn, cs;
+            sincospif((float)((k2 * e) & nmask) * scale, &sn, &cs);
+            t[i] = make_float2(cs, -sn);
+        }
+    }
+    // W_N^(k2 n) of row rr of the workgroup at position n of the row
+    __device__ __forceinline__ static float2 at(const float2* t, uint32_t rr, uint32_t n) {
+        const float2* b = t + rr * PER_ROW;
+        return cmul(b[n & (LO - 1)], b[LO + (n >> LOG2LO)]);
+    }
+};
+
 // exp(-2 pi i turns) of one trial's chirp at a bin with turns = dm g (Eq.
 // (4) with the DM factored out): the product and the reduction mod 1 in
 // float64, the sine and cosine of the reduced phase in float32.
@@ -207,7 +256,23 @@ k2_row(K2Args a) {
         }
         return;
     } else {
-        const float4* tab = a.table + ((int64_t)row0 << LOG2N1);
+        // float32 storage: twiddles formed here, float2 chirp table;
+        // otherwise the float4 table (twiddle, chirp)
+        constexpr bool OTF = std::is_same<T, float2>::value;
+        const float2* tab = reinterpret_cast<const float2*>(a.table) + ((int64_t)row0 << LOG2N1);
+        const float4* tab4 = reinterpret_cast<const float4*>(a.table) + ((int64_t)row0 << LOG2N1);
+        __shared__ float2 rtw[MODE == kRowFull && OTF ? Sh::ROWS * RowTw<LOG2N1>::PER_ROW : 1];
+        if constexpr (MODE == kRowFull && OTF) {
+            RowTw<LOG2N1>::template fill<Sh::ROWS, Sh::THREADS>(rtw, row0, LOG2N1 + a.log2n2, threadIdx.x);
+            __syncthreads();
+        }
+        auto tw_row = [&](uint32_t i) {
+            if constexpr (OTF) return RowTw<LOG2N1>::at(rtw, i >> LOG2N1, i & ((1u << LOG2N1) - 1u));
+            else {
+                const float4 t = *at(tab4, i * 16u);
+                return make_float2(t.x, t.y);
+            }
+        };
         const float2* tw4 = a.tw4 + ((int64_t)row0 << LOG2N1);
         const float2* chirp = a.chirp + ((int64_t)row0 << LOG2N1);
         const double* geo = a.geo + ((int64_t)row0 << LOG2N1);
@@ -217,8 +282,7 @@ k2_row(K2Args a) {
         for (int e = 0; e < 16; ++e) {
             const float2 x = Elem<T>::load(at(src, (to + TPV * e) * (uint32_t)sizeof(T)));
             if constexpr (MODE == kRowFull) {
-                const float4 t = *at(tab, (to + TPV * e) * 16u);
-                v[e] = cmul(x, make_float2(t.x, t.y));
+                v[e] = cmul(x, tw_row(to + TPV * e));
             } else if constexpr (MODE == kRowFwd) {
                 v[e] = cmul(x, *at(tw4, (to + TPV * e) * 8u));
             } else if constexpr (MODE == kRowInv) {
@@ -236,8 +300,10 @@ k2_row(K2Args a) {
             for (int e = 0; e < 16; ++e) {
                 if constexpr (MODE == kRowChirp) {
                     ch[e] = *at(chirp, (t2 + TPV * e) * 8u);
+                } else if constexpr (OTF) {
+                    ch[e] = *at(tab, (t2 + TPV * e) * 8u);
                 } else {
-                    const float4 t = *at(tab, (t2 + TPV * e) * 16u);
+                    const float4 t = *at(tab4, (t2 + TPV * e) * 16u);
                     ch[e] = make_float2(t.z, t.w);
                 }
             }
@@ -275,8 +341,7 @@ k2_row(K2Args a) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 if constexpr (MODE == kRowFull) {
-                    const float4 t = *at(tab, (t2 + TPV * e) * 16u);
-                    wo[e] = make_float2(t.x, t.y);
+                    wo[e] = tw_row(t2 + TPV * e);
                 } else {
                     wo[e] = *at(tw4, (t2 + TPV * e) * 8u);
                 }
@@ -293,10 +358,11 @@ k2_row(K2Args a) {
     }
 }
 
-// Float16 table of the middle pass for the packed-float16 form, 8 bytes per
-// (k2, k1): the four-step twiddle / 16 and the inverse ISM response times
-// 2^-rem (rem: the part of the row normalisation not applied by the
-// transform's stages), both evaluated in float64 as in k2_build_table.
+// Float16 table of the middle pass for the float16 arithmetic forms, 8
+// bytes per (k2, k1): the four-step twiddle / 16 and the inverse ISM
+// response times 2^-rem (rem: the part of the row normalisation not applied
+// by the transform's stages), both evaluated in float64 as in
+// k2_build_table.
 __global__ void __launch_bounds__(256) k2_build_table_h(uint2* __restrict__ tab, int log2n1, int log2n2,
                                                          double chirp_a, double f0, double df, double chirp_scale,
                                                          double taper) {
@@ -486,11 +552,15 @@ hipError_t launch_k2_build_table_h(void* tab, int log2n1, int log2n2, double chi
     return hipGetLastError();
 }
 
-hipError_t launch_k2_build_table(float4* tab, int log2n1, int log2n2, double chirp_a, double f0, double df,
-                                 double taper, hipStream_t s) {
+hipError_t launch_k2_build_table(void* tab, bool twiddle, int log2n1, int log2n2, double chirp_a, double f0,
+                                 double df, double taper, hipStream_t s) {
     const int64_t n = 1ll << (log2n1 + log2n2);
-    hipLaunchKernelGGL(k2_build_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n1, log2n2,
-                       chirp_a, f0, df, taper);
+    if (twiddle)
+        hipLaunchKernelGGL(k2_build_table<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n1,
+                           log2n2, chirp_a, f0, df, taper);
+    else
+        hipLaunchKernelGGL(k2_build_table<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tab, log2n1,
+                           log2n2, chirp_a, f0, df, taper);
     return hipGetLastError();
 }
 

@@ -99,7 +99,7 @@ int64_t pond_dedisperse_segment_noalloc(double f0_mhz, double bw_mhz, double dm,
     };
     float2* tw1 = reinterpret_cast<float2*>(take((size_t)n1 * sizeof(float2)));
     float2* tw2 = reinterpret_cast<float2*>(take((size_t)n2 * sizeof(float2)));
-    float4* table = reinterpret_cast<float4*>(take((size_t)nfft * sizeof(float4)));
+    void* table = take((size_t)nfft * (precision == POND_FP32 ? sizeof(float2) : sizeof(float4)));
     uint64_t* acc_sum = reinterpret_cast<uint64_t*>(take((size_t)nbins * 8));
     uint64_t* acc_cnt = reinterpret_cast<uint64_t*>(take((size_t)nbins * 8));
     uint64_t* status = reinterpret_cast<uint64_t*>(take(8));
@@ -119,8 +119,8 @@ int64_t pond_dedisperse_segment_noalloc(double f0_mhz, double bw_mhz, double dm,
     hipError_t e = launch_stage_twiddles(tw1, n1, stream);
     if (e == hipSuccess) e = launch_stage_twiddles(tw2, n2, stream);
     if (e == hipSuccess)
-        e = launch_k2_build_table(table, log2n1, log2n2, dm / (2.41e-10 * f0_mhz * f0_mhz), f0_mhz,
-                                  bw_mhz / (double)nfft, 0.0, stream);
+        e = launch_k2_build_table(table, precision != POND_FP32, log2n1, log2n2, dm / (2.41e-10 * f0_mhz * f0_mhz),
+                                  f0_mhz, bw_mhz / (double)nfft, 0.0, stream);
     // accumulators and status start at zero (fill kernels, no memset nodes)
     if (e == hipSuccess) e = launch_zero_u64(acc_sum, nbins, stream);
     if (e == hipSuccess) e = launch_zero_u64(acc_cnt, nbins, stream);
