@@ -111,9 +111,10 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel_prefix, form):
-    """HBM bytes per dispatch of a kernel from the committed counter summary
-    of that form, or None if the summary is missing or was taken on other
-    kernel sources."""
+    """HBM bytes per overlap-save block of a kernel (read, written) from the
+    committed counter summary of that form, or None if the summary is
+    missing or was taken on other kernel sources.  Per block, so that it
+    applies whatever blocks per launch the autotuner picked."""
     path = os.path.join(ROOT, "profiles", f"hbm_bytes_dm50_nfft2e23_{form}.txt")
     if not os.path.exists(path):
         return None
@@ -126,22 +127,23 @@ def measured_traffic(kernel_prefix, form):
     if src != kernel_source_hash():
         return None
     for ln in lines:
-        if ln.startswith("TRAFFIC ") and kernel_prefix in ln and "__half2" in ln:
+        if ln.startswith("TRAFFIC ") and kernel_prefix in ln:
             kv = dict(t.split("=") for t in ln.split() if "=" in t)
-            return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+            return float(kv["fetch_bytes_per_block"]), float(kv["write_bytes_per_block"])
     return None
 
 
-def run_form(precision, x, steps, warmup, graph=False):
+def run_form(precision, x, steps, warmup, graph=False, max_batch=0):
     import torch
     import paper_1503_01405_amd as P
 
     # blocks per launch chosen by the library's autotuner at plan creation
-    # (outside the timed region; POND_AUTOTUNE_CACHE, if set, holds it)
+    # (outside the timed region; POND_AUTOTUNE_CACHE, if set, holds it),
+    # unless given (--max-batch, for counter runs with a fixed launch shape)
     plan = P.Plan(F0, BW, DM, NFFT, NBINS, PERIOD, precision=precision, subint_nsamp=SUBINT, decim=DECIM,
-                  max_batch=P.POND_BATCH_AUTOTUNE)
+                  max_batch=max_batch if max_batch > 0 else P.POND_BATCH_AUTOTUNE)
     info = plan.info()
-    tune = plan.autotune()
+    tune = plan.autotune() if max_batch <= 0 else None
     nsamp = x.numel() // 2
     nprof, nout = P.pond_plan_expect(plan.handle, nsamp, SUBINT)
     prof = torch.empty((nprof + 1, NBINS), dtype=torch.float32, device=x.device)
@@ -317,7 +319,9 @@ def main_search(args):
     log(f"generated {SEARCH_NSAMP} samples in {time.perf_counter() - t:.1f} s")
     x = torch.from_numpy(iq).to("cuda:0")
     dms = [0.5 * i for i in range(128)]
-    forms = [f for f in args.forms.split(",") if f]
+    # the search takes the four single-DM forms (bfloat16 storage is a
+    # plan-only reported variant)
+    forms = [f for f in args.forms.split(",") if f and f != "bf16"]
     res = {}
     for f in forms:
         res[f] = run_search(f, x, dms, args.steps, args.warmup)
@@ -714,6 +718,8 @@ def main():
                          "two-channel input path")
     ap.add_argument("--serve-seconds", type=int, default=8, help="paced serving run length (s)")
     ap.add_argument("--serve-burst-blocks", type=int, default=8, help="1 s blocks per stream in the saturated run")
+    ap.add_argument("--max-batch", type=int, default=0,
+                    help="blocks per launch (default: the library's autotuner picks them)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size "
                          "reference for HBM byte counters)")
@@ -758,7 +764,7 @@ def main():
     forms = [f for f in args.forms.split(",") if f]
     res = {}
     for f in forms:
-        res[f] = run_form(f, x, args.steps, args.warmup, graph=args.graph)
+        res[f] = run_form(f, x, args.steps, args.warmup, graph=args.graph, max_batch=args.max_batch)
         log(f"{f}: {res[f]['ms_per_step']:.3f} ms/step  kernels {res[f]['kernels']}")
 
     # headline: the fastest float16 form (bfloat16 storage is a reported
@@ -777,7 +783,9 @@ def main():
     algo = algorithmic_bytes(dom, blocks, elem, NFFT, hop)
     achieved = algo / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     avg_s = ms / 1e3 / max(launches, 1)
-    meas = measured_traffic(dom, head) if head != "fp32" else None
+    per_block = measured_traffic(dom, head)
+    bpl = blocks / max(launches, 1)
+    meas = int(sum(per_block) * bpl) if per_block else None
     copy_gbs = copy_bandwidth()
     log(f"library streaming copy: {copy_gbs:.0f} GB/s")
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -794,10 +802,12 @@ def main():
         tu = r["tune"]
         forms_out[f] = dict(value=round(v, 2), xrealtime=round(v / 16.0, 1), ms_per_step=round(r["ms_per_step"], 3),
                             kernel_ms_per_step={k: round(kv[0] / args.steps, 4) for k, kv in r["kernels"].items()},
-                            autotune=dict(batch=tu["batch"], ms_per_block=round(tu["ms_per_block"], 4),
-                                          default_batch=tu["default_batch"],
-                                          default_ms_per_block=round(tu["default_ms_per_block"], 4),
-                                          from_cache=tu["from_cache"]))
+                            blocks_per_launch=r["info"]["max_batch"])
+        if tu:
+            forms_out[f]["autotune"] = dict(batch=tu["batch"], ms_per_block=round(tu["ms_per_block"], 4),
+                                            default_batch=tu["default_batch"],
+                                            default_ms_per_block=round(tu["default_ms_per_block"], 4),
+                                            from_cache=tu["from_cache"])
         if "graph_ms_per_step" in r:
             forms_out[f]["graph_ms_per_step"] = round(r["graph_ms_per_step"], 3)
 
