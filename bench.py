@@ -99,12 +99,22 @@ def copy_bandwidth(nbytes=1 << 31, reps=10):
 
 
 def kernel_source_hash():
-    """sha256[:16] over the HIP/C++ sources of the library (as recorded in
-    the committed rocprofv3 summaries)."""
+    """sha256[:16] over the device code of the library: the .hip sources and
+    the headers they include, transitively (as recorded in the committed
+    rocprofv3 summaries; host-only changes leave it as it is)."""
     import hashlib
+    import re
     d = os.path.join(ROOT, "paper_1503_01405_amd", "csrc")
+    files = {f for f in os.listdir(d) if f.endswith(".hip")}
+    todo = sorted(files)
+    while todo:
+        with open(os.path.join(d, todo.pop()), encoding="utf-8") as fh:
+            for inc in re.findall(r'^#include "([^"]+)"', fh.read(), re.M):
+                if inc not in files and os.path.exists(os.path.join(d, inc)):
+                    files.add(inc)
+                    todo.append(inc)
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
+    for f in sorted(files):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -123,7 +133,7 @@ def measured_traffic(kernel_prefix, form):
         lines = fh.read().splitlines()
     for ln in lines:
         if ln.startswith("kernel source sha256[:16]:"):
-            src = ln.rsplit(":", 1)[1].strip()
+            src = ln.split("]:", 1)[1].split()[0]
     if src != kernel_source_hash():
         return None
     for ln in lines:

@@ -187,8 +187,11 @@ pond_plan* pond_plan_create(double f0_mhz, double bw_mhz, double dm,
  * POND_MIXED_VALU, POND_HALF or POND_BF16) and a cap on overlap-save blocks
  * per launch:
  * max_batch > 0 is used as given; POND_BATCH_AUTOTUNE has the plan time its
- * own launch sequence (K1, middle pass, K3, fold) on pseudo-random int8
- * input at 1, 2, 3, 4, 6, 8, 12, 16, 24 and 32 blocks per launch (those
+ * own launch sequence (K1, middle pass, K3 with the series, fold) on
+ * pseudo-random int8 input streamed from a ring of 1 GiB (temporarily
+ * allocated, less if the device lacks six times that free; each timed
+ * run reads samples that no earlier run left in the caches) at 1, 2, 3,
+ * 4, 6, 8, 12, 16, 24 and 32 blocks per launch (those
  * whose work area fits in min(4 GiB, a third of the free device memory),
  * plus the default) during creation and
  * keep the fastest per block, a larger launch winning only by more than 2%;

@@ -243,7 +243,7 @@ hipError_t run_middle(const pond_plan* p, void* work, int nb, hipStream_t stream
 // One launch sequence of a complex-input plan (K1, middle pass, K3, fold
 // reduction) over blocks 0 .. nb-1 of `in`, with one open sub-integration
 // and no series: what the autotuner times.  Null stream.
-hipError_t run_blocks(pond_plan* p, void* work, const int8_t* in, int nb) {
+hipError_t run_blocks(pond_plan* p, void* work, const int8_t* in, int nb, float* series) {
     K1Args a1{};
     a1.tail = in;
     a1.tail_start = 0;
@@ -270,7 +270,8 @@ hipError_t run_blocks(pond_plan* p, void* work, const int8_t* in, int nb) {
     a3.tw2 = p->tw2;
     a3.scale = 1.0f;
     a3.pscale = p->pscale;
-    a3.series = nullptr;
+    a3.series = series;
+    a3.series_base = 0;
     a3.decim = 16;
     a3.nbins = p->nbins;
     a3.inv_pfs = p->inv_pfs;
@@ -310,11 +311,18 @@ hipError_t tune_plan(pond_plan* p) {
     const int nb_max = cand.back();
     void* work = nullptr;
     int8_t* in = nullptr;
-    const int64_t in_bytes = ((int64_t)(nb_max - 1) * p->hop + p->nfft) * p->bpe;
+    float* series = nullptr;
+    // The input streams through a ring several times the size of the
+    // Infinity Cache, so that each timed run reads samples no earlier run
+    // left in the caches (as a recorded stream is read); the work area is
+    // reused from run to run, as in a call.
+    const TuneRing ring = tune_ring(p->nfft, p->hop, p->bpe, nb_max, (int64_t)(free_b / 6));
+    const int64_t ser_floats = (int64_t)nb_max * (p->hop / 16 + 1);
     e = hipMalloc(&work, (size_t)nb_max * block_bytes);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&in), (size_t)((in_bytes + 7) & ~7ll));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&in), (size_t)ring.bytes);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&series), (size_t)ser_floats * sizeof(float));
     if (e == hipSuccess)
-        e = launch_fill_noise_u64(reinterpret_cast<uint64_t*>(in), (in_bytes + 7) / 8, 0x706f6e64ull, nullptr);
+        e = launch_fill_noise_u64(reinterpret_cast<uint64_t*>(in), ring.bytes / 8, 0x706f6e64ull, nullptr);
     if (e == hipSuccess) {
         TuneKey key;
         key.path = "dedisperse";
@@ -322,11 +330,18 @@ hipError_t tune_plan(pond_plan* p) {
         key.precision = p->precision;
         key.kind = p->kind;
         key.global_hist = p->nbins > p->hist_cap;
-        e = autotune_batch(key, cand, dflt, [&](int nb) { return run_blocks(p, work, in, nb); }, &p->tune);
+        int64_t runs = 0;
+        e = autotune_batch(key, cand, dflt,
+                           [&](int nb) {
+                               const int64_t b0 = ring.start(runs++, nb);
+                               return run_blocks(p, work, in + b0 * p->hop * p->bpe, nb, series);
+                           },
+                           &p->tune);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (work) (void)hipFree(work);
     if (in) (void)hipFree(in);
+    if (series) (void)hipFree(series);
     if (e == hipSuccess) {
         p->max_batch = p->tune.batch;
         p->tuned = true;

@@ -201,12 +201,13 @@ hipError_t tune_group(pond_search* s, Group& g, int default_batch) {
     const int nb_max = cand.back();
     void *spec = nullptr, *out = nullptr;
     int8_t* in = nullptr;
-    const int64_t in_bytes = ((int64_t)(nb_max - 1) * g.hop + g.nfft) * 2;
+    // input streamed through a ring larger than the caches (TuneRing)
+    const TuneRing ring = tune_ring(g.nfft, g.hop, 2, nb_max, (int64_t)(free_b / 6));
     e = hipMalloc(&spec, (size_t)nb_max * g.nfft * s->elem);
     if (e == hipSuccess) e = hipMalloc(&out, (size_t)nb_max * g.nfft * s->elem);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&in), (size_t)((in_bytes + 7) & ~7ll));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&in), (size_t)ring.bytes);
     if (e == hipSuccess)
-        e = launch_fill_noise_u64(reinterpret_cast<uint64_t*>(in), (in_bytes + 7) / 8, 0x706f6e64ull, nullptr);
+        e = launch_fill_noise_u64(reinterpret_cast<uint64_t*>(in), ring.bytes / 8, 0x706f6e64ull, nullptr);
     if (e == hipSuccess) {
         TuneKey key;
         key.path = "search2";
@@ -214,8 +215,10 @@ hipError_t tune_group(pond_search* s, Group& g, int default_batch) {
         key.precision = s->precision;
         key.kind = POND_INPUT_COMPLEX;
         key.global_hist = s->nbins > hist_capacity(g.log2n2, s->precision);
+        int64_t runs = 0;
         e = autotune_batch(key, cand, default_batch,
-                           [&](int nb) { return run_group(s, g, spec, out, in, 0, nb, 2, nullptr); }, &g.tune);
+                           [&](int nb) { return run_group(s, g, spec, out, in, ring.start(runs++, nb), nb, 2, nullptr); },
+                           &g.tune);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (spec) (void)hipFree(spec);

@@ -35,7 +35,7 @@ std::string device_tag(int dev) {
 
 std::string key_line(const TuneKey& k, const std::string& dev) {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "pond-tune-1 %s %s nfft=%lld form=%d kind=%d hist=%s", dev.c_str(), k.path,
+    std::snprintf(buf, sizeof buf, "pond-tune-2 %s %s nfft=%lld form=%d kind=%d hist=%s", dev.c_str(), k.path,
                   (long long)k.nfft, k.precision, k.kind, k.global_hist ? "global" : "lds");
     return buf;
 }
@@ -135,6 +135,18 @@ hipError_t autotune_batch(const TuneKey& key, const std::vector<int>& candidates
     out->from_cache = false;
     if (path && *path) cache_store(path, k, *out);
     return hipSuccess;
+}
+
+TuneRing tune_ring(int64_t nfft, int64_t hop, int64_t bytes_per_sample, int nb_max, int64_t spare_bytes) {
+    const int64_t span = ((int64_t)(nb_max - 1) * hop + nfft) * bytes_per_sample;  // one run of nb_max
+    int64_t want = (int64_t)1 << 30;
+    if (want > spare_bytes) want = spare_bytes;
+    if (want < span) want = span;
+    TuneRing r;
+    r.blocks = (want / bytes_per_sample - nfft) / hop + 1;
+    if (r.blocks < nb_max) r.blocks = nb_max;
+    r.bytes = (((r.blocks - 1) * hop + nfft) * bytes_per_sample + 7) & ~(int64_t)7;
+    return r;
 }
 
 std::vector<int> batch_candidates(int64_t block_bytes, int64_t cap_bytes, int default_batch) {

@@ -35,6 +35,18 @@ struct TuneResult {
 hipError_t autotune_batch(const TuneKey& key, const std::vector<int>& candidates, int default_batch,
                           const std::function<hipError_t(int)>& run, TuneResult* out);
 
+// The tuner's input: a ring of pseudo-random int8 samples of at least 1 GiB
+// (four times the 256 MB Infinity Cache; less only where the device has
+// not that much to spare), through which successive runs advance, so that
+// every run reads input that the caches do not hold.
+struct TuneRing {
+    int64_t bytes = 0;   // allocation, a multiple of 8
+    int64_t blocks = 0;  // overlap-save blocks the ring holds
+    // first block of run `run` of nb blocks
+    int64_t start(int64_t run, int nb) const { return (run * nb) % (blocks - nb + 1); }
+};
+TuneRing tune_ring(int64_t nfft, int64_t hop, int64_t bytes_per_sample, int nb_max, int64_t spare_bytes);
+
 // 1, 2, 3, 4, 6, 8, 12, 16, 24, 32 blocks where they fit in cap_bytes (1
 // always), plus the default.
 std::vector<int> batch_candidates(int64_t block_bytes, int64_t cap_bytes, int default_batch);
