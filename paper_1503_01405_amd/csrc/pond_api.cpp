@@ -243,7 +243,7 @@ hipError_t run_middle(const pond_plan* p, void* work, int nb, hipStream_t stream
 // One launch sequence of a complex-input plan (K1, middle pass, K3, fold
 // reduction) over blocks 0 .. nb-1 of `in`, with one open sub-integration
 // and no series: what the autotuner times.  Null stream.
-hipError_t run_blocks(pond_plan* p, void* work, const int8_t* in, int nb, float* series) {
+hipError_t run_blocks(pond_plan* p, void* work, const int8_t* in, int nb, float* series, ReduceQueue& rq) {
     K1Args a1{};
     a1.tail = in;
     a1.tail_start = 0;
@@ -279,17 +279,30 @@ hipError_t run_blocks(pond_plan* p, void* work, const int8_t* in, int nb, float*
     a3.s_base = 0;
     a3.entries = p->nbins;
     a3.global_mode = global_mode ? 1 : 0;
-    a3.part_sum = p->part_sum;
-    a3.part_cnt = p->part_cnt;
     a3.acc_sum = p->acc_sum;
     a3.acc_cnt = p->acc_cnt;
     a3.acc_s0 = 0;
     a3.status = reinterpret_cast<uint32_t*>(p->status);
     const size_t dyn = global_mode ? 0 : (size_t)p->nbins * 12;
     const int grid = k3_grid(p->log2n2, p->precision, dyn, (int64_t)nb << (p->log2n1 - 4), p->nbins, global_mode);
+    // fold reductions queued as in a call
+    const bool deferred = !global_mode && (int64_t)grid * p->nbins <= kPartRegion;
+    if (!global_mode && !deferred) e = rq.flush(nullptr);
+    if (e != hipSuccess) return e;
+    a3.part_sum = deferred ? rq.part_sum(p->part_sum) : p->part_sum;
+    a3.part_cnt = deferred ? rq.part_cnt(p->part_cnt) : p->part_cnt;
     e = launch_k3(p->precision, p->log2n2, a3, grid, dyn, nullptr);
-    if (e == hipSuccess && !global_mode)
-        e = launch_fold_reduce(p->part_sum, p->part_cnt, grid, p->nbins, p->acc_sum, p->acc_cnt, 0, nullptr);
+    if (e == hipSuccess && !global_mode) {
+        const ReduceJob job{a3.part_sum, a3.part_cnt, p->acc_sum, p->acc_cnt, 0, grid, p->nbins};
+        if (deferred) {
+            e = rq.push(job, nullptr);
+        } else {
+            ReduceBatch one;
+            one.job[0] = job;
+            one.n = 1;
+            e = launch_fold_reduce_batch(one, nullptr);
+        }
+    }
     return e;
 }
 
@@ -331,12 +344,14 @@ hipError_t tune_plan(pond_plan* p) {
         key.kind = p->kind;
         key.global_hist = p->nbins > p->hist_cap;
         int64_t runs = 0;
+        ReduceQueue rq;
         e = autotune_batch(key, cand, dflt,
                            [&](int nb) {
                                const int64_t b0 = ring.start(runs++, nb);
-                               return run_blocks(p, work, in + b0 * p->hop * p->bpe, nb, series);
+                               return run_blocks(p, work, in + b0 * p->hop * p->bpe, nb, series, rq);
                            },
                            &p->tune);
+        if (e == hipSuccess) e = rq.flush(nullptr);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (work) (void)hipFree(work);
@@ -1004,6 +1019,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
     const float k3_scale = 1.0f;
 
     int64_t b = p->blocks_done;
+    ReduceQueue rq;
     while (b < nb_total) {
         int64_t nb = nb_total - b < p->max_batch ? nb_total - b : p->max_batch;
         int64_t s_lo = 0, nsub = 1;
@@ -1090,27 +1106,48 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a3.s_base = s_lo;
         a3.entries = (int32_t)entries;
         a3.global_mode = global_mode ? 1 : 0;
-        a3.part_sum = p->part_sum;
-        a3.part_cnt = p->part_cnt;
         a3.acc_sum = p->acc_sum;
         a3.acc_cnt = p->acc_cnt;
         a3.acc_s0 = s_open;
         a3.status = reinterpret_cast<uint32_t*>(p->status);
         const size_t dyn = global_mode ? 0 : (size_t)entries * 12;
         const int grid = k3_grid(n2log, p->precision, dyn, nb * (n1 / 16), entries, global_mode);
+        // Partials in the next quarter of the buffers with a queued reduction
+        // when they fit there; otherwise the whole buffers, reduced at once
+        // (after the queued reductions, which read them).
+        const bool deferred = !global_mode && (int64_t)grid * entries <= kPartRegion;
+        if (!global_mode && !deferred && rq.pending()) {
+            e = timed(3, 0, [&] { return rq.flush(stream); });
+            if (e != hipSuccess) return fail(e);
+        }
+        a3.part_sum = deferred ? rq.part_sum(p->part_sum) : p->part_sum;
+        a3.part_cnt = deferred ? rq.part_cnt(p->part_cnt) : p->part_cnt;
         e = timed(2, nb, [&] {
             return real ? launch_k3_real(p->precision, n2log, a3, (int)grid, dyn, stream)
                         : launch_k3(p->precision, n2log, a3, (int)grid, dyn, stream);
         });
         if (e != hipSuccess) return fail(e);
         if (!global_mode) {
-            e = timed(3, nb, [&] {
-                return launch_fold_reduce(p->part_sum, p->part_cnt, (int)grid, (int)entries, p->acc_sum, p->acc_cnt,
-                                          (s_lo - s_open) * nbins, stream);
-            });
+            const ReduceJob job{a3.part_sum, a3.part_cnt, p->acc_sum, p->acc_cnt, (s_lo - s_open) * nbins,
+                                (int32_t)grid, (int32_t)entries};
+            if (deferred && !rq.push_flushes()) {
+                e = rq.push(job, stream);  // queued: nothing launched yet
+            } else {
+                e = timed(3, nb, [&] {
+                    if (deferred) return rq.push(job, stream);
+                    ReduceBatch one;
+                    one.job[0] = job;
+                    one.n = 1;
+                    return launch_fold_reduce_batch(one, stream);
+                });
+            }
             if (e != hipSuccess) return fail(e);
         }
         b += nb;
+    }
+    if (rq.pending()) {
+        e = timed(3, 0, [&] { return rq.flush(stream); });
+        if (e != hipSuccess) return fail(e);
     }
 
     if (n_complete > 0) {

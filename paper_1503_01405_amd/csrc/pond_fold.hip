@@ -2,6 +2,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -45,6 +46,44 @@ __global__ void __launch_bounds__(256) fold_reduce(const uint64_t* __restrict__ 
     if (n) {
         atomicAdd((unsigned long long*)&acc_sum[acc_off + i], (unsigned long long)s);
         atomicAdd((unsigned long long*)&acc_cnt[acc_off + i], (unsigned long long)n);
+    }
+}
+
+// The same for up to kReduceSlots queued launches at once (blockIdx.z
+// picks the launch; each has its own partials, accumulators and sizes).
+__global__ void __launch_bounds__(256) fold_reduce_batch(ReduceBatch b) {
+    const ReduceJob& j = b.job[blockIdx.z];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= j.entries) return;
+    const int p0 = blockIdx.y * kReduceChunk;
+    if (p0 >= j.nparts) return;
+    const int p1 = min(j.nparts, p0 + kReduceChunk);
+    const uint64_t* ps = j.part_sum;
+    const uint32_t* pc = j.part_cnt;
+    const int entries = j.entries;
+    uint64_t s = 0, n = 0;
+    if (p1 - p0 == kReduceChunk) {
+        uint64_t sv[kReduceChunk];
+        uint32_t nv[kReduceChunk];
+#pragma unroll
+        for (int k = 0; k < kReduceChunk; ++k) {
+            sv[k] = ps[(int64_t)(p0 + k) * entries + i];
+            nv[k] = pc[(int64_t)(p0 + k) * entries + i];
+        }
+#pragma unroll
+        for (int k = 0; k < kReduceChunk; ++k) {
+            s += sv[k];
+            n += nv[k];
+        }
+    } else {
+        for (int q = p0; q < p1; ++q) {
+            s += ps[(int64_t)q * entries + i];
+            n += pc[(int64_t)q * entries + i];
+        }
+    }
+    if (n) {
+        atomicAdd((unsigned long long*)&j.acc_sum[j.acc_off + i], (unsigned long long)s);
+        atomicAdd((unsigned long long*)&j.acc_cnt[j.acc_off + i], (unsigned long long)n);
     }
 }
 
@@ -137,6 +176,19 @@ hipError_t launch_fold_reduce(const uint64_t* ps, const uint32_t* pc, int nparts
                               uint64_t* acc_cnt, int64_t acc_off, hipStream_t s) {
     dim3 grid((entries + 255) / 256, (nparts + kReduceChunk - 1) / kReduceChunk);
     hipLaunchKernelGGL(fold_reduce, grid, dim3(256), 0, s, ps, pc, nparts, entries, acc_sum, acc_cnt, acc_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_reduce_batch(const ReduceBatch& b, hipStream_t s) {
+    if (b.n < 1 || b.n > kReduceSlots) return hipErrorInvalidValue;
+    int entries = 0, nparts = 0;
+    for (int k = 0; k < b.n; ++k) {
+        entries = std::max(entries, (int)b.job[k].entries);
+        nparts = std::max(nparts, (int)b.job[k].nparts);
+    }
+    if (entries <= 0 || nparts <= 0) return hipSuccess;
+    const dim3 grid((entries + 255) / 256, (nparts + kReduceChunk - 1) / kReduceChunk, b.n);
+    hipLaunchKernelGGL(fold_reduce_batch, grid, dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

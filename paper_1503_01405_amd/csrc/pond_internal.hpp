@@ -213,6 +213,49 @@ hipError_t launch_fold_profiles(const uint64_t* acc_sum, const uint64_t* acc_cnt
                                 hipStream_t s);
 
 constexpr int64_t kPartEntries = 1 << 21;  // per-workgroup fold partials: grid * entries <= this
+
+// Deferred fold reductions.  A K3 launch whose partials fit in a quarter
+// of the partial buffers writes them to the next free quarter and queues
+// its reduction; the queued reductions run as one launch when four are
+// pending, before a launch that needs the whole buffer, and before anything
+// reads the accumulators (integer sums: the order does not change a bit).
+constexpr int kReduceSlots = 4;
+constexpr int64_t kPartRegion = kPartEntries / kReduceSlots;
+struct ReduceJob {
+    const uint64_t* part_sum;  // nparts x entries partials, part-major
+    const uint32_t* part_cnt;
+    uint64_t* acc_sum;  // accumulators; entry i goes to acc_off + i
+    uint64_t* acc_cnt;
+    int64_t acc_off;
+    int32_t nparts;
+    int32_t entries;
+};
+struct ReduceBatch {
+    ReduceJob job[kReduceSlots];
+    int32_t n = 0;
+};
+hipError_t launch_fold_reduce_batch(const ReduceBatch& b, hipStream_t s);
+class ReduceQueue {
+   public:
+    // partial buffers of the next queued launch (a quarter of the full ones)
+    uint64_t* part_sum(uint64_t* full) const { return full + (int64_t)b_.n * kPartRegion; }
+    uint32_t* part_cnt(uint32_t* full) const { return full + (int64_t)b_.n * kPartRegion; }
+    bool pending() const { return b_.n > 0; }
+    bool push_flushes() const { return b_.n + 1 == kReduceSlots; }
+    hipError_t push(const ReduceJob& j, hipStream_t s) {
+        b_.job[b_.n++] = j;
+        return b_.n == kReduceSlots ? flush(s) : hipSuccess;
+    }
+    hipError_t flush(hipStream_t s) {
+        if (b_.n == 0) return hipSuccess;
+        const hipError_t e = launch_fold_reduce_batch(b_, s);
+        b_.n = 0;
+        return e;
+    }
+
+   private:
+    ReduceBatch b_;
+};
 // Workgroups of a K3 launch: enough to fill the chip at the occupancy the
 // LDS allows, at most one per item, a multiple of 8, and within the
 // partial-histogram budget.

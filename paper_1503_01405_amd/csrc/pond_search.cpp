@@ -107,7 +107,7 @@ void trial_geometry(double f0, double bw, double dm, int64_t* n_front, int64_t* 
 // the first `ntr` trials of the group the inverse rows into `out`, K3 and
 // the fold reduction into that trial's accumulators.
 hipError_t run_group(const pond_search* s, const Group& g, void* spec, void* out, const int8_t* iq, int64_t block0,
-                     int nb, size_t ntr, hipStream_t stream) {
+                     int nb, size_t ntr, hipStream_t stream, ReduceQueue& rq) {
     const int32_t nbins = s->nbins;
     const int64_t n1 = (int64_t)1 << g.log2n1;
     const int64_t cap = hist_capacity(g.log2n2, s->precision);
@@ -170,18 +170,30 @@ hipError_t run_group(const pond_search* s, const Group& g, void* spec, void* out
         a3.s_base = 0;
         a3.entries = nbins;
         a3.global_mode = global_mode ? 1 : 0;
-        a3.part_sum = s->part_sum;
-        a3.part_cnt = s->part_cnt;
         a3.acc_sum = s->acc_sum + (int64_t)t * nbins;
         a3.acc_cnt = s->acc_cnt + (int64_t)t * nbins;
         a3.acc_s0 = 0;
         a3.status = reinterpret_cast<uint32_t*>(s->status);
         const size_t dyn = global_mode ? 0 : (size_t)nbins * 12;
         const int grid = k3_grid(g.log2n2, s->precision, dyn, (int64_t)nb * (n1 / 16), nbins, global_mode);
+        // the trials' fold reductions are queued (ReduceQueue), four per launch
+        const bool deferred = !global_mode && (int64_t)grid * nbins <= kPartRegion;
+        if (!global_mode && !deferred) e = rq.flush(stream);
+        if (e != hipSuccess) return e;
+        a3.part_sum = deferred ? rq.part_sum(s->part_sum) : s->part_sum;
+        a3.part_cnt = deferred ? rq.part_cnt(s->part_cnt) : s->part_cnt;
         e = launch_k3(s->precision, g.log2n2, a3, grid, dyn, stream);
         if (e != hipSuccess) return e;
         if (!global_mode) {
-            e = launch_fold_reduce(s->part_sum, s->part_cnt, grid, nbins, a3.acc_sum, a3.acc_cnt, 0, stream);
+            const ReduceJob job{a3.part_sum, a3.part_cnt, a3.acc_sum, a3.acc_cnt, 0, grid, nbins};
+            if (deferred) {
+                e = rq.push(job, stream);
+            } else {
+                ReduceBatch one;
+                one.job[0] = job;
+                one.n = 1;
+                e = launch_fold_reduce_batch(one, stream);
+            }
             if (e != hipSuccess) return e;
         }
     }
@@ -216,9 +228,12 @@ hipError_t tune_group(pond_search* s, Group& g, int default_batch) {
         key.kind = POND_INPUT_COMPLEX;
         key.global_hist = s->nbins > hist_capacity(g.log2n2, s->precision);
         int64_t runs = 0;
-        e = autotune_batch(key, cand, default_batch,
-                           [&](int nb) { return run_group(s, g, spec, out, in, ring.start(runs++, nb), nb, 2, nullptr); },
-                           &g.tune);
+        ReduceQueue rq;
+        e = autotune_batch(
+            key, cand, default_batch,
+            [&](int nb) { return run_group(s, g, spec, out, in, ring.start(runs++, nb), nb, 2, nullptr, rq); },
+            &g.tune);
+        if (e == hipSuccess) e = rq.flush(nullptr);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (spec) (void)hipFree(spec);
@@ -432,14 +447,17 @@ int32_t pond_search_run(pond_search* s, const int8_t* iq, int64_t nsamp, float* 
     if (e == hipSuccess) e = launch_zero_u64(s->acc_cnt, (int64_t)s->ntrials * nbins, stream);
     if (e != hipSuccess) return fail();
 
+    ReduceQueue rq;
     for (auto& g : s->groups) {
         const int64_t nb_total = nsamp < g.nfft ? 0 : (nsamp - g.nfft) / g.hop + 1;
         for (int64_t b = 0; b < nb_total; b += g.max_batch) {
             const int nb = (int)(nb_total - b < g.max_batch ? nb_total - b : g.max_batch);
-            e = run_group(s, g, g.spec, g.out, iq, b, nb, g.trials.size(), stream);
+            e = run_group(s, g, g.spec, g.out, iq, b, nb, g.trials.size(), stream, rq);
             if (e != hipSuccess) return fail();
         }
     }
+    e = rq.flush(stream);
+    if (e != hipSuccess) return fail();
     e = launch_fold_profiles(s->acc_sum, s->acc_cnt, (int64_t)s->ntrials * nbins, profiles, stream);
     if (e != hipSuccess) return fail();
     s->last_stream = stream;
