@@ -57,14 +57,20 @@ template <class T>
 __device__ __forceinline__ T* at(T* base, uint32_t byte_off) {
     return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
 }
-// A pointer that is the same in every lane, moved to scalar registers, so
-// that bases derived from it stay scalar.
+// A pointer into global memory that is the same in every lane, moved to
+// scalar registers, so that bases derived from it stay scalar.  It is
+// rebuilt as a global-address-space pointer: accesses through a pointer
+// made from an integer would otherwise be flat ones, which also count as
+// LDS operations, so that every wait for an LDS result would wait for them
+// too.
 template <class T>
 __device__ __forceinline__ T* uniform_ptr(T* p) {
+    using G = __attribute__((address_space(1))) T;
     const uint64_t v = reinterpret_cast<uint64_t>(p);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+    G* g = reinterpret_cast<G*>(((uint64_t)hi << 32) | lo);
+    return (T*)g;
 }
 // Hide a value from the optimiser so that expressions depending on it are
 // recomputed where used instead of being hoisted and kept in registers.
