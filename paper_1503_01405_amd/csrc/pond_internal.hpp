@@ -35,6 +35,7 @@ struct K1Args {
     void* work;             // [nblocks][n2][n1] complex, storage type of the form
     const float2* tw2;      // exp(-2 pi i t / n2), t < n2
     float scale;            // power-of-two output scale
+    int32_t chain = 1;      // blocks per workgroup (set by launch_k1)
 };
 
 // K2: four-step twiddle, forward row FFT (length n1), chirp, inverse row

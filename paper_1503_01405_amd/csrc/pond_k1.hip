@@ -136,11 +136,132 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
     }
 }
 
+// The same pass for blocks that overlap by half (hop = N / 2, a discard of
+// N / 2: the production shape and every DM-search group), one workgroup
+// taking its column tile in `chain` consecutive blocks.  Thread j holds rows
+// j + TPV e; block b + 1 starts N / 2 = 8 TPV rows of n1 samples after block
+// b, so its rows with e < 8 are block b's rows with e + 8, already loaded:
+// each block after the first reads only its second half (the input is read
+// (chain + 1) / (2 chain) as often), and those loads are issued before the
+// previous block's transform, so that their latency is hidden behind it.
+// The values and the arithmetic are those of k1_unpack_colfft.
+template <int LOG2N2, class T, int FORM>
+__global__ void __launch_bounds__(1 << LOG2N2)
+    __attribute__((amdgpu_waves_per_eu(FORM == kFormF16 ? 8 : 4)))  // float16: two workgroups per CU
+k1_chain_colfft(K1Args a) {
+    static_assert(FORM == kFormF16 || FORM == kFormF32, "VALU forms");
+    constexpr int L = 1 << LOG2N2;
+    constexpr int TPV = L / 16;
+    constexpr bool H16 = FORM == kFormF16;
+    using V = std::conditional_t<H16, h2, float2>;
+    __shared__ LdsVal<FORM> lds[ColLds<LdsVal<FORM>, true>::kSlots(L)];
+
+    const int n1 = 1 << a.log2n1;
+    const int tiles_per_block = n1 >> 4;
+    const int nchains = (a.nblocks + a.chain - 1) / a.chain;
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    if (logical >= nchains * tiles_per_block) return;
+    const int ch = logical / tiles_per_block;
+    const int t = logical - ch * tiles_per_block;
+    const int bfirst = ch * a.chain;
+    const int bend = min(a.nblocks, bfirst + a.chain);
+    const int c = threadIdx.x & 15;
+    const int j = threadIdx.x >> 4;
+    const int col = 16 * t + c;
+    const uint32_t o0 = opaque((uint32_t)col);
+    const uint32_t uoff = 2u * (o0 + ((uint32_t)j << a.log2n1));
+
+    // raw int8 pairs of values e = E0 .. 15 of block b, which lies in the
+    // carried tail or in the call's input entirely (launch_k1 uses this
+    // pass only then)
+    auto load_raw = [&](int b, auto e0, uint32_t (&r)[16]) {
+        constexpr int E0 = decltype(e0)::value;
+        const int64_t bstart = (a.block0 + b) * a.hop;
+        const int8_t* ub = uniform_ptr(bstart >= a.in_start ? a.in + 2 * (bstart - a.in_start)
+                                                            : a.tail + 2 * (bstart - a.tail_start));
+#pragma unroll
+        for (int e = E0; e < 16; ++e)
+            r[e] = *reinterpret_cast<const uint16_t*>(at(ub + ((int64_t)(2 * TPV * e) << a.log2n1), uoff));
+    };
+    // int8 pair -> value (packed float16: exact, scaled by 1/16 as in
+    // k1_unpack_colfft; float32: exact)
+    auto unpack = [](uint32_t s) -> V {
+        if constexpr (H16) {
+            const uint32_t w = ((s & 0xffu) | ((s & 0xff00u) << 8)) ^ 0x64806480u;
+            return __builtin_elementwise_fma(__builtin_bit_cast(h2, w), h2{(_Float16)0.0625f, (_Float16)0.0625f},
+                                             h2{(_Float16)-72.0f, (_Float16)-72.0f});
+        } else {
+            return make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)((s >> 8) & 0xff));
+        }
+    };
+
+    StageBases<LOG2N2, V> tb;
+    tb.load(j, a.tw2);
+    __shared__ __align__(16) h2 ttab[H16 ? TwTab<LOG2N2>::kSize : 1];
+    if constexpr (H16) {
+        if (threadIdx.x < 64) fill_twiddle_tables<LOG2N2, 64>(ttab, a.tw2, threadIdx.x);  // one wave
+    }
+    const uint32_t woff = (opaque((uint32_t)col) + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(T);
+
+    uint32_t r[16];
+    load_raw(bfirst, std::integral_constant<int, 0>{}, r);
+    V v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = unpack(r[e]);
+    for (int b = bfirst; b < bend; ++b) {
+        V keep[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) keep[e] = v[e + 8];
+        if (b + 1 < bend) load_raw(b + 1, std::integral_constant<int, 8>{}, r);
+        // lead barrier: the previous block's transform may still be read
+        if constexpr (H16) fft_wg<LOG2N2, -1, true, 2, true>(v, j, tb, ColLds<h2, true>{lds + c}, ttab);
+        else fft_wg<LOG2N2, -1, false, false, true>(v, j, tb, ColLds<float2, true>{lds + c});
+        T* const ob = uniform_ptr(reinterpret_cast<T*>(a.work) + ((int64_t)b << (a.log2n1 + LOG2N2)));
+        if constexpr (H16) {
+            constexpr float osc = 1.0f / (float)(1 << Sched<LOG2N2>::kHalfRem);
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                st_h2(at(ob + ((int64_t)(TPV * e) << a.log2n1), woff), v[e] * (_Float16)osc);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                Elem<T>::store(at(ob + ((int64_t)(TPV * e) << a.log2n1), woff), cscale(v[e], a.scale));
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            v[e] = keep[e];
+            v[e + 8] = unpack(r[e + 8]);
+        }
+    }
+}
+
 // ---------------------------------------------------------- launchers
+// Blocks per workgroup of the chained pass: at most kK1Chain, the launch's
+// blocks spread evenly over the chains.
+constexpr int kK1Chain = 4;
+
 template <class T, int FORM, int LOG2N2>
 static hipError_t k1_one(const K1Args& a, hipStream_t s) {
-    const int ntiles = a.nblocks * ((1 << a.log2n1) >> 4);
-    const int grid = (ntiles + 7) & ~7;
+    const int tiles_per_block = (1 << a.log2n1) >> 4;
+    // half-overlapping blocks: the chained pass (VALU forms)
+    // half-overlapping blocks, none straddling the end of the carried tail
+    const int64_t n = (int64_t)1 << (a.log2n1 + LOG2N2);
+    const int64_t first = a.block0 * a.hop, last = (a.block0 + a.nblocks - 1) * a.hop;
+    // (the blocks cover [first, last + n) without gaps, so a tail end
+    // strictly inside that range falls strictly inside some block)
+    const bool straddle = first < a.in_start && a.in_start < last + n;
+    const bool chained = FORM != kFormMfma && a.nblocks >= 2 && (a.hop << 1) == n && !straddle;
+    if constexpr (FORM != kFormMfma) {
+        if (chained) {
+            K1Args c = a;
+            const int nchains = (a.nblocks + kK1Chain - 1) / kK1Chain;
+            c.chain = (a.nblocks + nchains - 1) / nchains;
+            const int grid = ((a.nblocks + c.chain - 1) / c.chain * tiles_per_block + 7) & ~7;
+            hipLaunchKernelGGL((k1_chain_colfft<LOG2N2, T, FORM>), dim3(grid), dim3(1 << LOG2N2), 0, s, c);
+            return hipGetLastError();
+        }
+    }
+    const int grid = (a.nblocks * tiles_per_block + 7) & ~7;
     hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, FORM>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
     return hipGetLastError();
 }
