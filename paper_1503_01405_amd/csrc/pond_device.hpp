@@ -72,6 +72,30 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
     G* g = reinterpret_cast<G*>(((uint64_t)hi << 32) | lo);
     return (T*)g;
 }
+// Raw buffer accesses (MUBUF): a uniform base and size in a resource
+// descriptor, the lane's 32-bit byte offset in a vector register and a
+// uniform byte offset in a scalar one, so that a thread's accesses at fixed
+// strides from one lane offset cost no vector address arithmetic (global
+// accesses fold such constants into 64-bit vector addresses instead).
+// Accesses at or beyond `bytes` read 0 and write nothing.
+struct BufRes {
+    __amdgpu_buffer_rsrc_t r;
+};
+__device__ __forceinline__ BufRes buf_res(const void* base, uint32_t bytes) {
+    // descriptor word 3 of the gfx9 family: 32-bit data format
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000)};
+}
+template <class V>
+__device__ __forceinline__ V buf_ld(const BufRes& b, uint32_t voff, int soff) {
+    static_assert(sizeof(V) == 4, "32-bit values");
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, soff, 0));
+}
+template <class V>
+__device__ __forceinline__ void buf_st(const BufRes& b, uint32_t voff, int soff, V v) {
+    static_assert(sizeof(V) == 4, "32-bit values");
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.r, (int)voff, soff, 0);
+}
+
 // Hide a value from the optimiser so that expressions depending on it are
 // recomputed where used instead of being hoisted and kept in registers.
 __device__ __forceinline__ uint32_t opaque(uint32_t x) {

@@ -173,9 +173,18 @@ k2_row(K2Args a) {
         const h2* tw4 = reinterpret_cast<const h2*>(a.htw4) + ((int64_t)row0 << LOG2N1);
         const h2* chirp = reinterpret_cast<const h2*>(a.hchirp) + ((int64_t)row0 << LOG2N1);
         const double* geo = a.geo + ((int64_t)row0 << LOG2N1);
-        auto tw_at = [&](uint32_t i) {
-            if constexpr (MODE == kRowFull) return __builtin_bit_cast(h2, at(tab, i * 8u)->x);
-            else return *at(tw4, i * 4u);
+        // Element u + i of the workgroup's rows through buffer descriptors:
+        // u (uniform) is the scalar offset, i the lane's, so that a thread's
+        // 16 accesses share one vector offset per array.
+        constexpr uint32_t kEl = (uint32_t)Sh::ROWS << LOG2N1;  // elements of the rows
+        const BufRes rsrc = buf_res(src, kEl * (uint32_t)sizeof(T));
+        const BufRes rdst = buf_res(dst, kEl * (uint32_t)sizeof(T));
+        const BufRes rtab = buf_res(tab, kEl * 8u);
+        const BufRes rtw4 = buf_res(tw4, kEl * 4u);
+        const BufRes rchirp = buf_res(chirp, kEl * 4u);
+        auto tw_at = [&](int u, uint32_t i) {
+            if constexpr (MODE == kRowFull) return buf_ld<h2>(rtab, i * 8u, u * 8);
+            else return buf_ld<h2>(rtw4, i * 4u, u * 4);
         };
         h2 v[16];
         uint32_t to = opaque(toff);
@@ -183,11 +192,12 @@ k2_row(K2Args a) {
         const uint32_t mxo = opaque(toff - (uint32_t)j + (uint32_t)mx_pos<false, TPV>(j, 0));
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const uint32_t i = MX ? mxo + (uint32_t)(16 * (e >> 2) + (e & 3) * TPV) : to + TPV * e;
-            const h2 x = ld_h2(at(src, i * (uint32_t)sizeof(T)));
-            if constexpr (MODE == kRowInv) v[e] = cmul(x, to_h2(dm_chirp(a.dm, *at(geo, i * 8u))));
+            const int u = MX ? 16 * (e >> 2) + (e & 3) * TPV : TPV * e;
+            const uint32_t i = MX ? mxo : to;
+            const h2 x = buf_ld<h2>(rsrc, i * (uint32_t)sizeof(T), u * (int)sizeof(T));
+            if constexpr (MODE == kRowInv) v[e] = cmul(x, to_h2(dm_chirp(a.dm, *at(geo + u, i * 8u))));
             else if constexpr (MODE == kRowChirp) v[e] = x;
-            else v[e] = cmul(x, tw_at(i));
+            else v[e] = cmul(x, tw_at(u, i));
         }
         // kRowFull: the chirp of each element is fetched during the forward
         // transform's last exchange.
@@ -196,8 +206,8 @@ k2_row(K2Args a) {
             const uint32_t t2 = opaque(toff);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                if constexpr (MODE == kRowChirp) ch[e] = *at(chirp, (t2 + TPV * e) * 4u);
-                else ch[e] = __builtin_bit_cast(h2, at(tab, (t2 + TPV * e) * 8u)->y);
+                if constexpr (MODE == kRowChirp) ch[e] = buf_ld<h2>(rchirp, t2 * 4u, TPV * e * 4);
+                else ch[e] = buf_ld<h2>(rtab, t2 * 8u, TPV * e * 8 + 4);
             }
         };
         if constexpr (MX) {
@@ -215,7 +225,7 @@ k2_row(K2Args a) {
             if (valid) {
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
-                    st_h2(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), v[e] * (_Float16)osc);
+                    buf_st<h2>(rdst, to * (uint32_t)sizeof(T), TPV * e * (int)sizeof(T), v[e] * (_Float16)osc);
             }
             return;
         }
@@ -230,7 +240,7 @@ k2_row(K2Args a) {
             to = opaque(toff);
             if (valid) {
 #pragma unroll
-                for (int e = 0; e < 16; ++e) st_h2(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), v[e]);
+                for (int e = 0; e < 16; ++e) buf_st<h2>(rdst, to * (uint32_t)sizeof(T), TPV * e * (int)sizeof(T), v[e]);
             }
             return;
         }
@@ -240,7 +250,7 @@ k2_row(K2Args a) {
         auto fetch_tw = [&] {
             const uint32_t t2 = opaque(toff);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) wo[e] = tw_at(t2 + TPV * e);
+            for (int e = 0; e < 16; ++e) wo[e] = tw_at(TPV * e, t2);
         };
         if constexpr (MX && MODE == kRowFull)  // input in registers (canonical), moved through LDS
             fft_mx<LOG2N1, +1, false, false, true, true>(v, j, lrow.base, ttab, fetch_tw);
@@ -252,7 +262,7 @@ k2_row(K2Args a) {
         if (valid) {
 #pragma unroll
             for (int e = 0; e < 16; ++e)
-                st_h2(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cmulc(v[e], wo[e]));
+                buf_st<h2>(rdst, to * (uint32_t)sizeof(T), TPV * e * (int)sizeof(T), cmulc(v[e], wo[e]));
         }
         return;
     } else {
@@ -266,10 +276,12 @@ k2_row(K2Args a) {
             RowTw<LOG2N1>::template fill<Sh::ROWS, Sh::THREADS>(rtw, row0, LOG2N1 + a.log2n2, threadIdx.x);
             __syncthreads();
         }
-        auto tw_row = [&](uint32_t i) {
-            if constexpr (OTF) return RowTw<LOG2N1>::at(rtw, i >> LOG2N1, i & ((1u << LOG2N1) - 1u));
-            else {
-                const float4 t = *at(tab4, i * 16u);
+        auto tw_row = [&](int u, uint32_t i) {
+            if constexpr (OTF) {
+                const uint32_t k = i + (uint32_t)u;
+                return RowTw<LOG2N1>::at(rtw, k >> LOG2N1, k & ((1u << LOG2N1) - 1u));
+            } else {
+                const float4 t = *at(tab4 + u, i * 16u);
                 return make_float2(t.x, t.y);
             }
         };
@@ -280,13 +292,13 @@ k2_row(K2Args a) {
         uint32_t to = opaque(toff);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const float2 x = Elem<T>::load(at(src, (to + TPV * e) * (uint32_t)sizeof(T)));
+            const float2 x = Elem<T>::load(at(src + TPV * e, to * (uint32_t)sizeof(T)));
             if constexpr (MODE == kRowFull) {
-                v[e] = cmul(x, tw_row(to + TPV * e));
+                v[e] = cmul(x, tw_row(TPV * e, to));
             } else if constexpr (MODE == kRowFwd) {
-                v[e] = cmul(x, *at(tw4, (to + TPV * e) * 8u));
+                v[e] = cmul(x, *at(tw4 + TPV * e, to * 8u));
             } else if constexpr (MODE == kRowInv) {
-                v[e] = cmul(x, dm_chirp(a.dm, *at(geo, (to + TPV * e) * 8u)));
+                v[e] = cmul(x, dm_chirp(a.dm, *at(geo + TPV * e, to * 8u)));
             } else {
                 v[e] = x;  // kRowInvPlain: the filter was applied before (real input path); kRowChirp
             }
@@ -299,11 +311,11 @@ k2_row(K2Args a) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 if constexpr (MODE == kRowChirp) {
-                    ch[e] = *at(chirp, (t2 + TPV * e) * 8u);
+                    ch[e] = *at(chirp + TPV * e, t2 * 8u);
                 } else if constexpr (OTF) {
-                    ch[e] = *at(tab, (t2 + TPV * e) * 8u);
+                    ch[e] = *at(tab + TPV * e, t2 * 8u);
                 } else {
-                    const float4 t = *at(tab4, (t2 + TPV * e) * 16u);
+                    const float4 t = *at(tab4 + TPV * e, t2 * 16u);
                     ch[e] = make_float2(t.z, t.w);
                 }
             }
@@ -319,7 +331,7 @@ k2_row(K2Args a) {
             if (valid) {
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
-                    Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+                    Elem<T>::store(at(dst + TPV * e, to * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
             }
             return;
         }
@@ -330,7 +342,7 @@ k2_row(K2Args a) {
             if (valid) {
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
-                    Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
+                    Elem<T>::store(at(dst + TPV * e, to * (uint32_t)sizeof(T)), cscale(v[e], a.scale));
             }
             return;
         }
@@ -341,9 +353,9 @@ k2_row(K2Args a) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 if constexpr (MODE == kRowFull) {
-                    wo[e] = tw_row(t2 + TPV * e);
+                    wo[e] = tw_row(TPV * e, t2);
                 } else {
-                    wo[e] = *at(tw4, (t2 + TPV * e) * 8u);
+                    wo[e] = *at(tw4 + TPV * e, t2 * 8u);
                 }
             }
         };
@@ -353,7 +365,7 @@ k2_row(K2Args a) {
         if (valid) {
 #pragma unroll
             for (int e = 0; e < 16; ++e)
-                Elem<T>::store(at(dst, (to + TPV * e) * (uint32_t)sizeof(T)), cscale(cmulc(v[e], wo[e]), a.scale));
+                Elem<T>::store(at(dst + TPV * e, to * (uint32_t)sizeof(T)), cscale(cmulc(v[e], wo[e]), a.scale));
         }
     }
 }
