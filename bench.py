@@ -120,12 +120,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_prefix, form):
+def measured_traffic(kernel_prefix, form, max_batch):
     """HBM bytes per overlap-save block of a kernel (read, written) from the
-    committed counter summary of that form, or None if the summary is
-    missing or was taken on other kernel sources.  Per block, so that it
-    applies whatever blocks per launch the autotuner picked."""
-    path = os.path.join(ROOT, "profiles", f"hbm_bytes_dm50_nfft2e23_{form}.txt")
+    committed counter summary of that form at the run's blocks per launch,
+    or None if there is none or it was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_bytes_dm50_nfft2e23_{form}_b{max_batch}.txt")
     if not os.path.exists(path):
         return None
     src = None
@@ -793,7 +792,7 @@ def main():
     algo = algorithmic_bytes(dom, blocks, elem, NFFT, hop)
     achieved = algo / (ms / 1e3) / 1e9 if ms > 0 else 0.0
     avg_s = ms / 1e3 / max(launches, 1)
-    per_block = measured_traffic(dom, head)
+    per_block = measured_traffic(dom, head, h["info"]["max_batch"])
     bpl = blocks / max(launches, 1)
     meas = int(sum(per_block) * bpl) if per_block else None
     copy_gbs = copy_bandwidth()
