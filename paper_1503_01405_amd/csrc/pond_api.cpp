@@ -256,6 +256,7 @@ hipError_t run_blocks(pond_plan* p, void* work, const int8_t* in, int nb, float*
     a1.work = work;
     a1.tw2 = p->tw2;
     a1.scale = std::ldexp(1.0f, -p->log2n2);
+    a1.f16_cols = 2 * p->hop == p->nfft;
     hipError_t e = launch_k1(p->precision, p->log2n2, a1, nullptr);
     if (e == hipSuccess) e = run_middle(p, work, nb, nullptr);
     if (e != hipSuccess) return e;
@@ -427,6 +428,7 @@ hipError_t half_power_gain(const HalfCal& c, const std::function<hipError_t(int,
         a1.log2n1 = c.log2n1;
         a1.work = c.work;
         a1.tw2 = c.tw2;
+        a1.f16_cols = c.f16_cols;
         e = launch_k1(c.prec, c.log2n2, a1, nullptr);
         const void* mid = nullptr;
         if (e == hipSuccess) e = middle(nb, &mid);
@@ -682,6 +684,7 @@ pond_plan* create_plan(double f0_mhz, double bw_mhz, double dm, int64_t nfft, in
         cal.tw2 = p->tw2;
         cal.work = p->work;
         cal.max_batch = p->max_batch;
+        cal.f16_cols = 2 * p->hop == p->nfft;
         double g = 1.0;
         chk(half_power_gain(
             cal,
@@ -1047,6 +1050,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         a1.work = p->work;
         a1.tw2 = p->tw2;
         a1.scale = k1_scale;
+        a1.f16_cols = 2 * hop == p->nfft;
         const bool real = p->kind != POND_INPUT_COMPLEX;
         e = timed(0, nb, [&] {
             return real ? launch_k1_aip(p->precision, n2log, a1, stream) : launch_k1(p->precision, n2log, a1, stream);

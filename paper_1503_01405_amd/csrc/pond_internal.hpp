@@ -36,6 +36,10 @@ struct K1Args {
     const float2* tw2;      // exp(-2 pi i t / n2), t < n2
     float scale;            // power-of-two output scale
     int32_t chain = 1;      // blocks per workgroup (set by launch_k1)
+    // matrix-core form: 1 = the packed-float16 column pass instead (a
+    // plan's choice where its blocks overlap by half, also for its
+    // calibration, so that every launch of the plan gives the same bits)
+    int32_t f16_cols = 0;
 };
 
 // K2: four-step twiddle, forward row FFT (length n1), chirp, inverse row
@@ -291,6 +295,7 @@ struct HalfCal {
     const float2* tw2 = nullptr;  // exp(-2 pi i t / n2)
     void* work = nullptr;         // max_batch blocks of float16 pairs
     int max_batch = 1;
+    int f16_cols = 0;             // the plan's K1Args::f16_cols
 };
 hipError_t half_power_gain(const HalfCal& c, const std::function<hipError_t(int, const void**)>& middle,
                            double* gain);

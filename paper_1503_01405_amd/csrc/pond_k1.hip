@@ -250,19 +250,29 @@ static hipError_t k1_one(const K1Args& a, hipStream_t s) {
     // (the blocks cover [first, last + n) without gaps, so a tail end
     // strictly inside that range falls strictly inside some block)
     const bool straddle = first < a.in_start && a.in_start < last + n;
-    const bool chained = FORM != kFormMfma && a.nblocks >= 2 && (a.hop << 1) == n && !straddle;
-    if constexpr (FORM != kFormMfma) {
-        if (chained) {
-            K1Args c = a;
-            const int nchains = (a.nblocks + kK1Chain - 1) / kK1Chain;
-            c.chain = (a.nblocks + nchains - 1) / nchains;
-            const int grid = ((a.nblocks + c.chain - 1) / c.chain * tiles_per_block + 7) & ~7;
-            hipLaunchKernelGGL((k1_chain_colfft<LOG2N2, T, FORM>), dim3(grid), dim3(1 << LOG2N2), 0, s, c);
-            return hipGetLastError();
-        }
+    // Where blocks overlap by half, plans of the matrix-core form ask for the
+    // packed-float16 column pass (f16_cols), chained or not: the matrix-core
+    // load layout puts the shifted rows in another thread (32 lanes up),
+    // and keeping them for the hand-off spills, so the chained VALU pass,
+    // which reads half the input, is the faster column pass there (the
+    // matrix cores carry the form's row pass and inverse column pass).
+    const bool half_overlap = (a.hop << 1) == n;
+    const bool mx16 = FORM == kFormMfma && a.f16_cols;
+    const bool chained = a.nblocks >= 2 && half_overlap && !straddle && (FORM != kFormMfma || mx16);
+    constexpr int CFORM = FORM == kFormMfma ? kFormF16 : FORM;
+    if (chained) {
+        K1Args c = a;
+        const int nchains = (a.nblocks + kK1Chain - 1) / kK1Chain;
+        c.chain = (a.nblocks + nchains - 1) / nchains;
+        const int grid = ((a.nblocks + c.chain - 1) / c.chain * tiles_per_block + 7) & ~7;
+        hipLaunchKernelGGL((k1_chain_colfft<LOG2N2, T, CFORM>), dim3(grid), dim3(1 << LOG2N2), 0, s, c);
+        return hipGetLastError();
     }
     const int grid = (a.nblocks * tiles_per_block + 7) & ~7;
-    hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, FORM>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
+    if (mx16)
+        hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, CFORM>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
+    else
+        hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, FORM>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
     return hipGetLastError();
 }
 

@@ -124,6 +124,7 @@ hipError_t run_group(const pond_search* s, const Group& g, void* spec, void* out
     a1.work = spec;
     a1.tw2 = g.tw2;
     a1.scale = std::ldexp(1.0f, -g.log2n2);
+    a1.f16_cols = 2 * g.hop == g.nfft;
     hipError_t e = launch_k1(s->precision, g.log2n2, a1, stream);
     if (e != hipSuccess) return e;
     K2Args f{};
@@ -363,6 +364,7 @@ pond_search* pond_search_create_ex(double f0_mhz, double bw_mhz, const double* d
             cal.tw2 = g.tw2;
             cal.work = g.spec;
             cal.max_batch = g.max_batch;
+            cal.f16_cols = 2 * g.hop == g.nfft;
             double gain = 1.0;
             chk(half_power_gain(
                 cal,

@@ -6,7 +6,8 @@ column tile in up to four consecutive blocks and loads only the second half
 of every block after the first, the first half being the previous block's
 second half, already in registers.  A launch in which a block straddles the
 end of the carried tail uses the one-block-per-workgroup pass.  The values
-and the arithmetic are the same, so:
+and the arithmetic are the same (the matrix-core form takes the packed-
+float16 column pass wherever blocks overlap by half, chained or not), so:
   * a stream at four blocks per launch (chained) equals the same stream at
     one block per launch (never chained) bit for bit, profiles and series;
   * the stream cut into calls whose ends fall inside blocks (launches that
@@ -25,7 +26,7 @@ pytestmark = pytest.mark.gpu
 
 # (nfft, DM, samples): discard N / 2 at 326.5 MHz, 16 MHz
 CASES = {"2^18": (1 << 18, 2.0, 3_000_000), "2^20": (1 << 20, 8.0, 12_000_000)}
-FORMS = ["fp32", "mixed_valu", "half", "bf16"]
+FORMS = ["fp32", "mixed_valu", "half", "mixed", "bf16"]
 NBINS, SUBINT = 256, 2_000_000
 
 
