@@ -291,7 +291,9 @@ int32_t pond_plan_expect(const pond_plan* p, int64_t nsamp, int64_t subint_nsamp
  *   0  int8 unpack + forward column FFTs
  *   1  twiddle + forward row FFT + chirp + inverse row FFT + twiddle
  *   2  inverse column FFTs + detection + decimation + fold partials
- *   3  fold partial reduction
+ *   3  fold partial reduction (the partials of up to four K3 launches are
+ *      queued and reduced by one launch; `blocks` counts the blocks whose
+ *      partials each reduction launch took)
  *   4  profile finalisation
  * With timing on, every launch of the plan is bracketed by two hipEvents
  * on the call's stream; pond_plan_kernel_times synchronises and returns the

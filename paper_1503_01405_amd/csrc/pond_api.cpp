@@ -1023,6 +1023,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
 
     int64_t b = p->blocks_done;
     ReduceQueue rq;
+    int64_t rq_blocks = 0;  // blocks whose fold partials are queued
     while (b < nb_total) {
         int64_t nb = nb_total - b < p->max_batch ? nb_total - b : p->max_batch;
         int64_t s_lo = 0, nsub = 1;
@@ -1121,7 +1122,8 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         // (after the queued reductions, which read them).
         const bool deferred = !global_mode && (int64_t)grid * entries <= kPartRegion;
         if (!global_mode && !deferred && rq.pending()) {
-            e = timed(3, 0, [&] { return rq.flush(stream); });
+            e = timed(3, rq_blocks, [&] { return rq.flush(stream); });
+            rq_blocks = 0;
             if (e != hipSuccess) return fail(e);
         }
         a3.part_sum = deferred ? rq.part_sum(p->part_sum) : p->part_sum;
@@ -1136,9 +1138,12 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
                                 (int32_t)grid, (int32_t)entries};
             if (deferred && !rq.push_flushes()) {
                 e = rq.push(job, stream);  // queued: nothing launched yet
+                rq_blocks += nb;
+            } else if (deferred) {
+                e = timed(3, rq_blocks + nb, [&] { return rq.push(job, stream); });
+                rq_blocks = 0;
             } else {
                 e = timed(3, nb, [&] {
-                    if (deferred) return rq.push(job, stream);
                     ReduceBatch one;
                     one.job[0] = job;
                     one.n = 1;
@@ -1150,7 +1155,7 @@ static int64_t run_call(pond_plan* p, const int8_t* iq, int64_t nsamp, int64_t s
         b += nb;
     }
     if (rq.pending()) {
-        e = timed(3, 0, [&] { return rq.flush(stream); });
+        e = timed(3, rq_blocks, [&] { return rq.flush(stream); });
         if (e != hipSuccess) return fail(e);
     }
 
