@@ -87,6 +87,9 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
         const uint32_t cc = opaque((uint32_t)((r0 + 16 * tt + c) & (n1 - 1)));
         const __half2* const ib =
             uniform_ptr(reinterpret_cast<const __half2*>(a.work) + ((int64_t)bb << (a.log2n1 + LOG2N2)));
+        // the block through a buffer descriptor: the lane's offset in a
+        // vector register, the row offset of value e in a scalar one
+        const BufRes rb = buf_res(ib, (uint32_t)sizeof(__half2) << (a.log2n1 + LOG2N2));
         if constexpr (MX) {
             // matrix-core layout: value e = 4b + t at position
             // 4 (j / 4) + b + (4 (j mod 4) + t) TPV
@@ -94,11 +97,11 @@ __global__ void __launch_bounds__(1 << LOG2N2) k3_colinv_detect_fold(K3Args a) {
                 (cc + ((uint32_t)(4 * (j >> 2) + 4 * (j & 3) * TPV) << a.log2n1)) * (uint32_t)sizeof(__half2);
 #pragma unroll
             for (int e = 0; e < 16; ++e)
-                dst[e] = ld_h2(at(ib + ((int64_t)((e >> 2) + (e & 3) * TPV) << a.log2n1), ioff));
+                dst[e] = buf_ld<h2>(rb, ioff, (int)(((e >> 2) + (e & 3) * TPV) * sizeof(__half2)) << a.log2n1);
         } else {
             const uint32_t ioff = (cc + ((uint32_t)j << a.log2n1)) * (uint32_t)sizeof(__half2);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) dst[e] = ld_h2(at(ib + ((int64_t)(TPV * e) << a.log2n1), ioff));
+            for (int e = 0; e < 16; ++e) dst[e] = buf_ld<h2>(rb, ioff, (int)(TPV * e * sizeof(__half2)) << a.log2n1);
         }
     };
     if constexpr (kPrefetch) {
