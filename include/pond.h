@@ -194,7 +194,7 @@ pond_plan* pond_plan_create(double f0_mhz, double bw_mhz, double dm,
  * 4, 6, 8, 12, 16, 24 and 32 blocks per launch (those
  * whose work area fits in min(4 GiB, a third of the free device memory),
  * plus the default) during creation and
- * keep the fastest per block, a larger launch winning only by more than 1%;
+ * keep the fastest per block, a larger launch winning only by more than 0.5%;
  * other values <= 0 pick the default (2^29 bytes of work area, 1 .. 16
  * blocks).  With the environment variable POND_AUTOTUNE_CACHE naming a
  * text file, a choice already measured for the same device, nfft, form,

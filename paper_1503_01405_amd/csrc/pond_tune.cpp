@@ -35,7 +35,7 @@ std::string device_tag(int dev) {
 
 std::string key_line(const TuneKey& k, const std::string& dev) {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "pond-tune-3 %s %s nfft=%lld form=%d kind=%d hist=%s", dev.c_str(), k.path,
+    std::snprintf(buf, sizeof buf, "pond-tune-4 %s %s nfft=%lld form=%d kind=%d hist=%s", dev.c_str(), k.path,
                   (long long)k.nfft, k.precision, k.kind, k.global_hist ? "global" : "lds");
     return buf;
 }
@@ -118,9 +118,9 @@ hipError_t autotune_batch(const TuneKey& key, const std::vector<int>& candidates
         if (e != hipSuccess) break;
         std::sort(t, t + 3);
         const double per = (double)t[1] / ((double)reps * nb);
-        // a larger launch must win by more than 1% (it costs memory; the
+        // a larger launch must win by more than 0.5% (it costs memory; the
         // samples' spread is below that)
-        if (best_b == 0 || per < best * 0.99) {
+        if (best_b == 0 || per < best * 0.995) {
             best = per;
             best_b = nb;
         }

@@ -29,7 +29,7 @@ struct TuneResult {
 // Times run(nb) (one launch sequence over nb blocks, on the null stream)
 // for every candidate, after one untimed run each, as the median of three
 // samples of back-to-back runs (about 10 ms or more each), and picks the
-// least time per block (a larger batch must win by more than 1%).  With POND_AUTOTUNE_CACHE set, a stored result for the same key
+// least time per block (a larger batch must win by more than 0.5%).  With POND_AUTOTUNE_CACHE set, a stored result for the same key
 // and device is used instead (if its batch is still a candidate), and a new
 // result is appended.  Synchronous.
 hipError_t autotune_batch(const TuneKey& key, const std::vector<int>& candidates, int default_batch,
