@@ -25,7 +25,8 @@ from test_gpu_parity import TOL, profile_tol
 pytestmark = pytest.mark.gpu
 
 # (nfft, DM, samples): discard N / 2 at 326.5 MHz, 16 MHz
-CASES = {"2^18": (1 << 18, 2.0, 3_000_000), "2^20": (1 << 20, 8.0, 12_000_000)}
+CASES = {"2^12": (1 << 12, 0.03, 200_000), "2^16": (1 << 16, 0.5, 1_500_000), "2^18": (1 << 18, 2.0, 3_000_000),
+         "2^20": (1 << 20, 8.0, 12_000_000)}
 FORMS = ["fp32", "mixed_valu", "half", "mixed", "bf16"]
 NBINS, SUBINT = 256, 2_000_000
 
