@@ -144,12 +144,15 @@ __global__ void __launch_bounds__(1 << LOG2N2) k1_unpack_colfft(K1Args a) {
 // each block after the first reads only its second half (the input is read
 // (chain + 1) / (2 chain) as often), and those loads are issued before the
 // previous block's transform, so that their latency is hidden behind it.
-// The values and the arithmetic are those of k1_unpack_colfft.
-template <int LOG2N2, class T, int FORM>
+// The values and the arithmetic are those of k1_unpack_colfft (AIP: the
+// real two-channel input, 4 bytes per element, float32 arithmetic forms).
+template <int LOG2N2, class T, int FORM, bool AIP = false>
 __global__ void __launch_bounds__(1 << LOG2N2)
     __attribute__((amdgpu_waves_per_eu(FORM == kFormF16 ? 8 : 4)))  // float16: two workgroups per CU
 k1_chain_colfft(K1Args a) {
     static_assert(FORM == kFormF16 || FORM == kFormF32, "VALU forms");
+    static_assert(!AIP || FORM == kFormF32, "the real input path has float32 arithmetic");
+    constexpr int BPE = AIP ? 4 : 2;  // input bytes per element
     constexpr int L = 1 << LOG2N2;
     constexpr int TPV = L / 16;
     constexpr bool H16 = FORM == kFormF16;
@@ -169,7 +172,7 @@ k1_chain_colfft(K1Args a) {
     const int j = threadIdx.x >> 4;
     const int col = 16 * t + c;
     const uint32_t o0 = opaque((uint32_t)col);
-    const uint32_t uoff = 2u * (o0 + ((uint32_t)j << a.log2n1));
+    const uint32_t uoff = (uint32_t)BPE * (o0 + ((uint32_t)j << a.log2n1));
 
     // raw int8 pairs of values e = E0 .. 15 of block b, which lies in the
     // carried tail or in the call's input entirely (launch_k1 uses this
@@ -177,11 +180,14 @@ k1_chain_colfft(K1Args a) {
     auto load_raw = [&](int b, auto e0, uint32_t (&r)[16]) {
         constexpr int E0 = decltype(e0)::value;
         const int64_t bstart = (a.block0 + b) * a.hop;
-        const int8_t* ub = uniform_ptr(bstart >= a.in_start ? a.in + 2 * (bstart - a.in_start)
-                                                            : a.tail + 2 * (bstart - a.tail_start));
+        const int8_t* ub = uniform_ptr(bstart >= a.in_start ? a.in + BPE * (bstart - a.in_start)
+                                                            : a.tail + BPE * (bstart - a.tail_start));
 #pragma unroll
-        for (int e = E0; e < 16; ++e)
-            r[e] = *reinterpret_cast<const uint16_t*>(at(ub + ((int64_t)(2 * TPV * e) << a.log2n1), uoff));
+        for (int e = E0; e < 16; ++e) {
+            const int8_t* p = at(ub + ((int64_t)(BPE * TPV * e) << a.log2n1), uoff);
+            if constexpr (AIP) r[e] = *reinterpret_cast<const uint32_t*>(p);
+            else r[e] = *reinterpret_cast<const uint16_t*>(p);
+        }
     };
     // int8 pair -> value (packed float16: exact, scaled by 1/16 as in
     // k1_unpack_colfft; float32: exact)
@@ -190,6 +196,10 @@ k1_chain_colfft(K1Args a) {
             const uint32_t w = ((s & 0xffu) | ((s & 0xff00u) << 8)) ^ 0x64806480u;
             return __builtin_elementwise_fma(__builtin_bit_cast(h2, w), h2{(_Float16)0.0625f, (_Float16)0.0625f},
                                              h2{(_Float16)-72.0f, (_Float16)-72.0f});
+        } else if constexpr (AIP) {
+            // samples 2m and 2m+1 of channels A and B, added in phase
+            return make_float2((float)((int)(int8_t)(s & 0xff) + (int)(int8_t)((s >> 8) & 0xff)),
+                               (float)((int)(int8_t)((s >> 16) & 0xff) + (int)(int8_t)(s >> 24)));
         } else {
             return make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)((s >> 8) & 0xff));
         }
@@ -291,8 +301,21 @@ static hipError_t k1_dispatch(int log2n2, const K1Args& a, hipStream_t s) {
 
 template <class T, int LOG2N2>
 static hipError_t k1_aip_one(const K1Args& a, hipStream_t s) {
-    const int ntiles = a.nblocks * ((1 << a.log2n1) >> 4);
-    const int grid = (ntiles + 7) & ~7;
+    const int tiles_per_block = (1 << a.log2n1) >> 4;
+    // half-overlapping blocks, none straddling the end of the carried tail:
+    // the chained pass (as in k1_one)
+    const int64_t n = (int64_t)1 << (a.log2n1 + LOG2N2);
+    const int64_t first = a.block0 * a.hop, last = (a.block0 + a.nblocks - 1) * a.hop;
+    const bool straddle = first < a.in_start && a.in_start < last + n;
+    if (a.nblocks >= 2 && (a.hop << 1) == n && !straddle) {
+        K1Args c = a;
+        const int nchains = (a.nblocks + kK1Chain - 1) / kK1Chain;
+        c.chain = (a.nblocks + nchains - 1) / nchains;
+        const int grid = ((a.nblocks + c.chain - 1) / c.chain * tiles_per_block + 7) & ~7;
+        hipLaunchKernelGGL((k1_chain_colfft<LOG2N2, T, kFormF32, true>), dim3(grid), dim3(1 << LOG2N2), 0, s, c);
+        return hipGetLastError();
+    }
+    const int grid = (a.nblocks * tiles_per_block + 7) & ~7;
     hipLaunchKernelGGL((k1_unpack_colfft<LOG2N2, T, kFormF32, true>), dim3(grid), dim3(1 << LOG2N2), 0, s, a);
     return hipGetLastError();
 }

@@ -73,3 +73,18 @@ def test_chained_oracle_parity(streams, precision):
     assert np.linalg.norm(ser - oser) / np.linalg.norm(oser) < TOL[precision][1]
     gain = power_gain(prof, oprof, r["cnts"])
     assert abs(gain - 1.0) < bias_tol(r["n_out"]), gain
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed_valu"])
+def test_chained_real_input_equals_unchained(precision):
+    """The real two-channel input (Sec. 3.7's AIP: 4 bytes per packed
+    element) through the chained pass: real blocks of 2^20 (packed 2^19) at
+    DM 3.1 overlap by half."""
+    from test_real_path import gpu_real_run, real_stream
+    print(f"case: K1 chain real input lsb 2^20 DM 3.1 {precision}", flush=True)
+    raw = real_stream(41, 3_000_002, 3.1, 3.3e-2, "lsb")
+    p4, s4 = gpu_real_run(raw, 3.1, 1 << 20, 256, 3.3e-2, "lsb", precision=precision, max_batch=4)
+    p1, s1 = gpu_real_run(raw, 3.1, 1 << 20, 256, 3.3e-2, "lsb", precision=precision, max_batch=1)
+    assert p4.shape == p1.shape and s4.shape == s1.shape
+    assert np.array_equal(bits(p4), bits(p1))
+    assert np.array_equal(bits(s4), bits(s1))
